@@ -1,0 +1,316 @@
+"""FP64 CPU oracle for the ADMM reconstruction of Cartesian dynamic parallel MRI.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module.  It shares no code with
+the HIP path (no kernels, headers, tables or helpers); both sides receive
+their inputs from the seeded generators in ``paper_1203_4587_amd.synthetic``.
+
+Everything here is plain numpy/scipy in complex128 and follows the paper
+(Bilen, Wang & Selesnick, "High Speed Compressed Sensing Reconstruction in
+Dynamic Parallel MRI Using Augmented Lagrangian and Parallel Processing"):
+
+* measurement model  y_{t,c} = M_t F (s_c . x_t): Sec. II-A, eqs. mri_mcoil2,
+  mri_csmcoill2, H_2, and the stacked H of eqs. H_1, S, F;
+* analysis objective lambda*||D_t x||_1 + ||y - Hx||^2 with the temporal
+  difference matrix D_t: Sec. II-A, eqs. L1an_pri and TV;
+* synthesis objective lambda*||w||_1 + ||y - H Psi' w||^2: eq. L1unconst;
+* complex soft threshold: Sec. III, the definition after eq. admm_bregman_3;
+* Algorithm 1 (ADMM_Synthesis) and Algorithm 2 (ADMM_Analysis): Sec. IV-A/B;
+* the per-(column, frame) structure of H'H and its eigendecomposition used
+  for (mu I + H'H)^{-1}: Sec. IV-C, eqs. HconjH, separate_x, eigen_mu;
+* the convergence ratio Delta(k): Sec. V, eq. r_ratio.
+
+Readings taken where the paper is silent or garbled (each is also pinned by a
+test): unitary transforms with DC at index 0 and forward sign exp(-2 pi i kn/N);
+the coil Gram in eq. HconjH taken as conj(s_j) s_k (the literal sum
+sum_c S_c' F~' F~ S_c is used here, not the printed Hadamard shortcut); the
+tight-frame inverse taken in its final two-term form (the first line of that
+derivation lacks a 1/mu on its second term); temporal TV non-periodic; the
+complex l1 norm is the sum of moduli; soft(a, tau) = 0 when |a| <= tau.
+
+Array layouts (C order): image (nt, nv, nh), coil (nc, nv, nh), mask (nt, nv),
+k-space (nt, nc, nv, nh); j = vertical (phase-encode) index, i = horizontal.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+# --------------------------------------------------------------------------
+# Measurement operator H (Sec. II-A)
+# --------------------------------------------------------------------------
+
+
+def forward(x: np.ndarray, coil: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """H x: y[t, c] = M_t F_h F_v (s_c . x_t), unitary 2D DFT (eqs. mri_mcoil2,
+    mri_csmcoill2).  Unsampled phase-encode rows of the result are zero."""
+    x = np.asarray(x, dtype=np.complex128)
+    y = np.fft.fft2(coil[None, :, :, :] * x[:, None, :, :], axes=(-2, -1), norm="ortho")
+    return y * mask[:, None, :, None]
+
+
+def adjoint(y: np.ndarray, coil: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """H' y: x_t = sum_c conj(s_c) . F_v' F_h' M_t y_{t,c} (conjugate transpose of
+    ``forward``; values of y on unsampled rows are ignored)."""
+    ym = np.asarray(y, dtype=np.complex128) * mask[:, None, :, None]
+    img = np.fft.ifft2(ym, axes=(-2, -1), norm="ortho")
+    return (np.conj(coil)[None] * img).sum(axis=1)
+
+
+def hybrid(y: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """F_h' applied to the sampled data: hybrid (ky, horizontal position) space.
+    Because F_h is unitary (Sec. IV-C uses F_h'F_h = I), the data term and H'y
+    of any column i only need column i of this array."""
+    ym = np.asarray(y, dtype=np.complex128) * mask[:, None, :, None]
+    return np.fft.ifft(ym, axis=-1, norm="ortho")
+
+
+def adjoint_columns(y: np.ndarray, coil: np.ndarray, mask: np.ndarray, cols) -> np.ndarray:
+    """Columns ``cols`` of H' y, shape (nt, nv, len(cols)); equal to
+    adjoint(y, coil, mask)[:, :, cols]."""
+    cols = np.asarray(cols)
+    yh = hybrid(y, mask)[..., cols]                              # (nt, nc, nv, k)
+    img = np.fft.ifft(yh * mask[:, None, :, None], axis=-2, norm="ortho")
+    return (np.conj(coil[:, :, cols])[None] * img).sum(axis=1)
+
+
+# --------------------------------------------------------------------------
+# Block structure of H'H and the exact x-update (Sec. IV-C)
+# --------------------------------------------------------------------------
+
+
+def dft_matrix(n: int) -> np.ndarray:
+    """Unitary DFT matrix, F[k, j] = exp(-2 pi i k j / n) / sqrt(n)."""
+    k = np.arange(n)
+    return np.exp(-2j * np.pi * np.outer(k, k) / n) / np.sqrt(n)
+
+
+def gram_block(coil_col: np.ndarray, mask_t: np.ndarray) -> np.ndarray:
+    """The (i, t) diagonal block of H'H:
+        sum_c S_{v,i,c}' F~_{v,t}' F~_{v,t} S_{v,i,c},   F~_{v,t} = M_{v,t} F_v,
+    written as the literal sum (eq. HconjH, first lines).  coil_col has shape
+    (nc, nv) = s_c restricted to column i; mask_t has shape (nv,)."""
+    nv = coil_col.shape[1]
+    Fv = dft_matrix(nv)
+    Ft = mask_t.astype(np.float64)[:, None] * Fv                 # M_t F_v
+    P = Ft.conj().T @ Ft
+    G = np.zeros((nv, nv), dtype=np.complex128)
+    for s in coil_col:
+        G += np.conj(s)[:, None] * P * s[None, :]                # S' P S
+    return G
+
+
+class BlockFactor:
+    """Eigendecompositions G_{i,t} = U diag(e) U' for a set of columns (eq.
+    separate_x), giving (mu I + H'H)^{-1} = U diag(1/(e + mu)) U' (eq. eigen_mu).
+
+    U has shape (nt, k, nv, nv), e has shape (nt, k, nv) for the k columns."""
+
+    def __init__(self, coil: np.ndarray, mask: np.ndarray, cols=None):
+        nc, nv, nh = coil.shape
+        nt = mask.shape[0]
+        self.cols = np.arange(nh) if cols is None else np.asarray(cols)
+        k = self.cols.size
+        self.U = np.empty((nt, k, nv, nv), dtype=np.complex128)
+        self.e = np.empty((nt, k, nv), dtype=np.float64)
+        for t in range(nt):
+            for ci, i in enumerate(self.cols):
+                G = gram_block(coil[:, :, i], mask[t])
+                e, U = np.linalg.eigh(G)
+                self.U[t, ci] = U
+                self.e[t, ci] = e
+
+    def solve(self, b: np.ndarray, mu: float) -> np.ndarray:
+        """x = (mu I + H'H)^{-1} b for b of shape (nt, nv, k)."""
+        bb = np.moveaxis(b, -1, 1)[..., None]                    # (nt, k, nv, 1)
+        Uh_b = np.conj(np.swapaxes(self.U, -1, -2)) @ bb
+        x = self.U @ (Uh_b / (self.e[..., None] + mu))
+        return np.moveaxis(x[..., 0], 1, -1)
+
+    def gram(self, t: int, ci: int) -> np.ndarray:
+        U, e = self.U[t, ci], self.e[t, ci]
+        return (U * e) @ U.conj().T
+
+
+# --------------------------------------------------------------------------
+# Shrinkage and temporal operators
+# --------------------------------------------------------------------------
+
+
+def soft(a: np.ndarray, tau: float) -> np.ndarray:
+    """Complex soft threshold (Sec. III): (|a| - tau) a / |a| if |a| > tau, else 0."""
+    a = np.asarray(a, dtype=np.complex128)
+    mag = np.abs(a)
+    out = np.zeros_like(a)
+    keep = mag > tau
+    out[keep] = (mag[keep] - tau) * a[keep] / mag[keep]
+    return out
+
+
+def tdiff(x: np.ndarray) -> np.ndarray:
+    """D_t x: frames x_t - x_{t-1}, t = 2..nt (eq. TV, non-periodic)."""
+    return x[1:] - x[:-1]
+
+
+def tdiff_adj(v: np.ndarray) -> np.ndarray:
+    """D_t' v for v with nt - 1 frames; result has nt frames."""
+    nt = v.shape[0] + 1
+    out = np.zeros((nt,) + v.shape[1:], dtype=np.result_type(v, np.complex128))
+    out[:-1] -= v
+    out[1:] += v
+    return out
+
+
+def tv_system_solve(r: np.ndarray, rho: float) -> np.ndarray:
+    """m = (rho I + D_t' D_t)^{-1} r along the frame axis (the m-update of
+    Algorithm 2 with R = D_t).  The matrix is tridiagonal, diagonal
+    [rho+1, rho+2, ..., rho+2, rho+1], off-diagonals -1; solved exactly."""
+    nt = r.shape[0]
+    flat = r.reshape(nt, -1)
+    if nt == 1:
+        return (flat / rho).reshape(r.shape)
+    ab = np.zeros((3, nt))
+    ab[0, 1:] = -1.0
+    ab[2, :-1] = -1.0
+    ab[1, :] = rho + 2.0
+    ab[1, 0] = ab[1, -1] = rho + 1.0
+    return scipy.linalg.solve_banded((1, 1), ab, flat).reshape(r.shape)
+
+
+def tdft(z: np.ndarray) -> np.ndarray:
+    """Psi: unitary DFT along the frame axis (the temporal DFT sparsifying
+    transform of Sec. V; orthonormal, Psi'Psi = Psi Psi' = I)."""
+    return np.fft.fft(z, axis=0, norm="ortho")
+
+
+def tdft_adj(w: np.ndarray) -> np.ndarray:
+    """Psi' (inverse unitary temporal DFT)."""
+    return np.fft.ifft(w, axis=0, norm="ortho")
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2: ADMM_Analysis with R = D_t (Sec. IV-B)
+# --------------------------------------------------------------------------
+
+
+def admm_analysis(Hy: np.ndarray, fac: BlockFactor, lam: float, mu: float, rho: float,
+                  iters: int, state: dict | None = None, callback=None) -> dict:
+    """Algorithm 2 with temporal TV.  mu is mu_2, rho = mu_2 / mu_1.
+
+    Hy: H'y restricted to the factor's columns, shape (nt, nv, k).
+    Returns the final state {x, m, d1, d2, iter}.  Initialisation follows the
+    algorithm: d1 = d2 = 0, x = H'y, m = x, unless ``state`` is given.
+    Each iteration, in the algorithm's order:
+        v  = soft(D m + d1, lambda / (2 mu_1))
+        m  = (mu_2/mu_1 I + D'D)^{-1} [D'(v - d1) + mu_2/mu_1 (x + d2)]
+        x  = (mu_2 I + H'H)^{-1} [H'y + mu_2 (m - d2)]
+        d1 = d1 - (v - D m)
+        d2 = d2 - (m - x)
+    """
+    mu2 = mu
+    mu1 = mu / rho
+    tau = lam / (2.0 * mu1)
+    if state is None:
+        x = Hy.copy()
+        m = x.copy()
+        d1 = np.zeros((Hy.shape[0] - 1,) + Hy.shape[1:], dtype=np.complex128)
+        d2 = np.zeros_like(Hy)
+        k0 = 0
+    else:
+        x, m, d1, d2 = (np.array(state[n], dtype=np.complex128) for n in ("x", "m", "d1", "d2"))
+        k0 = int(state.get("iter", 0))
+    for k in range(iters):
+        v = soft(tdiff(m) + d1, tau)
+        m = tv_system_solve(tdiff_adj(v - d1) + rho * (x + d2), rho)
+        x = fac.solve(Hy + mu2 * (m - d2), mu2)
+        d1 = d1 - (v - tdiff(m))
+        d2 = d2 - (m - x)
+        if callback is not None:
+            callback(k0 + k + 1, x)
+    return {"x": x, "m": m, "d1": d1, "d2": d2, "iter": k0 + iters}
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1: ADMM_Synthesis with a tight frame Psi (Sec. IV-A)
+# --------------------------------------------------------------------------
+
+
+def admm_synthesis(Hy: np.ndarray, fac: BlockFactor, lam: float, mu: float, iters: int,
+                   psi=tdft, psi_adj=tdft_adj, state: dict | None = None,
+                   callback=None) -> dict:
+    """Algorithm 1 for a tight frame Psi (Psi'Psi = I); default Psi = temporal DFT.
+
+    Initialisation: d = 0, w = Psi H'y.  Each iteration:
+        v = soft(w - d, lambda / (2 mu))
+        w = (1/mu)(I - Psi Psi')[Psi H'y + mu (v + d)]
+            + Psi (mu I + H'H)^{-1} [H'y + mu Psi'(v + d)]
+        d = d - (w - v)
+    Returns {x = Psi' w, w, v, d, iter}.
+    """
+    tau = lam / (2.0 * mu)
+    if state is None:
+        w = psi(Hy)
+        d = np.zeros_like(w)
+        v = np.zeros_like(w)
+        k0 = 0
+    else:
+        w, v, d = (np.array(state[n], dtype=np.complex128) for n in ("w", "v", "d"))
+        k0 = int(state.get("iter", 0))
+    PsiHy = psi(Hy)
+    for k in range(iters):
+        v = soft(w - d, tau)
+        q = PsiHy + mu * (v + d)
+        frame_part = (q - psi(psi_adj(q))) / mu
+        w = frame_part + psi(fac.solve(Hy + mu * psi_adj(v + d), mu))
+        d = d - (w - v)
+        if callback is not None:
+            callback(k0 + k + 1, psi_adj(w))
+    return {"x": psi_adj(w), "w": w, "v": v, "d": d, "iter": k0 + iters}
+
+
+# --------------------------------------------------------------------------
+# Objective and convergence ratio (Sec. II-A, Sec. V)
+# --------------------------------------------------------------------------
+
+
+def objective_tv(x, y, coil, mask, lam) -> float:
+    """J = lambda ||D_t x||_1 + ||y - H x||^2 (eq. L1an_pri with R = TV_t)."""
+    r = (y * mask[:, None, :, None]) - forward(x, coil, mask)
+    return float(lam * np.abs(tdiff(x)).sum() + (np.abs(r) ** 2).sum())
+
+
+def objective_dft(x, y, coil, mask, lam) -> float:
+    """J = lambda ||w||_1 + ||y - H Psi' w||^2 at w = Psi x (eq. L1unconst)."""
+    r = (y * mask[:, None, :, None]) - forward(x, coil, mask)
+    return float(lam * np.abs(tdft(x)).sum() + (np.abs(r) ** 2).sum())
+
+
+def delta(j_prev: float, j_cur: float) -> float:
+    """Delta(k) = (J(k-1) - J(k)) / J(k) (eq. r_ratio)."""
+    return (j_prev - j_cur) / j_cur
+
+
+# --------------------------------------------------------------------------
+# Convenience drivers on whole problems
+# --------------------------------------------------------------------------
+
+
+def solve(y, coil, mask, prior, lam, mu, rho, iters, cols=None, fac=None) -> dict:
+    """Run Algorithm 2 ("tv") or Algorithm 1 ("dft") on the given columns
+    (all by default).  Columns never interact under a temporal prior, so a
+    column subset gives exactly those columns of the full reconstruction."""
+    nh = coil.shape[2]
+    cols = np.arange(nh) if cols is None else np.asarray(cols)
+    if fac is None:
+        fac = BlockFactor(coil, mask, cols)
+    Hy = adjoint_columns(y, coil, mask, cols)
+    if prior == "tv":
+        return admm_analysis(Hy, fac, lam, mu, rho, iters)
+    if prior == "dft":
+        return admm_synthesis(Hy, fac, lam, mu, iters)
+    raise ValueError(prior)
+
+
+def measure(problem) -> np.ndarray:
+    """Synthetic measured data y = H x_true + noise for a generated problem."""
+    return forward(problem.x_true, problem.coil, problem.mask) + problem.noise
