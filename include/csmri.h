@@ -1,0 +1,176 @@
+/*
+ * csmri.h -- C ABI of the MI355X (gfx950) ADMM reconstruction library for
+ * Cartesian-sampled dynamic parallel MRI.
+ *
+ * Method: Bilen, Wang & Selesnick, "High Speed Compressed Sensing
+ * Reconstruction in Dynamic Parallel MRI Using Augmented Lagrangian and
+ * Parallel Processing".  The library computes
+ *   - the measurement operator H and its adjoint (Sec. II-A,
+ *     eqs. mri_mcoil2, mri_csmcoill2, H_2, H_1, S, F),
+ *   - Algorithm 2 (ADMM_Analysis, Sec. IV-B) with R = temporal TV (eq. TV),
+ *   - Algorithm 1 (ADMM_Synthesis, Sec. IV-A) with Psi = unitary temporal DFT,
+ *   - the exact x-update (mu I + H'H)^{-1} using the per-(column, frame)
+ *     block structure of H'H (Sec. IV-C, eqs. HconjH, separate_x, eigen_mu).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Complex values are interleaved single precision (cs_c64 = {re, im}),
+ *    bit-compatible with torch.complex64 / numpy.complex64.
+ *  * Every array pointer is a DEVICE pointer on the plan's GPU unless the
+ *    comment says otherwise.  Arrays are dense, C order, last index fastest:
+ *        image  x    [nt][nv][nh]
+ *        k-space y   [nt][nc][nv][nh]   (row ky of frame t is one readout line)
+ *        coil   s    [nc][nv][nh]
+ *        mask        [nt][nv]  uint8, nonzero = phase-encode line ky acquired
+ *    j / ky index the vertical (phase-encode, subsampled) axis and i / kx the
+ *    horizontal (readout) axis, as in eq. x_def.  Only ky is subsampled, and
+ *    the pattern may differ per frame (eq. mri_csmcoill2).
+ *  * Transforms are unitary with DC at index 0 (no fftshift); the forward
+ *    2D DFT uses exp(-2 pi i (ky j / nv + kx i / nh)).
+ *  * Sizes: nv and nh must be 2^a 3^b with 2 <= n <= 512; 1 <= nc <= 64;
+ *    2 <= nt <= 64 for the TV prior and 1 <= nt <= 64 for the DFT prior.
+ *  * Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *    asynchronous with respect to the host unless stated; results are ready
+ *    when the stream has drained.  A plan must not be used by two streams at
+ *    once (its workspaces are shared between calls).
+ *  * Errors: every call returns a cs_status.  No C++ exception crosses the
+ *    ABI.  On error the outputs are unspecified and the plan stays valid.
+ *    cs_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef CSMRI_H
+#define CSMRI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } cs_c64;
+typedef struct cs_plan cs_plan;   /* opaque: factor store, tables, workspaces */
+typedef void* cs_stream;          /* hipStream_t */
+
+typedef enum {
+  CS_OK = 0,
+  CS_EINVAL = 1,          /* null pointer, size out of range, mu <= 0, lambda < 0, iters < 0 */
+  CS_EUNSUPPORTED = 2,    /* size outside the supported set (see above) */
+  CS_ENOMEM = 3,          /* the allocator returned NULL */
+  CS_EDEVICE = 4,         /* a HIP runtime error; detail in cs_last_error() */
+  CS_EMU_MISMATCH = 5,    /* solve asked for another mu and CS_FLAG_NO_REFACTOR is set */
+} cs_status;
+
+typedef enum {
+  CS_PRIOR_TEMPORAL_TV = 0,   /* Algorithm 2 with R = D_t (eq. TV) */
+  CS_PRIOR_TEMPORAL_DFT = 1,  /* Algorithm 1 with Psi = unitary DFT along frames */
+} cs_prior;
+
+enum {
+  CS_FLAG_NO_REFACTOR = 1u << 0,  /* cs_admm_solve with a different mu fails instead of refactoring */
+  CS_FLAG_GRAPH = 1u << 1,        /* replay the iteration loop as a captured hipGraph */
+};
+
+/* Device-memory allocator used for everything the plan owns.  alloc returns
+ * NULL on failure (the call then returns CS_ENOMEM).  Passing NULL for the
+ * whole struct selects hipMalloc / hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} cs_allocator;
+
+typedef struct {
+  int32_t nv, nh, nt, nc;  /* rows (phase-encode), columns (readout), frames, coils */
+  int32_t prior;           /* cs_prior */
+  float mu_ratio;          /* rho = mu_2 / mu_1 of Algorithm 2 (Sec. V uses 0.5 or 0.25);
+                              must be > 0; ignored for the DFT prior */
+  uint32_t flags;          /* CS_FLAG_* */
+} cs_plan_desc;
+
+/* Solver state, caller-owned device arrays in the image layout.
+ *   TV : s0 = m [nt], s1 = d1 [nt-1], s2 = x [nt], s3 = d2 [nt]   (Algorithm 2)
+ *   DFT: s0 = w [nt], s1 = v  [nt],   s2 = d [nt], s3 unused       (Algorithm 1)
+ * (each [k] means k frames of nv*nh values).  iter = iterations already
+ * done: 0 means "start from the algorithm's initialisation", > 0 means "warm
+ * start from these arrays".  On return the arrays hold the state after the
+ * call and iter has been advanced by the number of iterations run. */
+typedef struct {
+  cs_c64* s0;
+  cs_c64* s1;
+  cs_c64* s2;
+  cs_c64* s3;
+  int32_t iter;
+} cs_state;
+
+/* Build a plan for one slice: copies the coil maps and mask, forms every
+ * per-(column i, frame t) block G = sum_c S' F~' F~ S of H'H (eq. HconjH, with
+ * the coil product taken as conj(s_j) s_k) and stores (mu I + G)^{-1} for the
+ * exact x-update (Sec. IV-C).  The factor is computed in FP64 and stored in
+ * complex64, packed Hermitian: nv(nv+1)/2 values per block, nh*nt blocks.
+ * Synchronises `stream` before returning; `coil` and `mask` may be freed
+ * afterwards.  Returns CS_EINVAL / CS_EUNSUPPORTED / CS_ENOMEM / CS_EDEVICE. */
+int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* mask,
+                   float mu, const cs_allocator* alloc, cs_stream stream, cs_plan** out);
+
+/* Release everything the plan owns (through its allocator).  NULL is a no-op. */
+int cs_plan_destroy(cs_plan* plan);
+
+/* Bytes of device memory the plan holds (factor + tables + workspaces). */
+int cs_plan_bytes(const cs_plan* plan, size_t* bytes);
+
+/* y = H x (eq. mri_csmcoill2): y[t,c] = M_t F (s_c . x_t).  Writes every
+ * element of y; rows ky that frame t does not sample are set to zero. */
+int cs_apply_A(cs_plan* plan, const cs_c64* x, cs_c64* y, cs_stream stream);
+
+/* x = H' y: x_t = sum_c conj(s_c) . F' M_t y_{t,c}.  Reads only the sampled
+ * rows of y (other rows are ignored and may hold anything). */
+int cs_apply_AH(cs_plan* plan, const cs_c64* y, cs_c64* x, cs_stream stream);
+
+/* x = (mu I + H'H)^{-1} b with the plan's mu (eq. eigen_mu), b and x images. */
+int cs_apply_block_inverse(cs_plan* plan, const cs_c64* b, cs_c64* x, cs_stream stream);
+
+/* Run `iters` ADMM iterations on data y (Algorithm 2 for the TV prior,
+ * Algorithm 1 for the DFT prior) and write the image series to x_out.
+ *   lambda >= 0 weights the l1 term; mu > 0 is mu (Algorithm 1) or mu_2
+ *   (Algorithm 2, with mu_1 = mu / mu_ratio).  If mu differs from the plan's
+ *   mu the factor is rebuilt first (FP64, not cheap) unless the plan has
+ *   CS_FLAG_NO_REFACTOR, which makes the call return CS_EMU_MISMATCH.
+ *   state may be NULL (fresh start, nothing returned) -- see cs_state.
+ *   J_trace, if not NULL, is a device float[iters] that receives the
+ *   objective J(k) after each iteration (lambda ||D_t x||_1 + ||y - Hx||^2, or
+ *   lambda ||Psi x||_1 + ||y - Hx||^2), used for Delta(k) of eq. r_ratio.
+ * iters == 0 writes H'y (the algorithms' initial x) to x_out. */
+int cs_admm_solve(cs_plan* plan, const cs_c64* y, float lambda, float mu, int32_t iters,
+                  cs_c64* x_out, cs_state* state, float* J_trace, cs_stream stream);
+
+/* Per-kernel device timing, a profiling aid for callers that report kernel
+ * throughput.  cs_kernel_timing(plan, 1) starts bracketing every launch of
+ * the per-iteration kernels made by cs_admm_solve with a pair of hipEvents on
+ * the solve's stream (0 stops; either call clears the accumulated times).
+ * cs_kernel_times waits for those events and fills up to `max` records, one
+ * per kernel kind, with the number of launches and their summed device time;
+ * *count receives the number of kinds seen.  Kinds: "tv_step", "dft_step",
+ * "x_update", "objective".  Event records add a few microseconds of host
+ * work per launch and nothing to the kernels themselves. */
+typedef struct {
+  char name[24];
+  int32_t launches;
+  double ms;
+} cs_kernel_time;
+
+int cs_kernel_timing(cs_plan* plan, int enable);
+int cs_kernel_times(cs_plan* plan, cs_kernel_time* out, int max, int* count);
+
+/* Static description of a status code. */
+const char* cs_status_string(int status);
+
+/* Thread-local text of the last error raised on this thread ("" if none). */
+const char* cs_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int cs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSMRI_H */

@@ -1,0 +1,233 @@
+"""Python binding of libcsmri: argument marshalling only.
+
+Every array is a torch CUDA tensor (complex64 / uint8, C-contiguous) whose
+device pointer is handed to the C ABI together with torch's current stream;
+the plan's own device memory comes from torch's caching allocator through
+the ABI's allocator callback.  No reconstruction arithmetic happens here.
+
+Layouts (see include/csmri.h): image (nt, nv, nh), k-space (nt, nc, nv, nh),
+coil maps (nc, nv, nh), mask (nt, nv) uint8.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import CsAllocator, CsPlanDesc, CsState, check
+
+PRIORS = {"tv": _lib.CS_PRIOR_TEMPORAL_TV, "dft": _lib.CS_PRIOR_TEMPORAL_DFT}
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t: torch.Tensor, name: str, dtype: torch.dtype, shape) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a CUDA/HIP device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class _TorchAllocator:
+    """cs_allocator backed by torch's caching allocator on one device."""
+
+    def __init__(self, device: int):
+        self.device = device
+        self.live = {}
+
+        def alloc(nbytes, ctx):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device)
+            except RuntimeError:
+                return None
+            self.live[ptr] = nbytes
+            return ptr
+
+        def free(ptr, ctx):
+            if ptr in self.live:
+                del self.live[ptr]
+                torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc = _lib.ALLOC_FN(alloc)
+        self._free = _lib.FREE_FN(free)
+        self.struct = CsAllocator(self._alloc, self._free, None)
+
+
+@dataclass
+class State:
+    """Solver state in image layout (see cs_state in include/csmri.h).
+
+    TV : s0 = m, s1 = d1 (nt-1 frames), s2 = x, s3 = d2
+    DFT: s0 = w, s1 = v, s2 = d, s3 unused
+    """
+    s0: torch.Tensor
+    s1: torch.Tensor
+    s2: torch.Tensor
+    s3: torch.Tensor | None
+    iter: int = 0
+
+    @classmethod
+    def empty(cls, prior: str, nt: int, nv: int, nh: int, device) -> "State":
+        def img(frames):
+            return torch.zeros((frames, nv, nh), dtype=torch.complex64, device=device)
+        if prior == "tv":
+            return cls(img(nt), img(nt - 1), img(nt), img(nt), 0)
+        return cls(img(nt), img(nt), img(nt), None, 0)
+
+
+class Plan:
+    """A reconstruction plan for one dynamic slice (cs_plan_create)."""
+
+    def __init__(self, coil: torch.Tensor, mask: torch.Tensor, mu: float, prior: str = "tv",
+                 mu_ratio: float = 0.5, flags: int = 0, use_torch_allocator: bool = True, stream=None):
+        lib = _lib.load()
+        if prior not in PRIORS:
+            raise ValueError(f"prior must be one of {sorted(PRIORS)}")
+        if coil.dim() != 3 or mask.dim() != 2:
+            raise ValueError("coil must be (nc, nv, nh) and mask (nt, nv)")
+        nc, nv, nh = coil.shape
+        nt = mask.shape[0]
+        _need(coil, "coil", torch.complex64, (nc, nv, nh))
+        _need(mask, "mask", torch.uint8, (nt, nv))
+        self.nv, self.nh, self.nt, self.nc = int(nv), int(nh), int(nt), int(nc)
+        self.prior = prior
+        self.device = coil.device
+        self.desc = CsPlanDesc(self.nv, self.nh, self.nt, self.nc, PRIORS[prior], float(mu_ratio), int(flags))
+        self._alloc = _TorchAllocator(coil.device.index or 0) if use_torch_allocator else None
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.cs_plan_create(ctypes.byref(self.desc), _ptr(coil), _ptr(mask), float(mu),
+                                    ctypes.byref(self._alloc.struct) if self._alloc else None,
+                                    _stream(stream), ctypes.byref(handle))
+        check(st, "cs_plan_create")
+        self._h = handle
+        self.mu = float(mu)
+
+    # -- lifetime
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.load().cs_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h or not self._h.value:
+            raise RuntimeError("plan is closed")
+        return self._h
+
+    @property
+    def nbytes(self) -> int:
+        n = ctypes.c_size_t()
+        check(_lib.load().cs_plan_bytes(self.handle, ctypes.byref(n)), "cs_plan_bytes")
+        return n.value
+
+    # -- shapes
+    @property
+    def image_shape(self):
+        return (self.nt, self.nv, self.nh)
+
+    @property
+    def kspace_shape(self):
+        return (self.nt, self.nc, self.nv, self.nh)
+
+    # -- operators
+    def apply_A(self, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        _need(x, "x", torch.complex64, self.image_shape)
+        y = out if out is not None else torch.empty(self.kspace_shape, dtype=torch.complex64, device=x.device)
+        _need(y, "out", torch.complex64, self.kspace_shape)
+        check(_lib.load().cs_apply_A(self.handle, _ptr(x), _ptr(y), _stream(stream)), "cs_apply_A")
+        return y
+
+    def apply_AH(self, y: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        _need(y, "y", torch.complex64, self.kspace_shape)
+        x = out if out is not None else torch.empty(self.image_shape, dtype=torch.complex64, device=y.device)
+        _need(x, "out", torch.complex64, self.image_shape)
+        check(_lib.load().cs_apply_AH(self.handle, _ptr(y), _ptr(x), _stream(stream)), "cs_apply_AH")
+        return x
+
+    def block_inverse(self, b: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        _need(b, "b", torch.complex64, self.image_shape)
+        x = out if out is not None else torch.empty(self.image_shape, dtype=torch.complex64, device=b.device)
+        _need(x, "out", torch.complex64, self.image_shape)
+        check(_lib.load().cs_apply_block_inverse(self.handle, _ptr(b), _ptr(x), _stream(stream)),
+              "cs_apply_block_inverse")
+        return x
+
+    def kernel_timing(self, enable: bool = True) -> None:
+        """Start (or stop) HIP-event timing of every per-iteration kernel launch."""
+        check(_lib.load().cs_kernel_timing(self.handle, int(enable)), "cs_kernel_timing")
+
+    def kernel_times(self) -> dict:
+        """{kind: (launches, total_ms)} accumulated since timing was enabled."""
+        recs = (_lib.CsKernelTime * 8)()
+        n = ctypes.c_int()
+        check(_lib.load().cs_kernel_times(self.handle, recs, 8, ctypes.byref(n)), "cs_kernel_times")
+        return {recs[i].name.decode(): (int(recs[i].launches), float(recs[i].ms)) for i in range(min(n.value, 8))}
+
+    def new_state(self) -> State:
+        return State.empty(self.prior, self.nt, self.nv, self.nh, self.device)
+
+    def solve(self, y: torch.Tensor, lam: float, iters: int, mu: float | None = None,
+              state: State | None = None, trace: bool = False, out: torch.Tensor | None = None,
+              stream=None):
+        """cs_admm_solve.  Returns x, or (x, J) with J the per-iteration objective
+        (a float32 tensor of length iters) when trace=True."""
+        _need(y, "y", torch.complex64, self.kspace_shape)
+        x = out if out is not None else torch.empty(self.image_shape, dtype=torch.complex64, device=y.device)
+        _need(x, "out", torch.complex64, self.image_shape)
+        cstate = None
+        if state is not None:
+            fr = {"tv": (self.nt, self.nt - 1, self.nt, self.nt), "dft": (self.nt, self.nt, self.nt, None)}[self.prior]
+            for name, frames in zip(("s0", "s1", "s2", "s3"), fr):
+                if frames is not None:
+                    _need(getattr(state, name), f"state.{name}", torch.complex64, (frames, self.nv, self.nh))
+            cstate = CsState(state.s0.data_ptr(), state.s1.data_ptr(), state.s2.data_ptr(),
+                             state.s3.data_ptr() if state.s3 is not None else None, int(state.iter))
+        J = torch.empty(max(iters, 1), dtype=torch.float32, device=y.device) if trace else None
+        st = _lib.load().cs_admm_solve(self.handle, _ptr(y), float(lam), float(self.mu if mu is None else mu),
+                                       int(iters), _ptr(x), ctypes.byref(cstate) if cstate else None,
+                                       _ptr(J) if J is not None else None, _stream(stream))
+        check(st, "cs_admm_solve")
+        if mu is not None:
+            self.mu = float(mu)
+        if cstate is not None:
+            state.iter = int(cstate.iter)
+        return (x, J[:iters]) if trace else x
+
+
+def to_device(a, device="cuda", dtype=None) -> torch.Tensor:
+    """numpy -> contiguous torch tensor on the GPU (complex128 -> complex64)."""
+    import numpy as np
+    arr = np.asarray(a)
+    if dtype is None:
+        dtype = torch.uint8 if arr.dtype == np.uint8 else torch.complex64
+    if dtype == torch.complex64:
+        arr = arr.astype(np.complex64)
+    return torch.from_numpy(np.ascontiguousarray(arr)).to(device=device, dtype=dtype)

@@ -1,0 +1,455 @@
+// C ABI entry points of libcsmri (declared in include/csmri.h).
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+namespace csmri {
+
+static thread_local std::string g_last_error;
+
+int set_error(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return set_error(CS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* DeviceAlloc::get(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (custom) return a.alloc(bytes, a.ctx);
+  void* ptr = nullptr;
+  if (hipMalloc(&ptr, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return ptr;
+}
+
+void DeviceAlloc::put(void* ptr) {
+  if (!ptr) return;
+  if (custom) {
+    if (a.free) a.free(ptr, a.ctx);
+  } else {
+    (void)hipFree(ptr);
+  }
+}
+
+int objective_partial_count();
+
+static bool smooth_23(int n) {
+  if (n < 2) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+template <typename T>
+static int plan_alloc(cs_plan* p, T** out, size_t count, const char* what) {
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  void* ptr = p->alloc.get(bytes);
+  if (!ptr) return set_error(CS_ENOMEM, std::string("allocator returned NULL for ") + what);
+  p->owned.push_back(ptr);
+  p->bytes += bytes;
+  *out = static_cast<T*>(ptr);
+  return CS_OK;
+}
+
+static void plan_release(cs_plan* p) {
+  if (!p) return;
+  if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  for (void* ptr : p->owned) p->alloc.put(ptr);
+  p->owned.clear();
+  delete p;
+}
+
+static int validate_desc(const cs_plan_desc* d) {
+  if (d->nv < 2 || d->nh < 2 || d->nt < 1 || d->nc < 1)
+    return set_error(CS_EINVAL, "nv, nh must be >= 2 and nt, nc >= 1");
+  if (d->prior != CS_PRIOR_TEMPORAL_TV && d->prior != CS_PRIOR_TEMPORAL_DFT)
+    return set_error(CS_EINVAL, "unknown prior");
+  if (d->prior == CS_PRIOR_TEMPORAL_TV && d->nt < 2)
+    return set_error(CS_EINVAL, "the temporal TV prior needs nt >= 2");
+  if (d->prior == CS_PRIOR_TEMPORAL_TV && !(d->mu_ratio > 0.f && std::isfinite(d->mu_ratio)))
+    return set_error(CS_EINVAL, "mu_ratio (mu2/mu1) must be finite and > 0");
+  if (!smooth_23(d->nv) || !smooth_23(d->nh) || d->nv > 512 || d->nh > 512)
+    return set_error(CS_EUNSUPPORTED, "nv and nh must be of the form 2^a 3^b and at most 512");
+  if (d->nt > 64) return set_error(CS_EUNSUPPORTED, "nt must be at most 64");
+  if (d->nc > 64) return set_error(CS_EUNSUPPORTED, "nc must be at most 64");
+  return CS_OK;
+}
+
+static inline hipStream_t S(cs_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- timing
+enum KernelKind { kKindTV = 0, kKindDFT = 1, kKindX = 2, kKindJ = 3, kKinds = 4 };
+static const char* kKindNames[kKinds] = {"tv_step", "dft_step", "x_update", "objective"};
+
+static hipEvent_t pool_event(cs_plan* p) {
+  if (p->pool_next == p->event_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p->event_pool.push_back(e);
+  }
+  return p->event_pool[p->pool_next++];
+}
+
+// runs launch() bracketed by events when timing is on
+template <typename F>
+static int timed_launch(cs_plan* p, int kind, hipStream_t s, F launch) {
+  if (!p->timing) return launch();
+  hipEvent_t a = pool_event(p), b = pool_event(p);
+  if (!a || !b) return set_error(CS_EDEVICE, "hipEventCreate failed");
+  CS_HIP(hipEventRecord(a, s));
+  int st = launch();
+  if (st != CS_OK) return st;
+  CS_HIP(hipEventRecord(b, s));
+  p->timed.push_back({kind, a, b});
+  return CS_OK;
+}
+
+static int run_iterations(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
+                          const float2* wgiven, hipStream_t s) {
+  const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
+  int st = CS_OK;
+  for (int k = 0; k < iters && st == CS_OK; ++k) {
+    if (tv) {
+      st = timed_launch(p, kKindTV, s, [&] { return launch_tv_step(p, lambda, mu, s); });
+      if (st == CS_OK)
+        st = timed_launch(p, kKindX, s,
+                          [&] { return launch_block_solve(p, kSolveTV, p->hy, p->s0, p->s3, p->s2, mu, s); });
+    } else {
+      st = timed_launch(p, kKindDFT, s, [&] {
+        return launch_dft_step(p, lambda, mu, k == 0 ? 1 : 0, k == 0 ? wgiven : nullptr, s);
+      });
+      if (st == CS_OK)
+        st = timed_launch(p, kKindX, s,
+                          [&] { return launch_block_solve(p, kSolveDFT, p->hy, p->s3, nullptr, p->s2, mu, s); });
+    }
+    if (st == CS_OK && J_trace)
+      st = timed_launch(p, kKindJ, s, [&] { return launch_objective(p, p->s2, lambda, J_trace + k, s); });
+  }
+  return st;
+}
+
+
+}  // namespace csmri
+
+using namespace csmri;
+
+extern "C" {
+
+int cs_version(void) { return 10000; }
+
+const char* cs_status_string(int status) {
+  switch (status) {
+    case CS_OK: return "CS_OK";
+    case CS_EINVAL: return "CS_EINVAL: invalid argument";
+    case CS_EUNSUPPORTED: return "CS_EUNSUPPORTED: unsupported size";
+    case CS_ENOMEM: return "CS_ENOMEM: device allocation failed";
+    case CS_EDEVICE: return "CS_EDEVICE: HIP runtime error";
+    case CS_EMU_MISMATCH: return "CS_EMU_MISMATCH: mu differs from the plan's and refactoring is disabled";
+    default: return "unknown cs_status";
+  }
+}
+
+const char* cs_last_error(void) { return g_last_error.c_str(); }
+
+int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* mask, float mu,
+                   const cs_allocator* alloc, cs_stream stream, cs_plan** out) {
+  if (!out) return set_error(CS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!desc || !coil || !mask) return set_error(CS_EINVAL, "desc, coil and mask must not be NULL");
+  if (!(mu > 0.f && std::isfinite(mu))) return set_error(CS_EINVAL, "mu must be finite and > 0");
+  if (alloc && !alloc->alloc) return set_error(CS_EINVAL, "allocator without an alloc callback");
+  int st = validate_desc(desc);
+  if (st != CS_OK) return st;
+  cs_plan* p = new (std::nothrow) cs_plan();
+  if (!p) return set_error(CS_ENOMEM, "host allocation of the plan failed");
+  p->desc = *desc;
+  p->alloc.custom = alloc != nullptr;
+  if (alloc) p->alloc.a = *alloc;
+  const int nv = desc->nv, nh = desc->nh, nt = desc->nt, nc = desc->nc;
+  const size_t npix = (size_t)nv * nh;
+  const size_t nimg = npix * nt;
+  hipStream_t s = S(stream);
+  auto fail = [&](int status) {
+    plan_release(p);
+    return status;
+  };
+  // the factor is by far the largest buffer; take it before any device work
+  p->flayout = make_factor_layout(nv, (size_t)nt * nh);
+  if ((st = plan_alloc(p, &p->factor, factor_elems(p->flayout), "the factor store")) != CS_OK) return fail(st);
+  if (!make_fft_desc(nv, &p->fft_v) || !make_fft_desc(nh, &p->fft_h))
+    return fail(set_error(CS_EUNSUPPORTED, "no FFT plan for this size"));
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) return fail(hip_fail(e, "hipGetDevice"));
+
+  // sampling pattern: rows per frame (host), uploaded as tables
+  std::vector<uint8_t> hmask((size_t)nt * nv);
+  e = hipMemcpyAsync(hmask.data(), mask, hmask.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(hip_fail(e, "copy of the mask to the host"));
+  p->h_mcnt.assign(nt, 0);
+  for (int t = 0; t < nt; ++t)
+    for (int j = 0; j < nv; ++j) p->h_mcnt[t] += hmask[(size_t)t * nv + j] != 0;
+  p->m_max = *std::max_element(p->h_mcnt.begin(), p->h_mcnt.end());
+  const int mrow = std::max(p->m_max, 1);
+  std::vector<int32_t> hrows((size_t)nt * mrow, -1);
+  for (int t = 0; t < nt; ++t) {
+    int r = 0;
+    for (int j = 0; j < nv; ++j)
+      if (hmask[(size_t)t * nv + j]) hrows[(size_t)t * mrow + r++] = j;
+  }
+  // FP64 first column of F_v' M_t F_v: p_t[l] = (1/nv) sum_{ky in Omega_t} exp(+2 pi i ky l / nv)
+  std::vector<double2> hp((size_t)nt * nv);
+  for (int t = 0; t < nt; ++t)
+    for (int l = 0; l < nv; ++l) {
+      double re = 0, im = 0;
+      for (int r = 0; r < p->h_mcnt[t]; ++r) {
+        const long long ky = hrows[(size_t)t * mrow + r];
+        const double ang = 2.0 * M_PI * (double)((ky * l) % nv) / nv;
+        re += std::cos(ang);
+        im += std::sin(ang);
+      }
+      hp[(size_t)t * nv + l] = make_double2(re / nv, im / nv);
+    }
+  auto twiddles = [](int n) {
+    std::vector<float2> w(n);
+    for (int q = 0; q < n; ++q) {
+      const double ang = -2.0 * M_PI * q / n;
+      w[q] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    return w;
+  };
+  std::vector<float2> htwv = twiddles(nv), htwh = twiddles(nh);
+  // unitary temporal DFT: Psi[f][t] = exp(-2 pi i f t / nt) / sqrt(nt)
+  std::vector<float2> hpsi((size_t)nt * nt);
+  for (int f = 0; f < nt; ++f)
+    for (int t = 0; t < nt; ++t) {
+      const double ang = -2.0 * M_PI * (double)((f * t) % nt) / nt;
+      hpsi[(size_t)f * nt + t] =
+          make_float2((float)(std::cos(ang) / std::sqrt((double)nt)), (float)(std::sin(ang) / std::sqrt((double)nt)));
+    }
+  // Thomas pivots of rho I + D'D: den_0 = b_0, den_t = b_t - 1/den_{t-1}
+  std::vector<float> hinv(nt, 0.f);
+  if (desc->prior == CS_PRIOR_TEMPORAL_TV) {
+    const double rho = desc->mu_ratio;
+    double den = 0;
+    for (int t = 0; t < nt; ++t) {
+      const double b = rho + ((t == 0 || t == nt - 1) ? 1.0 : 2.0);
+      den = t == 0 ? b : b - 1.0 / den;
+      hinv[t] = (float)(1.0 / den);
+    }
+  }
+
+  const size_t ksz = (size_t)nt * nc * mrow * nh;
+  if ((st = plan_alloc(p, &p->rows, hrows.size(), "rows")) ||
+      (st = plan_alloc(p, &p->mcnt, (size_t)nt, "mcnt")) ||
+      (st = plan_alloc(p, &p->mask, hmask.size(), "mask")) ||
+      (st = plan_alloc(p, &p->pcol, hp.size(), "pcol")) ||
+      (st = plan_alloc(p, &p->tw_v, (size_t)nv, "tw_v")) ||
+      (st = plan_alloc(p, &p->tw_h, (size_t)nh, "tw_h")) ||
+      (st = plan_alloc(p, &p->psi_t, hpsi.size(), "psi")) ||
+      (st = plan_alloc(p, &p->tv_invden, (size_t)nt, "tv_invden")) ||
+      (st = plan_alloc(p, &p->coil_cm, npix * nc, "coil")) ||
+      (st = plan_alloc(p, &p->ktmp, ksz, "ktmp")) ||
+      (st = plan_alloc(p, &p->ftmp, ksz, "ftmp")) ||
+      (st = plan_alloc(p, &p->hy, nimg, "hy")) ||
+      (st = plan_alloc(p, &p->s0, nimg, "state")) ||
+      (st = plan_alloc(p, &p->s1, nimg, "state")) ||
+      (st = plan_alloc(p, &p->s2, nimg, "state")) ||
+      (st = plan_alloc(p, &p->s3, nimg, "state")) ||
+      (st = plan_alloc(p, &p->img_tmp, nimg, "image workspace")) ||
+      (st = plan_alloc(p, &p->jpart, (size_t)objective_partial_count(), "objective partials")))
+    return fail(st);
+  p->jpart_len = objective_partial_count();
+
+#define UP(dst, src, bytes)                                                                     \
+  do {                                                                                          \
+    hipError_t _e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);                  \
+    if (_e != hipSuccess) return fail(hip_fail(_e, "upload of plan tables"));                   \
+  } while (0)
+  UP(p->rows, hrows.data(), hrows.size() * sizeof(int32_t));
+  UP(p->mcnt, p->h_mcnt.data(), (size_t)nt * sizeof(int32_t));
+  UP(p->mask, hmask.data(), hmask.size());
+  UP(p->pcol, hp.data(), hp.size() * sizeof(double2));
+  UP(p->tw_v, htwv.data(), htwv.size() * sizeof(float2));
+  UP(p->tw_h, htwh.data(), htwh.size() * sizeof(float2));
+  UP(p->psi_t, hpsi.data(), hpsi.size() * sizeof(float2));
+  UP(p->tv_invden, hinv.data(), hinv.size() * sizeof(float));
+#undef UP
+  // coil maps [c][j][i] -> column-major [c][i][j]
+  if ((st = launch_transpose(reinterpret_cast<const float2*>(coil), p->coil_cm, nc, nv, nh, s)) != CS_OK)
+    return fail(st);
+  if ((st = build_factor(p, mu, s)) != CS_OK) return fail(st);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(hip_fail(e, "hipStreamSynchronize(plan)"));
+  *out = p;
+  return CS_OK;
+}
+
+int cs_plan_destroy(cs_plan* plan) {
+  if (!plan) return CS_OK;
+  (void)hipSetDevice(plan->device);
+  (void)hipDeviceSynchronize();
+  for (hipEvent_t e : plan->event_pool) (void)hipEventDestroy(e);
+  plan_release(plan);
+  return CS_OK;
+}
+
+int cs_kernel_timing(cs_plan* plan, int enable) {
+  if (!plan) return set_error(CS_EINVAL, "plan is NULL");
+  plan->timing = enable != 0;
+  plan->timed.clear();
+  plan->pool_next = 0;
+  return CS_OK;
+}
+
+int cs_kernel_times(cs_plan* plan, cs_kernel_time* out, int max, int* count) {
+  if (!plan || !count || (max > 0 && !out)) return set_error(CS_EINVAL, "plan, out and count must not be NULL");
+  CS_HIP(hipSetDevice(plan->device));
+  double ms[kKinds] = {0, 0, 0, 0};
+  int n[kKinds] = {0, 0, 0, 0};
+  for (const auto& t : plan->timed) {
+    CS_HIP(hipEventSynchronize(t.stop));
+    float e = 0.f;
+    CS_HIP(hipEventElapsedTime(&e, t.start, t.stop));
+    ms[t.kind] += e;
+    n[t.kind] += 1;
+  }
+  int c = 0;
+  for (int k = 0; k < kKinds; ++k) {
+    if (!n[k]) continue;
+    if (c < max) {
+      std::memset(out[c].name, 0, sizeof(out[c].name));
+      std::strncpy(out[c].name, kKindNames[k], sizeof(out[c].name) - 1);
+      out[c].launches = n[k];
+      out[c].ms = ms[k];
+    }
+    ++c;
+  }
+  *count = c;
+  plan->timed.clear();
+  plan->pool_next = 0;
+  return CS_OK;
+}
+
+int cs_plan_bytes(const cs_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return set_error(CS_EINVAL, "plan and bytes must not be NULL");
+  *bytes = plan->bytes;
+  return CS_OK;
+}
+
+int cs_apply_A(cs_plan* p, const cs_c64* x, cs_c64* y, cs_stream stream) {
+  if (!p || !x || !y) return set_error(CS_EINVAL, "plan, x and y must not be NULL");
+  CS_HIP(hipSetDevice(p->device));
+  return launch_forward(p, reinterpret_cast<const float2*>(x), false, reinterpret_cast<float2*>(y), S(stream));
+}
+
+int cs_apply_AH(cs_plan* p, const cs_c64* y, cs_c64* x, cs_stream stream) {
+  if (!p || !x || !y) return set_error(CS_EINVAL, "plan, x and y must not be NULL");
+  CS_HIP(hipSetDevice(p->device));
+  int st = launch_adjoint_rows(p, reinterpret_cast<const float2*>(y), S(stream));
+  if (st != CS_OK) return st;
+  return launch_adjoint_image(p, reinterpret_cast<float2*>(x), false, S(stream));
+}
+
+int cs_apply_block_inverse(cs_plan* p, const cs_c64* b, cs_c64* x, cs_stream stream) {
+  if (!p || !b || !x) return set_error(CS_EINVAL, "plan, b and x must not be NULL");
+  CS_HIP(hipSetDevice(p->device));
+  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
+  hipStream_t s = S(stream);
+  int st = launch_transpose(reinterpret_cast<const float2*>(b), p->img_tmp, nt, nv, nh, s);
+  if (st == CS_OK) st = launch_block_solve(p, kSolvePlain, p->img_tmp, nullptr, nullptr, p->img_tmp, p->mu, s);
+  if (st == CS_OK) st = launch_transpose(p->img_tmp, reinterpret_cast<float2*>(x), nt, nh, nv, s);
+  return st;
+}
+
+int cs_admm_solve(cs_plan* p, const cs_c64* y, float lambda, float mu, int32_t iters, cs_c64* x_out,
+                  cs_state* state, float* J_trace, cs_stream stream) {
+  if (!p || !y || !x_out) return set_error(CS_EINVAL, "plan, y and x_out must not be NULL");
+  if (!(lambda >= 0.f && std::isfinite(lambda))) return set_error(CS_EINVAL, "lambda must be finite and >= 0");
+  if (!(mu > 0.f && std::isfinite(mu))) return set_error(CS_EINVAL, "mu must be finite and > 0");
+  if (iters < 0) return set_error(CS_EINVAL, "iters must be >= 0");
+  const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
+  const bool warm = state && state->iter > 0;
+  if (state && (!state->s0 || !state->s1 || !state->s2 || (tv && !state->s3)))
+    return set_error(CS_EINVAL, "state arrays must not be NULL");
+  if (state && state->iter < 0) return set_error(CS_EINVAL, "state->iter must be >= 0");
+  CS_HIP(hipSetDevice(p->device));
+  hipStream_t s = S(stream);
+  int st = CS_OK;
+  if (mu != p->mu) {
+    if (p->desc.flags & CS_FLAG_NO_REFACTOR)
+      return set_error(CS_EMU_MISMATCH, "mu differs from the plan's mu");
+    if ((st = build_factor(p, mu, s)) != CS_OK) return st;
+  }
+  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
+  const size_t nimg = (size_t)nv * nh * nt;
+  const float2 zero = make_float2(0.f, 0.f);
+  auto in_t = [&](const cs_c64* src, float2* dst, int frames) {
+    return launch_transpose(reinterpret_cast<const float2*>(src), dst, frames, nv, nh, s);
+  };
+  auto out_t = [&](const float2* src, cs_c64* dst, int frames) {
+    return launch_transpose(src, reinterpret_cast<float2*>(dst), frames, nh, nv, s);
+  };
+#define CK(expr)                      \
+  do {                                \
+    if ((st = (expr)) != CS_OK) return st; \
+  } while (0)
+  // setup: hybrid data F_h' y (kept for the objective) and H'y in solver layout
+  CK(launch_adjoint_rows(p, reinterpret_cast<const float2*>(y), s));
+  CK(launch_adjoint_image(p, p->hy, true, s));
+  const size_t img_bytes = nimg * sizeof(float2);
+  if (tv) {
+    if (warm) {
+      CK(in_t(state->s0, p->s0, nt));
+      CK(in_t(state->s1, p->s1, nt - 1));
+      CK(in_t(state->s2, p->s2, nt));
+      CK(in_t(state->s3, p->s3, nt));
+    } else {
+      CS_HIP(hipMemcpyAsync(p->s0, p->hy, img_bytes, hipMemcpyDeviceToDevice, s));  // m = x
+      CS_HIP(hipMemcpyAsync(p->s2, p->hy, img_bytes, hipMemcpyDeviceToDevice, s));  // x = H'y
+      CK(launch_fill(p->s1, nimg, zero, s));
+      CK(launch_fill(p->s3, nimg, zero, s));
+    }
+  } else {
+    if (warm) {
+      CK(in_t(state->s0, p->img_tmp, nt));                 // w, used as is by the first pass
+      CK(launch_dft_apply(p, p->img_tmp, p->s2, nullptr, nullptr, 1, s));  // z = Psi' w (x_out if iters == 0)
+      CK(in_t(state->s1, p->s1, nt));                      // v
+      CK(in_t(state->s2, p->s0, nt));                      // d
+    } else {
+      CS_HIP(hipMemcpyAsync(p->s2, p->hy, img_bytes, hipMemcpyDeviceToDevice, s));  // Psi' w_0 = H'y
+      CK(launch_fill(p->s0, nimg, zero, s));
+      CK(launch_fill(p->s1, nimg, zero, s));
+    }
+  }
+  CK(run_iterations(p, iters, lambda, mu, J_trace, (!tv && warm) ? p->img_tmp : nullptr, s));
+  CK(out_t(p->s2, x_out, nt));
+  if (state) {
+    if (tv) {
+      CK(out_t(p->s0, state->s0, nt));
+      CK(out_t(p->s1, state->s1, nt - 1));
+      CK(out_t(p->s2, state->s2, nt));
+      CK(out_t(p->s3, state->s3, nt));
+    } else if (iters > 0 || !warm) {
+      // w = Psi z; after iterations this also completes the deferred dual
+      // update d <- d - (w - v) of the last one.  A warm start with no
+      // iteration leaves the caller's state untouched.
+      CK(launch_dft_apply(p, p->s2, p->img_tmp, iters > 0 ? p->s0 : nullptr, p->s1, 0, s));
+      CK(out_t(p->img_tmp, state->s0, nt));
+      CK(out_t(p->s1, state->s1, nt));
+      CK(out_t(p->s0, state->s2, nt));
+    }
+    state->iter += iters;
+  }
+#undef CK
+  return CS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+// Plan-time factor of the exact x-update (Sec. IV-C).
+//
+// H'H is block diagonal with one nv x nv block per (column i, frame t)
+// (eqs. HconjH, separate_x):
+//     G_{i,t}[j,k] = p_t[(j - k) mod nv] * sum_c conj(s_{c,j,i}) s_{c,k,i},
+// where p_t is the first column of the circulant F_v' M_t F_v,
+//     p_t[l] = (1/nv) sum_{ky sampled in frame t} exp(+2 pi i ky l / nv).
+// (The coil product is conj(s_j) s_k; the printed Hadamard form s s' is its
+// conjugate, which is not the block for complex maps.)
+//
+// The paper applies (mu I + G)^{-1} = U diag(1/(e + mu)) U' through an
+// eigendecomposition of every block.  Here the inverse W = (mu I + G)^{-1} is
+// formed once, in FP64, by blocked in-place Gauss-Jordan elimination without
+// pivoting (mu I + G is Hermitian positive definite, so every pivot block is
+// too), and stored in complex64 as nv(nv+1)/2 values per block in
+// "circulant-diagonal" order: for s = 0 .. floor(nv/2),
+//     c_s[k] = W[k, (k + s) mod nv],   k < nv   (k < nv/2 when s = nv/2).
+// Those wrapped diagonals hold every entry of the Hermitian W exactly once,
+// and the per-iteration product W b then reads them as contiguous runs.
+#include "internal.hpp"
+
+namespace csmri {
+
+// ws block (column-major, A(r, c) at c * nv + r) = mu I + G_{i,t}
+__global__ __launch_bounds__(512) void k_gram_assemble(double2* __restrict__ ws,
+                                                       const float2* __restrict__ coil_cm,
+                                                       const double2* __restrict__ pcol, int nv, int nh,
+                                                       int nc, int blk0, double mu) {
+  constexpr int kCoilChunk = 16;
+  extern __shared__ float2 sc[];  // [kCoilChunk][nv]
+  const int blk = blk0 + blockIdx.x;
+  const int t = blk / nh, i = blk - t * nh;
+  const int j = threadIdx.x;  // row
+  double2* A = ws + (size_t)blockIdx.x * nv * nv;
+  const double2* pt = pcol + (size_t)t * nv;
+  for (int c0 = 0; c0 < nc; c0 += kCoilChunk) {
+    const int cn = min(kCoilChunk, nc - c0);
+    const bool last = c0 + kCoilChunk >= nc;
+    __syncthreads();
+    for (int e = threadIdx.x; e < cn * nv; e += blockDim.x) {
+      const int cc = e / nv, q = e - cc * nv;
+      sc[cc * nv + q] = coil_cm[((size_t)(c0 + cc) * nh + i) * nv + q];
+    }
+    __syncthreads();
+    if (j < nv) {
+      double2 sj[kCoilChunk];
+#pragma unroll
+      for (int cc = 0; cc < kCoilChunk; ++cc) {
+        float2 v = cc < cn ? sc[cc * nv + j] : make_float2(0.f, 0.f);
+        sj[cc] = make_double2(v.x, -(double)v.y);  // conj(s_j)
+      }
+      for (int k = 0; k < nv; ++k) {
+        double2 g = c0 == 0 ? make_double2(0.0, 0.0) : A[(size_t)k * nv + j];
+#pragma unroll
+        for (int cc = 0; cc < kCoilChunk; ++cc) {
+          if (cc < cn) {
+            const float2 v = sc[cc * nv + k];
+            g = zfma(sj[cc], make_double2(v.x, v.y), g);
+          }
+        }
+        if (last) {
+          int l = j - k;
+          l += l < 0 ? nv : 0;
+          g = zmul(pt[l], g);
+          if (j == k) g.x += mu;
+        }
+        A[(size_t)k * nv + j] = g;
+      }
+    }
+  }
+}
+
+// In-place inverse of each column-major n x n block (Hermitian positive
+// definite) by blocked Gauss-Jordan with panels of NB columns:
+//   D = A_PP^{-1};  A_PQ <- D A_PQ;  A_QQ <- A_QQ - A_QP A_PQ;  A_QP <- -A_QP D;  A_PP <- D
+// Thread i owns row i; the new row panel sits in LDS as Rl[j * NB + k].
+template <int NB>
+__global__ __launch_bounds__(512) void k_gj_inverse(double2* __restrict__ ws, int n) {
+  extern __shared__ double2 lds2[];
+  double2* Rl = lds2;                   // [n][NB]
+  double2* Dl = lds2 + (size_t)n * NB;  // [NB][NB + 1]
+  constexpr int LD = NB + 1;
+  double2* A = ws + (size_t)blockIdx.x * n * n;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int i = tid;
+  for (int p0 = 0; p0 < n; p0 += NB) {
+    const int nb = min(NB, n - p0);
+    const bool in_panel = i >= p0 && i < p0 + nb;
+    double2 C[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      C[k] = (i < n && k < nb) ? A[(size_t)(p0 + k) * n + i] : make_double2(0.0, 0.0);
+    if (in_panel) {
+#pragma unroll
+      for (int k = 0; k < NB; ++k)
+        if (k < nb) Dl[(i - p0) * LD + k] = C[k];
+    }
+    __syncthreads();
+    // unblocked Gauss-Jordan on the nb x nb diagonal block; every thread
+    // computes up to kPer entries from the old block, then all write
+    {
+      constexpr int kPer = (NB * NB + 63) / 64;  // the workgroup has >= 64 threads
+      for (int q = 0; q < nb; ++q) {
+        double2 val[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int e = tid + u * nthr;
+          val[u] = make_double2(0.0, 0.0);
+          if (e < nb * nb) {
+            const int r = e / nb, cc = e - (e / nb) * nb;
+            const double2 pinv = zrecip(Dl[q * LD + q]);
+            if (r == q && cc == q) {
+              val[u] = pinv;
+            } else if (r == q) {
+              val[u] = zmul(Dl[q * LD + cc], pinv);
+            } else if (cc == q) {
+              const double2 v = zmul(Dl[r * LD + q], pinv);
+              val[u] = make_double2(-v.x, -v.y);
+            } else {
+              val[u] = zfms(zmul(Dl[r * LD + q], pinv), Dl[q * LD + cc], Dl[r * LD + cc]);
+            }
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int e = tid + u * nthr;
+          if (e < nb * nb) Dl[(e / nb) * LD + (e - (e / nb) * nb)] = val[u];
+        }
+        __syncthreads();
+      }
+    }
+    // new row panel R = D A_PQ
+    for (int e = tid; e < n * NB; e += nthr) {
+      const int j = e / NB, k = e - j * NB;
+      if (k < nb && (j < p0 || j >= p0 + nb)) {
+        const double2* col = A + (size_t)j * n + p0;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int l = 0; l < nb; ++l) acc = zfma(Dl[k * LD + l], col[l], acc);
+        Rl[j * NB + k] = acc;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < n * NB; e += nthr) {
+      const int j = e / NB, k = e - j * NB;
+      if (k < nb && (j < p0 || j >= p0 + nb)) A[(size_t)j * n + p0 + k] = Rl[j * NB + k];
+    }
+    if (i < n) {
+      if (!in_panel) {
+        // columns outside the panel: [0, p0) and [p0 + nb, n)
+        auto update = [&](int j) {
+          double2 a = A[(size_t)j * n + i];
+#pragma unroll
+          for (int k = 0; k < NB; ++k)
+            if (k < nb) a = zfms(C[k], Rl[j * NB + k], a);
+          A[(size_t)j * n + i] = a;
+        };
+        for (int j = 0; j < p0; ++j) update(j);
+        for (int j = p0 + nb; j < n; ++j) update(j);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          if (k < nb) {
+            double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int l = 0; l < NB; ++l)
+              if (l < nb) acc = zfma(C[l], Dl[l * LD + k], acc);
+            A[(size_t)(p0 + k) * n + i] = make_double2(-acc.x, -acc.y);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+          if (k < nb) A[(size_t)(p0 + k) * n + i] = Dl[(i - p0) * LD + k];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// packing into the wrapped-diagonal layout: c_s[k] = W[k, (k + s) mod n]
+__global__ void k_pack_circdiag(const double2* __restrict__ ws, float2* __restrict__ factor, FactorLayout L,
+                                int blk0) {
+  const int s = blockIdx.y;
+  const int k = threadIdx.x;
+  const int n = L.n;
+  if (k >= n) return;
+  const bool half = s == L.F;  // only launched for even n
+  if (half && k >= n / 2) return;
+  const double2* W = ws + (size_t)blockIdx.x * n * n;
+  int col = k + s;
+  col -= col >= n ? n : 0;
+  const double2 w = W[(size_t)col * n + k];
+  const size_t blk = (size_t)blk0 + blockIdx.x;
+  const size_t off = half ? half_offset(L, blk) : diag_offset(L, blk, s);
+  factor[off + k] = make_float2((float)w.x, (float)w.y);
+}
+
+static inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+int build_factor(cs_plan* p, float mu, hipStream_t s) {
+  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
+  const size_t nblocks = (size_t)nt * nh;
+  const size_t blk_bytes = (size_t)nv * nv * sizeof(double2);
+  const size_t ws_limit = (size_t)1 << 30;
+  const size_t chunk = std::max<size_t>(1, std::min(nblocks, ws_limit / blk_bytes));
+  double2* ws = static_cast<double2*>(p->alloc.get(chunk * blk_bytes));
+  if (!ws) return set_error(CS_ENOMEM, "allocator returned NULL for the FP64 factor workspace");
+  const int wg = round_up(nv, 64);
+  const int nb = nv <= 256 ? 16 : 8;
+  const size_t lds_gj = ((size_t)nv * nb + (size_t)nb * (nb + 1)) * sizeof(double2);
+  const int ndiag = (nv & 1) ? (nv + 1) / 2 : nv / 2 + 1;
+  if (lds_gj > 65536) {
+    hipError_t ea = nb == 16 ? hipFuncSetAttribute((const void*)k_gj_inverse<16>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_gj)
+                             : hipFuncSetAttribute((const void*)k_gj_inverse<8>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_gj);
+    if (ea != hipSuccess) {
+      p->alloc.put(ws);
+      return hip_fail(ea, "hipFuncSetAttribute(k_gj_inverse)");
+    }
+  }
+  int st = CS_OK;
+  for (size_t b0 = 0; b0 < nblocks && st == CS_OK; b0 += chunk) {
+    const int nblk = (int)std::min(chunk, nblocks - b0);
+    hipLaunchKernelGGL(k_gram_assemble, dim3(nblk), dim3(wg), (size_t)16 * nv * sizeof(float2), s, ws,
+                       p->coil_cm, p->pcol, nv, nh, nc, (int)b0, (double)mu);
+    if (nb == 16)
+      hipLaunchKernelGGL(k_gj_inverse<16>, dim3(nblk), dim3(wg), lds_gj, s, ws, nv);
+    else
+      hipLaunchKernelGGL(k_gj_inverse<8>, dim3(nblk), dim3(wg), lds_gj, s, ws, nv);
+    hipLaunchKernelGGL(k_pack_circdiag, dim3(nblk, ndiag), dim3(wg), 0, s, ws, p->factor, p->flayout, (int)b0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) st = hip_fail(e, "factor kernels");
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  p->alloc.put(ws);
+  if (st != CS_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(factor)");
+  p->mu = mu;
+  return CS_OK;
+}
+
+}  // namespace csmri

@@ -1,0 +1,219 @@
+// Internal declarations shared by the HIP translation units of libcsmri.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "csmri.h"
+
+namespace csmri {
+
+// ---------------------------------------------------------------- complex
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__host__ __device__ inline float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+// acc + a * b
+__host__ __device__ inline float2 cfma(float2 a, float2 b, float2 acc) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+  return acc;
+}
+// acc + conj(a) * b
+__host__ __device__ inline float2 cfmac(float2 a, float2 b, float2 acc) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(-a.y, b.x, acc.y);
+  return acc;
+}
+__host__ __device__ inline double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 zfma(double2 a, double2 b, double2 acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+// acc - a * b
+__host__ __device__ inline double2 zfms(double2 a, double2 b, double2 acc) {
+  acc.x = fma(-a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(-a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+  return acc;
+}
+__host__ __device__ inline double2 zrecip(double2 a) {
+  double d = a.x * a.x + a.y * a.y;
+  return make_double2(a.x / d, -a.y / d);
+}
+
+// Complex soft threshold: (|a| - tau) a / |a| if |a| > tau, else 0.
+__device__ inline float2 soft_threshold(float2 a, float tau) {
+  float mag = sqrtf(a.x * a.x + a.y * a.y);
+  if (!(mag > tau)) return make_float2(0.f, 0.f);
+  float s = (mag - tau) / mag;
+  return make_float2(a.x * s, a.y * s);
+}
+
+// ---------------------------------------------------------------- factor layout
+//
+// Storage of the per-(column, frame) inverses W = (mu I + G)^{-1}, n = nv.
+// Block b = t*nh + i holds its wrapped diagonals c_s[k] = W[k, (k+s) mod n]:
+// F = ceil(n/2) full diagonals s = 0..F-1 of n values, plus for even n the
+// half diagonal s = n/2 of n/2 values -- n(n+1)/2 values per block in all.
+// Full diagonals are grouped G = 2^glog at a time across blocks,
+//     [s / G][block][s % G][k],
+// so that the workgroups streaming neighbouring blocks read a compact
+// address window; the half diagonals of all blocks follow, [block][k].
+struct FactorLayout {
+  int n;
+  int F;
+  int glog;
+  size_t nblk;
+};
+__host__ __device__ inline size_t diag_offset(const FactorLayout& L, size_t blk, int s) {
+  return ((((size_t)(s >> L.glog) * L.nblk + blk) << L.glog) + (size_t)(s & ((1 << L.glog) - 1))) * L.n;
+}
+__host__ __device__ inline size_t half_offset(const FactorLayout& L, size_t blk) {
+  return (size_t)L.F * L.n * L.nblk + blk * (size_t)(L.n / 2);
+}
+inline FactorLayout make_factor_layout(int n, size_t nblk) {
+  FactorLayout L;
+  L.n = n;
+  L.F = (n + 1) / 2;
+  L.glog = 3;
+  while (L.glog > 0 && (L.F % (1 << L.glog)) != 0) --L.glog;
+  L.nblk = nblk;
+  return L;
+}
+inline size_t factor_elems(const FactorLayout& L) { return L.nblk * (size_t)L.n * (L.n + 1) / 2; }
+
+// ---------------------------------------------------------------- FFT plan
+constexpr int kMaxFftPasses = 12;
+struct FftDesc {
+  int n;
+  int npass;
+  int radix[kMaxFftPasses];
+};
+bool make_fft_desc(int n, FftDesc* d);  // false if n is not 2^a 3^b in [2, 512]
+
+// ---------------------------------------------------------------- errors
+int set_error(int status, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+#define CS_HIP(expr)                                   \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);  \
+  } while (0)
+
+// ---------------------------------------------------------------- plan
+struct DeviceAlloc {
+  cs_allocator a;
+  bool custom;
+  void* get(size_t bytes);
+  void put(void* p);
+};
+
+}  // namespace csmri
+
+struct cs_plan {
+  cs_plan_desc desc;
+  int device = 0;
+  float mu = 0.f;
+  csmri::DeviceAlloc alloc;
+  std::vector<void*> owned;
+  size_t bytes = 0;
+
+  // sampling pattern
+  int m_max = 0;
+  std::vector<int32_t> h_mcnt;  // sampled rows per frame
+  int32_t* rows = nullptr;      // [nt][m_max] sampled ky, padded with -1
+  int32_t* mcnt = nullptr;      // [nt]
+  uint8_t* mask = nullptr;      // [nt][nv]
+  double2* pcol = nullptr;      // [nt][nv] first column of F_v' M_t F_v (FP64)
+
+  // tables
+  csmri::FftDesc fft_v{}, fft_h{};
+  float2* tw_v = nullptr;       // exp(-2 pi i q / nv), q < nv
+  float2* tw_h = nullptr;
+  float2* psi_t = nullptr;      // [nt][nt] unitary temporal DFT matrix (DFT prior)
+  float* tv_invden = nullptr;   // [nt] Thomas coefficients of (rho I + D'D)
+
+  // coil maps in the solver's column-major layout [c][i][j]
+  float2* coil_cm = nullptr;
+
+  // factor: nt*nh blocks (t, i), block index t*nh + i, layout csmri::FactorLayout
+  float2* factor = nullptr;
+  csmri::FactorLayout flayout{};
+
+  // workspaces (solver layout [t][i][j], i.e. column-contiguous)
+  float2* ktmp = nullptr;       // [nt][nc][m_max][nh] hybrid-space rows of the data, F_h' y
+  float2* ftmp = nullptr;       // [nt][nc][m_max][nh] forward intermediate, M_t F_v (s_c . x)
+  float2* hy = nullptr;         // H'y
+  float2* s0 = nullptr;         // TV: m   DFT: d
+  float2* s1 = nullptr;         // TV: d1  DFT: v
+  float2* s2 = nullptr;         // TV: x   DFT: z (image-domain iterate)
+  float2* s3 = nullptr;         // TV: d2  DFT: u
+  float2* img_tmp = nullptr;    // one image, layout conversions
+  double* jpart = nullptr;      // objective partial sums
+  int jpart_len = 0;
+
+  hipGraphExec_t graph = nullptr;  // cached iteration graph
+  void* graph_key[8] = {};
+
+  // per-kernel event timing (cs_kernel_timing)
+  bool timing = false;
+  struct TimedLaunch {
+    int kind;
+    hipEvent_t start, stop;
+  };
+  std::vector<TimedLaunch> timed;   // event pairs recorded since the last read
+  std::vector<hipEvent_t> event_pool;
+  size_t pool_next = 0;
+};
+
+namespace csmri {
+
+// sense.hip
+int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipStream_t s);
+int launch_adjoint_rows(cs_plan* p, const float2* y, hipStream_t s);  // y -> p->ktmp
+int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s);  // p->ktmp -> x
+int launch_transpose(const float2* in, float2* out, int frames, int rows, int cols, hipStream_t s);
+
+// factor.hip
+int build_factor(cs_plan* p, float mu, hipStream_t s);
+
+// iterate.hip
+int launch_block_solve(cs_plan* p, int mode, const float2* hy, const float2* m, float2* d2,
+                       float2* x, float mu, hipStream_t s);
+int launch_tv_step(cs_plan* p, float lambda, float mu, hipStream_t s);
+// first != 0 skips the deferred dual update; wgiven (nullable) replaces Psi z on this pass
+int launch_dft_step(cs_plan* p, float lambda, float mu, int first, const float2* wgiven, hipStream_t s);
+// out = Psi in (adjoint == 0) or Psi' in (adjoint == 1); with dual != nullptr (forward only)
+// also d <- d - (out - v)
+int launch_dft_apply(cs_plan* p, const float2* in, float2* out, float2* dual, const float2* v, int adjoint,
+                     hipStream_t s);
+int launch_fill(float2* ptr, size_t n, float2 v, hipStream_t s);
+int launch_objective(cs_plan* p, const float2* x, float lambda, float* out, hipStream_t s);
+
+enum BlockSolveMode { kSolvePlain = 0, kSolveTV = 1, kSolveDFT = 2 };
+
+}  // namespace csmri

@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/csmri.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1203_4587_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "csmri.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cs_[a-z_A-Z0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libcsmri.so is not built (run python -m paper_1203_4587_amd.build)")
+    return _lib.load()
+
+
+def test_every_declared_function_is_exported(lib):
+    names = declared_functions()
+    assert "cs_admm_solve" in names and "cs_plan_create" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(_lib.EXPORTED) == names
+
+
+def test_status_strings(lib):
+    for st in range(6):
+        assert lib.cs_status_string(st)
+    assert b"unknown" in lib.cs_status_string(99)
+    assert lib.cs_version() >= 10000
+
+
+def _desc(nv=64, nh=64, nt=8, nc=4, prior=0, rho=0.5):
+    return _lib.CsPlanDesc(nv, nh, nt, nc, prior, rho, 0)
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced on the paths below
+
+
+def _create(lib, desc, mu=0.1, alloc=None, coil=FAKE, mask=FAKE):
+    h = ctypes.c_void_p()
+    st = lib.cs_plan_create(ctypes.byref(desc) if desc is not None else None, coil, mask, mu,
+                            ctypes.byref(alloc) if alloc is not None else None, None, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(nv=1), _lib.CS_EINVAL),
+    (dict(nc=0), _lib.CS_EINVAL),
+    (dict(nt=1, prior=0), _lib.CS_EINVAL),          # TV needs two frames
+    (dict(prior=7), _lib.CS_EINVAL),
+    (dict(rho=0.0), _lib.CS_EINVAL),
+    (dict(nv=100), _lib.CS_EUNSUPPORTED),           # not 2^a 3^b
+    (dict(nh=1024), _lib.CS_EUNSUPPORTED),          # > 512
+    (dict(nt=65), _lib.CS_EUNSUPPORTED),
+    (dict(nc=65), _lib.CS_EUNSUPPORTED),
+])
+def test_plan_create_rejects_bad_descriptors(lib, kw, expect):
+    st, h = _create(lib, _desc(**kw))
+    assert st == expect, lib.cs_last_error()
+    assert h.value is None
+    assert lib.cs_last_error()
+
+
+def test_plan_create_rejects_bad_scalars_and_nulls(lib):
+    assert _create(lib, _desc(), mu=0.0)[0] == _lib.CS_EINVAL
+    assert _create(lib, _desc(), mu=float("nan"))[0] == _lib.CS_EINVAL
+    assert _create(lib, None)[0] == _lib.CS_EINVAL
+    assert _create(lib, _desc(), coil=None)[0] == _lib.CS_EINVAL
+    assert lib.cs_plan_create(ctypes.byref(_desc()), FAKE, FAKE, 0.1, None, None, None) == _lib.CS_EINVAL
+
+
+def test_allocator_failure_is_enomem(lib):
+    calls = []
+
+    def alloc(nbytes, ctx):
+        calls.append(nbytes)
+        return None
+
+    def free(ptr, ctx):
+        raise AssertionError("nothing was allocated")
+    a = _lib.CsAllocator(_lib.ALLOC_FN(alloc), _lib.FREE_FN(free), None)
+    st, h = _create(lib, _desc(nv=256, nh=256, nt=32, nc=8), alloc=a)
+    assert st == _lib.CS_ENOMEM
+    assert h.value is None
+    # the first request is the packed factor: nh*nt blocks of nv(nv+1)/2 complex64
+    assert calls and calls[0] >= 256 * 32 * (256 * 257 // 2) * 8
+
+
+def test_null_plan_calls_are_einval(lib):
+    assert lib.cs_apply_A(None, FAKE, FAKE, None) == _lib.CS_EINVAL
+    assert lib.cs_apply_AH(None, FAKE, FAKE, None) == _lib.CS_EINVAL
+    assert lib.cs_apply_block_inverse(None, FAKE, FAKE, None) == _lib.CS_EINVAL
+    assert lib.cs_admm_solve(None, FAKE, 0.01, 0.1, 10, FAKE, None, None, None) == _lib.CS_EINVAL
+    assert lib.cs_plan_destroy(None) == _lib.CS_OK
+    n = ctypes.c_size_t()
+    assert lib.cs_plan_bytes(None, ctypes.byref(n)) == _lib.CS_EINVAL
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        _lib.load()

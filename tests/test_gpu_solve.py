@@ -1,0 +1,178 @@
+"""GPU parity of cs_admm_solve against the FP64 oracle (Algorithms 1 and 2),
+through the C ABI.  Tolerance: relative l2 <= 1e-4 after a fixed number of
+iterations.  Full-size workloads are checked on sampled columns, which the
+oracle computes exactly because temporal priors never couple columns."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1203_4587_amd import synthetic as S
+from tests.helpers import Case, c64, make_case, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _run(case, prior, lam, mu, rho, iters, state=None, trace=False, flags=0):
+    from paper_1203_4587_amd.api import Plan
+    coil, mask, y = case.device()
+    plan = Plan(coil, mask, mu, prior=prior, mu_ratio=rho, flags=flags)
+    out = plan.solve(y, lam, iters, state=state, trace=trace)
+    return plan, y, out
+
+
+def _oracle(case, prior, lam, mu, rho, iters, cols=None):
+    return O.solve(case.y, case.coil, case.mask, prior, lam, mu, rho, iters, cols=cols)
+
+
+def test_tv_small_workload_matches_oracle():
+    """The 64x64x8, 4-coil, R=4 temporal-TV workload, 50 iterations."""
+    case = Case(S.CONFIGS["tv64"]())
+    p = case.p
+    plan, _, x = _run(case, "tv", p.lam, p.mu, p.rho, p.iters)
+    ref = _oracle(case, "tv", p.lam, p.mu, p.rho, p.iters)
+    err = rel_l2(x.cpu().numpy(), ref["x"])
+    print("tv64 rel_l2", err)
+    assert err < TOL
+
+
+@pytest.mark.parametrize("shape,prior,iters", [
+    ((48, 32, 12, 3), "dft", 40),
+    ((96, 24, 5, 4), "tv", 30),
+    ((27, 18, 4, 2), "tv", 25),       # odd nv: wrapped-diagonal storage without the n/2 diagonal
+    ((54, 12, 7, 3), "dft", 25),
+    ((32, 16, 2, 2), "tv", 20),       # two frames: one temporal difference
+    ((16, 8, 1, 2), "dft", 10),       # single frame: Psi is the identity
+    ((64, 8, 64, 2), "tv", 10),       # maximum frame count
+    ((64, 8, 64, 2), "dft", 10),
+], ids=lambda v: str(v))
+def test_solves_match_oracle(shape, prior, iters):
+    nv, nh, nt, nc = shape
+    fam = "cardiac" if prior == "tv" else "periodic"
+    case = make_case(nv, nh, nt, nc, accel=3, ncenter=2, prior=prior, family=fam, seed=nv * nt, sigma=0.01)
+    lam, mu, rho = 0.02, 0.1, 0.5
+    _, _, x = _run(case, prior, lam, mu, rho, iters)
+    ref = _oracle(case, prior, lam, mu, rho, iters)
+    err = rel_l2(x.cpu().numpy(), ref["x"])
+    print(shape, prior, "rel_l2", err)
+    assert err < TOL
+
+
+@pytest.mark.parametrize("prior", ["tv", "dft"])
+def test_state_resume_and_oracle_state(prior):
+    fam = "cardiac" if prior == "tv" else "periodic"
+    case = make_case(64, 32, 10, 4, accel=4, ncenter=4, prior=prior, family=fam, seed=77)
+    lam, mu, rho = 0.02, 0.1, 0.5
+    from paper_1203_4587_amd.api import Plan
+    coil, mask, y = case.device()
+    plan = Plan(coil, mask, mu, prior=prior, mu_ratio=rho)
+    full = plan.new_state()
+    x50 = plan.solve(y, lam, 50, state=full)
+    part = plan.new_state()
+    plan.solve(y, lam, 25, state=part)
+    x2 = plan.solve(y, lam, 25, state=part)
+    assert part.iter == 50 and full.iter == 50
+    assert torch.equal(x50, x2)
+    for name in ("s0", "s1", "s2", "s3"):
+        a, b = getattr(full, name), getattr(part, name)
+        if a is not None:
+            assert torch.equal(a, b), name
+    ref = _oracle(case, prior, lam, mu, rho, 50)
+    names = {"tv": ("m", "d1", "x", "d2"), "dft": ("w", "v", "d", None)}[prior]
+    for sname, oname in zip(("s0", "s1", "s2", "s3"), names):
+        if oname is not None:
+            err = rel_l2(getattr(full, sname).cpu().numpy(), ref[oname])
+            assert err < TOL * 5, (oname, err)
+
+
+@pytest.mark.parametrize("prior", ["tv", "dft"])
+def test_zero_iterations_return_initialisation(prior):
+    case = make_case(32, 16, 4, 2, prior=prior, seed=5)
+    plan, _, x = _run(case, prior, 0.01, 0.1, 0.5, 0)
+    assert rel_l2(x.cpu().numpy(), O.adjoint(case.y, case.coil, case.mask)) < 1e-5
+
+
+@pytest.mark.parametrize("prior", ["tv", "dft"])
+def test_objective_trace_matches_oracle(prior):
+    fam = "cardiac" if prior == "tv" else "periodic"
+    case = make_case(48, 32, 8, 3, accel=3, ncenter=4, prior=prior, family=fam, seed=11)
+    lam, mu, rho, iters = 0.02, 0.1, 0.5, 12
+    _, _, (x, J) = _run(case, prior, lam, mu, rho, iters, trace=True)
+    Jref = []
+    fac = O.BlockFactor(case.coil, case.mask)
+    Hy = O.adjoint(case.y, case.coil, case.mask)
+    f = O.objective_tv if prior == "tv" else O.objective_dft
+    cb = lambda k, xx: Jref.append(f(xx, case.y, case.coil, case.mask, lam))
+    if prior == "tv":
+        O.admm_analysis(Hy, fac, lam, mu, rho, iters, callback=cb)
+    else:
+        O.admm_synthesis(Hy, fac, lam, mu, iters, callback=cb)
+    J = J.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(J, Jref, rtol=1e-4)
+    d = [O.delta(a, b) for a, b in zip(J[:-1], J[1:])]
+    dref = [O.delta(a, b) for a, b in zip(Jref[:-1], Jref[1:])]
+    np.testing.assert_allclose(d, dref, atol=1e-4)
+
+
+def test_mu_change_refactors_and_no_refactor_flag():
+    from paper_1203_4587_amd import _lib
+    from paper_1203_4587_amd.api import Plan
+    case = make_case(32, 16, 6, 3, seed=21)
+    coil, mask, y = case.device()
+    plan = Plan(coil, mask, 0.1, prior="tv")
+    x_a = plan.solve(y, 0.01, 10, mu=0.2)
+    ref = _oracle(case, "tv", 0.01, 0.2, 0.5, 10)
+    assert rel_l2(x_a.cpu().numpy(), ref["x"]) < TOL
+    strict = Plan(coil, mask, 0.1, prior="tv", flags=_lib.CS_FLAG_NO_REFACTOR)
+    with pytest.raises(_lib.CsmriError) as ei:
+        strict.solve(y, 0.01, 10, mu=0.2)
+    assert ei.value.status == _lib.CS_EMU_MISMATCH
+
+
+def test_solve_rejects_bad_scalars():
+    from paper_1203_4587_amd import _lib
+    from paper_1203_4587_amd.api import Plan
+    case = make_case(16, 8, 3, 2, seed=1)
+    coil, mask, y = case.device()
+    plan = Plan(coil, mask, 0.1)
+    for lam, mu, it in [(-1.0, 0.1, 5), (0.01, 0.0, 5), (0.01, 0.1, -1), (float("inf"), 0.1, 5)]:
+        with pytest.raises(_lib.CsmriError) as ei:
+            plan.solve(y, lam, it, mu=mu)
+        assert ei.value.status == _lib.CS_EINVAL
+
+
+def _sampled_columns(nh):
+    return np.array(sorted({0, 1, nh // 3, nh // 2 + 1, nh - 1}))
+
+
+def test_full_size_tv_256x256x32_8c_sampled_columns():
+    """The 256x256x32, 8-coil, R=8 temporal-TV workload at full size, 100
+    iterations, in the launch configuration the benchmark times; the oracle
+    recomputes five columns exactly."""
+    case = Case(S.CONFIGS["tv256"]())
+    p = case.p
+    _, _, x = _run(case, "tv", p.lam, p.mu, p.rho, p.iters)
+    cols = _sampled_columns(p.x_true.shape[2])
+    ref = _oracle(case, "tv", p.lam, p.mu, p.rho, p.iters, cols=cols)
+    err = rel_l2(x.cpu().numpy()[:, :, cols], ref["x"])
+    print("tv256 sampled rel_l2", err)
+    assert err < TOL
+
+
+def test_full_size_dft_192x192x40_12c_sampled_columns():
+    case = Case(S.CONFIGS["dft192"]())
+    p = case.p
+    _, _, x = _run(case, "dft", p.lam, p.mu, p.rho, p.iters)
+    cols = _sampled_columns(p.x_true.shape[2])
+    ref = _oracle(case, "dft", p.lam, p.mu, p.rho, p.iters, cols=cols)
+    err = rel_l2(x.cpu().numpy()[:, :, cols], ref["x"])
+    print("dft192 sampled rel_l2", err)
+    assert err < TOL
