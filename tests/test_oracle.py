@@ -486,3 +486,24 @@ def test_dft_iteration_steps_are_the_stated_argmins(rng):
     np.testing.assert_allclose(st1["w"].ravel(), w1, atol=1e-12)
     np.testing.assert_allclose(st1["d"].ravel(), d0 - (w1 - v), atol=1e-12)
     np.testing.assert_allclose(st1["x"].ravel(), P.conj().T @ w1, atol=1e-12)
+
+
+def test_objectives_match_dense_definitions(rng):
+    """J of eqs. L1an_pri / L1unconst from dense matrices built without FFTs."""
+    nt, nv, nh, nc = 3, 4, 2, 2
+    coil, mask = tiny_problem(rng, nt=nt, nv=nv, nh=nh, nc=nc)
+    y = crandn(rng, nt, nc, nv, nh) * mask[:, None, :, None]
+    x = crandn(rng, nt, nv, nh)
+    lam = 0.37
+    H = dense_H(coil, mask)
+    r = y.ravel() - H @ x.ravel()
+    Dm = np.zeros((nt - 1, nt))
+    for t in range(nt - 1):
+        Dm[t, t], Dm[t, t + 1] = -1, 1
+    Dx = np.einsum("st,tji->sji", Dm, x)
+    J_tv = lam * np.abs(Dx).sum() + np.vdot(r, r).real
+    assert np.isclose(O.objective_tv(x, y, coil, mask, lam), J_tv, rtol=1e-13)
+    Fm = np.array([[np.exp(-2j * np.pi * f * t / nt) for t in range(nt)] for f in range(nt)]) / np.sqrt(nt)
+    Px = np.einsum("ft,tji->fji", Fm, x)
+    J_dft = lam * np.abs(Px).sum() + np.vdot(r, r).real
+    assert np.isclose(O.objective_dft(x, y, coil, mask, lam), J_dft, rtol=1e-13)
