@@ -35,7 +35,6 @@ WORKLOADS = {
     "dft192": dict(name="dft-192x192x40-12c", prior="dft"),
     "tv64": dict(name="tv-64x64x8-4c", prior="tv"),
 }
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "x_update_tv256_traffic.json")
 
 
 def log(*a):
@@ -47,16 +46,21 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per x-update launch from the committed rocprofv3 PMC summary,
-    or None when it is missing or was taken on a different kernel source."""
+def measured_traffic(kind: str, workload: str, steps: int):
+    """HBM bytes per launch of `kind` from the committed rocprofv3 PMC summary
+    (profiles/<kind>_<workload>_traffic.json), or None when it is missing or
+    was taken on a different kernel source.  The single-launch solve's record
+    is per iteration and is scaled by the launch's iteration count."""
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_traffic.json")
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
     if rec.get("kernel_sha") != kernel_source_sha() or rec.get("workload") != workload:
         return None
+    if "bytes_per_iteration" in rec:
+        return int(rec["bytes_per_iteration"] * steps)
     return rec.get("bytes_per_launch")
 
 
@@ -108,6 +112,9 @@ def main() -> int:
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--column-resident", action="store_true",
+                    help="one launch for all iterations (a workgroup per readout column) instead of two "
+                         "launches per iteration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs the reconstruction on one "
@@ -132,7 +139,9 @@ def main() -> int:
     coil = to_device(problem.coil)
     mask = to_device(problem.mask, dtype=torch.uint8)
     t0 = time.perf_counter()
-    plan = Plan(coil, mask, problem.mu, prior=wl["prior"], mu_ratio=problem.rho)
+    from paper_1203_4587_amd import _lib
+    flags = _lib.CS_FLAG_COLUMN_RESIDENT if args.column_resident else 0
+    plan = Plan(coil, mask, problem.mu, prior=wl["prior"], mu_ratio=problem.rho, flags=flags)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     # synthetic measured data y = H x_true + noise, formed on the device
@@ -174,11 +183,23 @@ def main() -> int:
         x_bytes = factor_bytes + 3 * img_bytes          # reads H'y, u; writes z
         t_bytes = 6 * img_bytes                         # reads z, d, v; writes d, v, u
         tkind = "dft_step"
-    launches, ms = ktimes.get("x_update", (0, 0.0))
-    x_avg_s = ms / max(launches, 1) / 1e3
-    achieved = x_bytes / x_avg_s / 1e9 if launches else None
+    if "column_solve" in ktimes:
+        # one launch runs every iteration: temporal step + x-update per column
+        kind = "column_solve"
+        launches, ms = ktimes[kind]
+        alg_bytes = (x_bytes + t_bytes) * args.steps
+        kdesc = ("column_solve (one launch for all iterations; per readout column: temporal step, then "
+                 "x-update streaming the packed Hermitian (mu I + G)^-1 of each frame)")
+    else:
+        kind = "x_update"
+        launches, ms = ktimes.get(kind, (0, 0.0))
+        alg_bytes = x_bytes
+        kdesc = "x_update (packed Hermitian (mu I + G)^-1 per column and frame)"
+    avg_s = ms / max(launches, 1) / 1e3
+    achieved = alg_bytes / avg_s / 1e9 if launches else None
     tl, tms = ktimes.get(tkind, (0, 0.0))
-    traffic = measured_traffic(args.workload)
+    xl, xms = ktimes.get("x_update", (0, 0.0))
+    traffic = measured_traffic(kind, args.workload, args.steps)
 
     line = {
         "metric": METRIC,
@@ -201,20 +222,22 @@ def main() -> int:
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "x_update (k_block_solve, packed Hermitian (mu I + G)^-1 per column and frame)",
+            "kernel": kdesc,
             "achieved": round(achieved, 1) if achieved else None,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": x_bytes,
-            "avg_launch_us": round(x_avg_s * 1e6, 2),
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "avg_launch_us": round(avg_s * 1e6, 2),
             "launches": launches,
         },
         "kernels": {
-            "x_update_us": round(x_avg_s * 1e6, 2),
-            f"{tkind}_us": round(tms / max(tl, 1) * 1e3, 2),
-            f"{tkind}_GBps": round(t_bytes / (tms / max(tl, 1) / 1e3) / 1e9, 1) if tl else None,
+            "iteration_us": round(avg_s * 1e6 / (args.steps if kind == "column_solve" else 1), 2),
+            "x_update_us": round(xms / max(xl, 1) * 1e3, 2) if xl else None,
+            f"{tkind}_us": round(tms / max(tl, 1) * 1e3, 2) if tl else None,
+            "factor_bytes_per_iteration": factor_bytes,
+            "iteration_algorithmic_bytes": x_bytes + t_bytes,
             "iteration_algorithmic_GBps": round((x_bytes + t_bytes) * value / 1e9, 1),
         },
         "plan_s": round(t_plan, 3),

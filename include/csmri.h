@@ -66,8 +66,12 @@ typedef enum {
 } cs_prior;
 
 enum {
-  CS_FLAG_NO_REFACTOR = 1u << 0,  /* cs_admm_solve with a different mu fails instead of refactoring */
-  CS_FLAG_GRAPH = 1u << 1,        /* replay the iteration loop as a captured hipGraph */
+  CS_FLAG_NO_REFACTOR = 1u << 0,     /* cs_admm_solve with a different mu fails instead of refactoring */
+  CS_FLAG_GRAPH = 1u << 1,           /* phase-kernel form: capture the iteration loop once per distinct
+                                        (iters, lambda, mu, J_trace) as a hipGraph, cache it in the plan
+                                        and replay it (not while cs_kernel_timing is on) */
+  CS_FLAG_COLUMN_RESIDENT = 1u << 2, /* run all iterations in one launch, one workgroup per readout
+                                        column, instead of two launches per iteration; same results */
 };
 
 /* Device-memory allocator used for everything the plan owns.  alloc returns
@@ -139,7 +143,11 @@ int cs_apply_block_inverse(cs_plan* plan, const cs_c64* b, cs_c64* x, cs_stream 
  *   J_trace, if not NULL, is a device float[iters] that receives the
  *   objective J(k) after each iteration (lambda ||D_t x||_1 + ||y - Hx||^2, or
  *   lambda ||Psi x||_1 + ||y - Hx||^2), used for Delta(k) of eq. r_ratio.
- * iters == 0 writes H'y (the algorithms' initial x) to x_out. */
+ * iters == 0 writes H'y (the algorithms' initial x) to x_out.
+ * Execution: two launches per iteration (temporal step, x-update).  With
+ * CS_FLAG_COLUMN_RESIDENT, even nv and no J_trace, all iterations run in one
+ * launch in which a workgroup owns one readout column (temporal priors never
+ * couple columns).  Both forms give bit-identical results. */
 int cs_admm_solve(cs_plan* plan, const cs_c64* y, float lambda, float mu, int32_t iters,
                   cs_c64* x_out, cs_state* state, float* J_trace, cs_stream stream);
 
@@ -150,7 +158,8 @@ int cs_admm_solve(cs_plan* plan, const cs_c64* y, float lambda, float mu, int32_
  * cs_kernel_times waits for those events and fills up to `max` records, one
  * per kernel kind, with the number of launches and their summed device time;
  * *count receives the number of kinds seen.  Kinds: "tv_step", "dft_step",
- * "x_update", "objective".  Event records add a few microseconds of host
+ * "x_update", "objective" (phase-kernel form) and "column_solve" (one launch
+ * running all iterations, one workgroup per readout column).  Event records add a few microseconds of host
  * work per launch and nothing to the kernels themselves. */
 typedef struct {
   char name[24];

@@ -22,6 +22,7 @@ CS_PRIOR_TEMPORAL_DFT = 1
 
 CS_FLAG_NO_REFACTOR = 1 << 0
 CS_FLAG_GRAPH = 1 << 1
+CS_FLAG_COLUMN_RESIDENT = 1 << 2
 
 # every function declared in include/csmri.h
 EXPORTED = (

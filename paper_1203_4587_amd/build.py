@@ -30,6 +30,9 @@ COMMON = [
     "-fPIC",
     # keep the compiler from forming packed-FP32 VALU instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # every fused multiply-add is written out (fmaf / fma); no implicit
+    # contraction, so a device function rounds the same wherever it is inlined
+    "-ffp-contract=off",
     "-I", os.path.join(ROOT, "include"),
     "-I", CSRC,
 ]

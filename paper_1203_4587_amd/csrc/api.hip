@@ -61,6 +61,7 @@ static int plan_alloc(cs_plan* p, T** out, size_t count, const char* what) {
 static void plan_release(cs_plan* p) {
   if (!p) return;
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   for (void* ptr : p->owned) p->alloc.put(ptr);
   p->owned.clear();
   delete p;
@@ -85,8 +86,8 @@ static int validate_desc(const cs_plan_desc* d) {
 static inline hipStream_t S(cs_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
 // ---------------------------------------------------------------- timing
-enum KernelKind { kKindTV = 0, kKindDFT = 1, kKindX = 2, kKindJ = 3, kKinds = 4 };
-static const char* kKindNames[kKinds] = {"tv_step", "dft_step", "x_update", "objective"};
+enum KernelKind { kKindTV = 0, kKindDFT = 1, kKindX = 2, kKindJ = 3, kKindColumn = 4, kKinds = 5 };
+static const char* kKindNames[kKinds] = {"tv_step", "dft_step", "x_update", "objective", "column_solve"};
 
 static hipEvent_t pool_event(cs_plan* p) {
   if (p->pool_next == p->event_pool.size()) {
@@ -111,7 +112,60 @@ static int timed_launch(cs_plan* p, int kind, hipStream_t s, F launch) {
   return CS_OK;
 }
 
+static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
+                          const float2* wgiven, hipStream_t s);
+
+// CS_FLAG_GRAPH: the phase-kernel loop is captured once per distinct
+// (iters, lambda, mu, J_trace, wgiven) and replayed from the plan's cache
+static int run_phase_graph(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
+                           const float2* wgiven, hipStream_t s) {
+  float lm[2] = {lambda, mu};
+  void* key[8] = {reinterpret_cast<void*>((intptr_t)iters), nullptr, J_trace, const_cast<float2*>(wgiven),
+                  reinterpret_cast<void*>((intptr_t)(wgiven != nullptr)), nullptr, nullptr, nullptr};
+  std::memcpy(&key[1], lm, sizeof(lm));
+  if (!p->graph || std::memcmp(key, p->graph_key, sizeof(key)) != 0) {
+    if (p->graph) {
+      CS_HIP(hipStreamSynchronize(s));  // the cached graph may still run on this stream
+      CS_HIP(hipGraphExecDestroy(p->graph));
+      p->graph = nullptr;
+    }
+    // recording runs nothing, so it happens on a private stream: the caller's
+    // stream may be the null stream, which cannot be captured
+    if (!p->capture_stream) CS_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = p->capture_stream;
+    CS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int st = run_phase_loop(p, iters, lambda, mu, J_trace, wgiven, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (st != CS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      p->graph = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    std::memcpy(p->graph_key, key, sizeof(key));
+  }
+  CS_HIP(hipGraphLaunch(p->graph, s));
+  return CS_OK;
+}
+
 static int run_iterations(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
+                          const float2* wgiven, hipStream_t s) {
+  if (!J_trace && (p->desc.flags & CS_FLAG_COLUMN_RESIDENT) && column_solve_supported(p)) {
+    if (iters == 0) return CS_OK;
+    return timed_launch(p, kKindColumn, s, [&] { return launch_column_solve(p, iters, lambda, mu, wgiven, s); });
+  }
+  if ((p->desc.flags & CS_FLAG_GRAPH) && !p->timing && iters > 0)
+    return run_phase_graph(p, iters, lambda, mu, J_trace, wgiven, s);
+  return run_phase_loop(p, iters, lambda, mu, J_trace, wgiven, s);
+}
+
+static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
                           const float2* wgiven, hipStream_t s) {
   const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
   int st = CS_OK;
@@ -234,6 +288,33 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
       hpsi[(size_t)f * nt + t] =
           make_float2((float)(std::cos(ang) / std::sqrt((double)nt)), (float)(std::sin(ang) / std::sqrt((double)nt)));
     }
+  // MFMA fragments of the real 2x2-block embedding of Psi (and of Psi'):
+  // Psihat[2f + a][2t + b] = [[Re P, -Im P], [Im P, Re P]], P = Psi[f][t],
+  // padded to KP = 2 nt rounded up to 16; Psihat' is its transpose.  Lane l of
+  // fragment (m, k) holds A[16 m + l % 16][4 k + l / 16].
+  const int kp = (2 * nt + 15) / 16 * 16;
+  const int kmt = kp / 16, kks = kp / 4;
+  std::vector<float> hfrag((size_t)2 * kmt * kks * 64, 0.f);
+  {
+    std::vector<double> E((size_t)kp * kp, 0.0);
+    for (int f = 0; f < nt; ++f)
+      for (int t = 0; t < nt; ++t) {
+        const double ang = -2.0 * M_PI * (double)((f * t) % nt) / nt, sc = 1.0 / std::sqrt((double)nt);
+        const double re = std::cos(ang) * sc, im = std::sin(ang) * sc;
+        E[(size_t)(2 * f) * kp + 2 * t] = re;
+        E[(size_t)(2 * f) * kp + 2 * t + 1] = -im;
+        E[(size_t)(2 * f + 1) * kp + 2 * t] = im;
+        E[(size_t)(2 * f + 1) * kp + 2 * t + 1] = re;
+      }
+    for (int mat = 0; mat < 2; ++mat)
+      for (int mm = 0; mm < kmt; ++mm)
+        for (int kk = 0; kk < kks; ++kk)
+          for (int l = 0; l < 64; ++l) {
+            const int r = 16 * mm + l % 16, c = 4 * kk + l / 16;
+            const double val = mat == 0 ? E[(size_t)r * kp + c] : E[(size_t)c * kp + r];
+            hfrag[(size_t)mat * kmt * kks * 64 + ((size_t)mm * kks + kk) * 64 + l] = (float)val;
+          }
+  }
   // Thomas pivots of rho I + D'D: den_0 = b_0, den_t = b_t - 1/den_{t-1}
   std::vector<float> hinv(nt, 0.f);
   if (desc->prior == CS_PRIOR_TEMPORAL_TV) {
@@ -254,6 +335,7 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
       (st = plan_alloc(p, &p->tw_v, (size_t)nv, "tw_v")) ||
       (st = plan_alloc(p, &p->tw_h, (size_t)nh, "tw_h")) ||
       (st = plan_alloc(p, &p->psi_t, hpsi.size(), "psi")) ||
+      (st = plan_alloc(p, &p->dft_frags, hfrag.size(), "psi fragments")) ||
       (st = plan_alloc(p, &p->tv_invden, (size_t)nt, "tv_invden")) ||
       (st = plan_alloc(p, &p->coil_cm, npix * nc, "coil")) ||
       (st = plan_alloc(p, &p->ktmp, ksz, "ktmp")) ||
@@ -280,6 +362,7 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
   UP(p->tw_v, htwv.data(), htwv.size() * sizeof(float2));
   UP(p->tw_h, htwh.data(), htwh.size() * sizeof(float2));
   UP(p->psi_t, hpsi.data(), hpsi.size() * sizeof(float2));
+  UP(p->dft_frags, hfrag.data(), hfrag.size() * sizeof(float));
   UP(p->tv_invden, hinv.data(), hinv.size() * sizeof(float));
 #undef UP
   // coil maps [c][j][i] -> column-major [c][i][j]
@@ -312,8 +395,8 @@ int cs_kernel_timing(cs_plan* plan, int enable) {
 int cs_kernel_times(cs_plan* plan, cs_kernel_time* out, int max, int* count) {
   if (!plan || !count || (max > 0 && !out)) return set_error(CS_EINVAL, "plan, out and count must not be NULL");
   CS_HIP(hipSetDevice(plan->device));
-  double ms[kKinds] = {0, 0, 0, 0};
-  int n[kKinds] = {0, 0, 0, 0};
+  double ms[kKinds] = {};
+  int n[kKinds] = {};
   for (const auto& t : plan->timed) {
     CS_HIP(hipEventSynchronize(t.stop));
     float e = 0.f;

@@ -18,12 +18,14 @@ namespace csmri {
 __host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// complex products with explicit FMAs (the library is built without implicit
+// contraction, so these round identically in every kernel)
 __host__ __device__ inline float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 // conj(a) * b
 __host__ __device__ inline float2 cmulc(float2 a, float2 b) {
-  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.x, b.y, -(a.y * b.x)));
 }
 // acc + a * b
 __host__ __device__ inline float2 cfma(float2 a, float2 b, float2 acc) {
@@ -43,7 +45,7 @@ __host__ __device__ inline float2 cfmac(float2 a, float2 b, float2 acc) {
 }
 __host__ __device__ inline double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline double2 zmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
 __host__ __device__ inline double2 zfma(double2 a, double2 b, double2 acc) {
   acc.x = fma(a.x, b.x, acc.x);
@@ -61,13 +63,13 @@ __host__ __device__ inline double2 zfms(double2 a, double2 b, double2 acc) {
   return acc;
 }
 __host__ __device__ inline double2 zrecip(double2 a) {
-  double d = a.x * a.x + a.y * a.y;
+  double d = fma(a.x, a.x, a.y * a.y);
   return make_double2(a.x / d, -a.y / d);
 }
 
 // Complex soft threshold: (|a| - tau) a / |a| if |a| > tau, else 0.
 __device__ inline float2 soft_threshold(float2 a, float tau) {
-  float mag = sqrtf(a.x * a.x + a.y * a.y);
+  float mag = sqrtf(fmaf(a.x, a.x, a.y * a.y));
   if (!(mag > tau)) return make_float2(0.f, 0.f);
   float s = (mag - tau) / mag;
   return make_float2(a.x * s, a.y * s);
@@ -155,6 +157,7 @@ struct cs_plan {
   float2* tw_v = nullptr;       // exp(-2 pi i q / nv), q < nv
   float2* tw_h = nullptr;
   float2* psi_t = nullptr;      // [nt][nt] unitary temporal DFT matrix (DFT prior)
+  float* dft_frags = nullptr;   // MFMA A-operand fragments of the embedded Psi and Psi' (DFT prior)
   float* tv_invden = nullptr;   // [nt] Thomas coefficients of (rho I + D'D)
 
   // coil maps in the solver's column-major layout [c][i][j]
@@ -178,6 +181,7 @@ struct cs_plan {
 
   hipGraphExec_t graph = nullptr;  // cached iteration graph
   void* graph_key[8] = {};
+  hipStream_t capture_stream = nullptr;  // private stream used only to record graphs
 
   // per-kernel event timing (cs_kernel_timing)
   bool timing = false;
@@ -212,6 +216,9 @@ int launch_dft_step(cs_plan* p, float lambda, float mu, int first, const float2*
 int launch_dft_apply(cs_plan* p, const float2* in, float2* out, float2* dual, const float2* v, int adjoint,
                      hipStream_t s);
 int launch_fill(float2* ptr, size_t n, float2 v, hipStream_t s);
+// all iterations in one launch, one workgroup per readout column (even nv)
+bool column_solve_supported(const cs_plan* p);
+int launch_column_solve(cs_plan* p, int iters, float lambda, float mu, const float2* wgiven, hipStream_t s);
 int launch_objective(cs_plan* p, const float2* x, float lambda, float* out, hipStream_t s);
 
 enum BlockSolveMode { kSolvePlain = 0, kSolveTV = 1, kSolveDFT = 2 };

@@ -46,9 +46,11 @@ __device__ inline float2 rhs_value(const float2* hy, const float2* m, const floa
   return make_float2(fmaf(mu, u.x, h.x), fmaf(mu, u.y, h.y));
 }
 
-// Even n: lane l owns rows 2l and 2l+1 and streams each diagonal as one
-// 16-byte load per lane.  The rotated values c_s[k-s] belong to other lanes;
-// UNR diagonals at a time are staged in LDS and read back rotated.
+// Pair form (even n, one block per workgroup of round_up(n/2, 64) lanes):
+// lane l owns rows 2l and 2l+1 and streams each diagonal as one 16-byte load;
+// UNR diagonals at a time are staged in LDS behind workgroup barriers.  Used
+// when n/2 is not a multiple of 64, where the wave-per-block form below would
+// leave part of a wave idle on every load.
 template <int MODE, int UNR>
 __global__ __launch_bounds__(256) void k_xupdate_pairs(const float2* __restrict__ W, FactorLayout L,
                                                        const float2* hy, const float2* __restrict__ m,
@@ -115,6 +117,133 @@ __global__ __launch_bounds__(256) void k_xupdate_pairs(const float2* __restrict_
   }
 }
 
+// Wave-per-block form (even n): one wave solves a block alone, so no
+// workgroup barrier is needed.  Lane l owns the row pairs (2q, 2q+1),
+// q = l + 64 r, r < RP; each diagonal is one 16-byte non-temporal load per
+// pair.  Diagonals are handled UNR at a time through wave-private LDS (the
+// rotated operand c_s[k-s] of the Hermitian mirror belongs to another lane),
+// and the next UNR diagonals are already in flight while the current ones
+// are staged and multiplied (two register buffers, alternated by hand so
+// that no copy forces an early wait).  LDS needs (1 + UNR) n values.
+template <int UNR, int RP>
+struct DiagChunk {
+  float4 c[UNR][RP];
+};
+
+template <int UNR, int RP>
+__device__ inline void load_chunk(DiagChunk<UNR, RP>& ch, const float2* __restrict__ W, const FactorLayout& L,
+                                  size_t blk, int s0, int lane) {
+  const int h = L.n >> 1;
+#pragma unroll
+  for (int u = 0; u < UNR; ++u)
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int q = lane + 64 * r;
+      ch.c[u][r] = (q < h && s0 + u < L.F) ? ld_stream4(W + diag_offset(L, blk, s0 + u) + 2 * q)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+template <int UNR, int RP>
+__device__ inline void apply_chunk(const DiagChunk<UNR, RP>& ch, const FactorLayout& L, int s0, int lane,
+                                   const float2* bsh, float2* dsh, float2 (&a0)[RP], float2 (&a1)[RP]) {
+  const int n = L.n, h = n >> 1;
+#pragma unroll
+  for (int u = 0; u < UNR; ++u)
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int q = lane + 64 * r;
+      if (q < h) *reinterpret_cast<float4*>(dsh + u * n + 2 * q) = ch.c[u][r];
+    }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int u = 0; u < UNR; ++u) {
+    const int s = s0 + u;
+    if (s < L.F) {
+      const float2* d = dsh + u * n;
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        const int q = lane + 64 * r;
+        if (q < h) {
+          const int k0 = 2 * q, k1 = 2 * q + 1;
+          int p0 = k0 + s, p1 = k1 + s, q0 = k0 - s, q1 = k1 - s;
+          p0 -= p0 >= n ? n : 0;
+          p1 -= p1 >= n ? n : 0;
+          q0 += q0 < 0 ? n : 0;
+          q1 += q1 < 0 ? n : 0;
+          a0[r] = cfma(make_float2(ch.c[u][r].x, ch.c[u][r].y), bsh[p0], a0[r]);
+          a1[r] = cfma(make_float2(ch.c[u][r].z, ch.c[u][r].w), bsh[p1], a1[r]);
+          a0[r] = cfmac(d[q0], bsh[q0], a0[r]);
+          a1[r] = cfmac(d[q1], bsh[q1], a1[r]);
+        }
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int MODE, int UNR, int RP>
+__device__ inline void xupdate_wave_block(const float2* __restrict__ W, const FactorLayout& L, size_t blk, int lane,
+                                          float2* bsh, float2* dsh, const float2* hy, const float2* __restrict__ m,
+                                          float2* __restrict__ d2, float2* x, float mu) {
+  const int n = L.n, h = n >> 1, F = L.F;
+  const size_t base = blk * (size_t)n;
+  DiagChunk<UNR, RP> A, B;
+  if (F > 1) load_chunk<UNR, RP>(A, W, L, blk, 1, lane);
+  float2 b0[RP], b1[RP], m0[RP], m1[RP], e0[RP], e1[RP], a0[RP], a1[RP];
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int q = lane + 64 * r;
+    b0[r] = b1[r] = m0[r] = m1[r] = e0[r] = e1[r] = a0[r] = a1[r] = make_float2(0.f, 0.f);
+    if (q < h) {
+      b0[r] = rhs_value<MODE>(hy, m, d2, base + 2 * q, mu, m0[r], e0[r]);
+      b1[r] = rhs_value<MODE>(hy, m, d2, base + 2 * q + 1, mu, m1[r], e1[r]);
+      const float4 c = ld_stream4(W + diag_offset(L, blk, 0) + 2 * q);
+      a0[r] = cmul(make_float2(c.x, c.y), b0[r]);
+      a1[r] = cmul(make_float2(c.z, c.w), b1[r]);
+    }
+  }
+  // a previous block's epilogue of this wave may still be reading bsh; the
+  // wave executes in order, so a compiler barrier is all that is needed
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int q = lane + 64 * r;
+    if (q < h) *reinterpret_cast<float4*>(bsh + 2 * q) = make_float4(b0[r].x, b0[r].y, b1[r].x, b1[r].y);
+  }
+  __builtin_amdgcn_wave_barrier();
+  for (int s0 = 1; s0 < F; s0 += 2 * UNR) {
+    if (s0 + UNR < F) load_chunk<UNR, RP>(B, W, L, blk, s0 + UNR, lane);
+    apply_chunk<UNR, RP>(A, L, s0, lane, bsh, dsh, a0, a1);
+    if (s0 + 2 * UNR < F) load_chunk<UNR, RP>(A, W, L, blk, s0 + 2 * UNR, lane);
+    if (s0 + UNR < F) apply_chunk<UNR, RP>(B, L, s0 + UNR, lane, bsh, dsh, a0, a1);
+  }
+  const float2* hd = W + half_offset(L, blk);
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int q = lane + 64 * r;
+    if (q < h) {
+      const int k0 = 2 * q, k1 = 2 * q + 1;
+      a0[r] = k0 < h ? cfma(hd[k0], bsh[k0 + h], a0[r]) : cfmac(hd[k0 - h], bsh[k0 - h], a0[r]);
+      a1[r] = k1 < h ? cfma(hd[k1], bsh[k1 + h], a1[r]) : cfmac(hd[k1 - h], bsh[k1 - h], a1[r]);
+      *reinterpret_cast<float4*>(x + base + k0) = make_float4(a0[r].x, a0[r].y, a1[r].x, a1[r].y);
+      if (MODE == kSolveTV)
+        *reinterpret_cast<float4*>(d2 + base + k0) =
+            make_float4(e0[r].x - (m0[r].x - a0[r].x), e0[r].y - (m0[r].y - a0[r].y),
+                        e1[r].x - (m1[r].x - a1[r].x), e1[r].y - (m1[r].y - a1[r].y));
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int MODE, int UNR, int RP>
+__global__ __launch_bounds__(64) void k_xupdate_wave(const float2* __restrict__ W, FactorLayout L, const float2* hy,
+                                                     const float2* __restrict__ m, float2* __restrict__ d2, float2* x,
+                                                     float mu) {
+  extern __shared__ float2 lds[];
+  xupdate_wave_block<MODE, UNR, RP>(W, L, blockIdx.x, threadIdx.x, lds, lds + L.n, hy, m, d2, x, mu);
+}
+
 // Odd n: lane k owns row k; the rotated c_s[k-s] is re-read from the same
 // diagonal run, which the vector cache serves.
 template <int MODE>
@@ -148,23 +277,41 @@ __global__ __launch_bounds__(512) void k_xupdate_rows(const float2* __restrict__
   if (MODE == kSolveTV) d2[base + k] = make_float2(dk.x - (mk.x - acc.x), dk.y - (mk.y - acc.y));
 }
 
-constexpr int kXUnroll = 8;
+constexpr int kXUnroll = 8;   // diagonals per chunk, phase-form x-update
+constexpr int kXUnrollCol = 4;  // diagonals per chunk, column-resident solve (8 waves share a CU's LDS)
+
+// row pairs per lane: nv/2 pairs over 64 lanes
+inline int pairs_per_lane(int n) { return ((n >> 1) + 63) / 64; }
+
+template <int MODE, int RP>
+static void xupdate_wave_launch(cs_plan* p, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
+                                hipStream_t s) {
+  const FactorLayout& L = p->flayout;
+  constexpr int UNR = RP <= 2 ? kXUnroll : kXUnroll / 2;
+  const size_t lds = (size_t)(1 + UNR) * L.n * sizeof(float2);
+  hipLaunchKernelGGL((k_xupdate_wave<MODE, UNR, RP>), dim3((unsigned)L.nblk), dim3(64), lds, s, p->factor, L, hy,
+                     m, d2, x, mu);
+}
 
 template <int MODE>
 static void xupdate_launch(cs_plan* p, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
                            hipStream_t s) {
   const FactorLayout& L = p->flayout;
   const int n = L.n;
-  const unsigned nblk = (unsigned)L.nblk;
-  if ((n & 1) == 0) {
+  if ((n & 1) == 0 && (n / 2) % 64 == 0) {
+    const int rp = pairs_per_lane(n);
+    if (rp == 1) xupdate_wave_launch<MODE, 1>(p, hy, m, d2, x, mu, s);
+    else if (rp == 2) xupdate_wave_launch<MODE, 2>(p, hy, m, d2, x, mu, s);
+    else xupdate_wave_launch<MODE, 4>(p, hy, m, d2, x, mu, s);
+  } else if ((n & 1) == 0) {
     const int wg = (std::max(n / 2, 1) + 63) / 64 * 64;
     const size_t lds = (size_t)(1 + kXUnroll) * n * sizeof(float2);
-    hipLaunchKernelGGL((k_xupdate_pairs<MODE, kXUnroll>), dim3(nblk), dim3(wg), lds, s, p->factor, L, hy, m, d2,
-                       x, mu);
+    hipLaunchKernelGGL((k_xupdate_pairs<MODE, kXUnroll>), dim3((unsigned)L.nblk), dim3(wg), lds, s, p->factor, L,
+                       hy, m, d2, x, mu);
   } else {
     const int wg = (n + 63) / 64 * 64;
-    hipLaunchKernelGGL(k_xupdate_rows<MODE>, dim3(nblk), dim3(wg), (size_t)n * sizeof(float2), s, p->factor, L,
-                       hy, m, d2, x, mu);
+    hipLaunchKernelGGL(k_xupdate_rows<MODE>, dim3((unsigned)L.nblk), dim3(wg), (size_t)n * sizeof(float2), s,
+                       p->factor, L, hy, m, d2, x, mu);
   }
 }
 
@@ -192,11 +339,9 @@ int launch_block_solve(cs_plan* p, int mode, const float2* hy, const float2* m, 
 // arithmetic so that all its loads are in flight together: a 256x256 image
 // has only one wave per SIMD, so latency has to be hidden inside the wave.
 template <int NT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tv_step(
-    float2* __restrict__ m, float2* __restrict__ d1, const float2* __restrict__ x, const float2* __restrict__ d2,
-    const float* __restrict__ invden, int nt, size_t npix, float tau, float rho) {
-  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npix) return;
+__device__ inline void tv_pixel(float2* __restrict__ m, float2* __restrict__ d1, const float2* __restrict__ x,
+                                const float2* __restrict__ d2, const float* __restrict__ invden, int nt,
+                                size_t npix, size_t p, float tau, float rho) {
   float2 M[NT], E[NT], R[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -247,6 +392,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 }
 
 template <int NT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tv_step(
+    float2* __restrict__ m, float2* __restrict__ d1, const float2* __restrict__ x, const float2* __restrict__ d2,
+    const float* __restrict__ invden, int nt, size_t npix, float tau, float rho) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < npix) tv_pixel<NT>(m, d1, x, d2, invden, nt, npix, p, tau, rho);
+}
+
+template <int NT>
 static void tv_launch(cs_plan* p, float tau, float rho, hipStream_t s) {
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
   hipLaunchKernelGGL(k_tv_step<NT>, dim3((unsigned)((npix + 63) / 64)), dim3(64), 0, s, p->s0, p->s1, p->s2,
@@ -284,105 +437,230 @@ int launch_tv_step(cs_plan* p, float lambda, float mu, hipStream_t s) {
 // On a warm start the saved w is passed as `wgiven` and used as is on the
 // first pass (it is the value an uninterrupted run computes there), so a
 // resumed solve reproduces the uninterrupted one bit for bit.
-template <int NT>
-__global__ __launch_bounds__(256) void k_dft_step(const float2* __restrict__ z, float2* __restrict__ d,
-                                                  float2* __restrict__ v, float2* __restrict__ u,
-                                                  const float2* __restrict__ psi,
-                                                  const float2* __restrict__ wgiven, int nt, size_t npix,
-                                                  float tau, int first) {
-  __shared__ float2 ps[NT * NT];
-  for (int q = threadIdx.x; q < nt * nt; q += blockDim.x) ps[q] = psi[q];
-  __syncthreads();
-  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npix) return;
-  float2 zz[NT], uu[NT];
+// ---------------------------------------------------------------- temporal DFT on MFMA
+//
+// The temporal DFT of 16 pixels at a time is a dense real contraction: with a
+// complex series written as interleaved real rows (re z_t, im z_t), w = Psi z
+// becomes What = Psihat zhat, Psihat the real 2x2-block embedding
+//   [[Re P, -Im P], [Im P, Re P]]  of every entry P = Psi[f][t],
+// of size 2 nt x 2 nt (zero-padded to KP = a multiple of 16).  One wave runs it
+// as (KP/16) x (KP/4) v_mfma_f32_16x16x4f32 steps: A = a 16x4 block of Psihat
+// (lane l holds A[l % 16][l / 16]), B = 4 rows x 16 pixels of zhat staged in
+// LDS (lane l holds B[l / 16][l % 16]), accumulator lane l holds
+// D[4 (l / 16) + v][l % 16], v < 4, i.e. the real and imaginary parts of two
+// consecutive frequencies of pixel l % 16.  The A fragments of Psihat and of
+// Psihat' (adjoint) are built on the host in FP64 and held in LDS.
+
+typedef float mfma_v4 __attribute__((ext_vector_type(4)));
+
+template <int KP>
+struct DftTile {
+  static constexpr int MT = KP / 16;  // 16-row output tiles
+  static constexpr int KS = KP / 4;   // 4-deep contraction steps
+  static constexpr int FRAG = MT * KS * 64;  // floats per matrix
+};
+
+// acc[m] = sum_k Ahat(m, k) Bhat(k), Bhat = tile[KP][16] in LDS
+template <int KP>
+__device__ inline void tile_gemm(const float* __restrict__ frag, const float* tile, int lane,
+                                 mfma_v4 (&acc)[DftTile<KP>::MT]) {
+  constexpr int MT = DftTile<KP>::MT, KS = DftTile<KP>::KS;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    zz[t] = (t < nt && !wgiven) ? z[(size_t)t * npix + p] : make_float2(0.f, 0.f);
-    uu[t] = make_float2(0.f, 0.f);
+  for (int m = 0; m < MT; ++m) acc[m] = mfma_v4{0.f, 0.f, 0.f, 0.f};
+  const int col = lane & 15, grp = lane >> 4;
+#pragma unroll 4
+  for (int k = 0; k < KS; ++k) {
+    const float b = tile[(4 * k + grp) * 16 + col];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(m * KS + k) * 64 + lane], b, acc[m], 0, 0, 0);
   }
-#pragma unroll
-  for (int f = 0; f < NT; ++f) {
-    if (f < nt) {
-      const float2* row = ps + f * nt;
-      float2 w = make_float2(0.f, 0.f);
-      if (wgiven) {
-        w = wgiven[(size_t)f * npix + p];
-      } else {
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (t < nt) w = cfma(row[t], zz[t], w);
-      }
-      float2 df = d[(size_t)f * npix + p];
-      if (!first) {
-        const float2 vp = v[(size_t)f * npix + p];
-        df = make_float2(df.x - (w.x - vp.x), df.y - (w.y - vp.y));
-      }
-      const float2 vf = soft_threshold(csub(w, df), tau);
-      d[(size_t)f * npix + p] = df;
-      v[(size_t)f * npix + p] = vf;
-      const float2 q = cadd(vf, df);
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-        if (t < nt) uu[t] = cfmac(row[t], q, uu[t]);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-    if (t < nt) u[(size_t)t * npix + p] = uu[t];
 }
 
-// out = Psi in (adjoint = 0) or Psi' in (adjoint = 1); with dual != nullptr
-// (forward only) also completes the deferred dual update d <- d - (out - v).
-template <int NT>
-__global__ __launch_bounds__(256) void k_dft_apply(const float2* __restrict__ in, float2* __restrict__ out,
-                                                   float2* __restrict__ dual, const float2* __restrict__ v,
-                                                   const float2* __restrict__ psi, int nt, size_t npix,
-                                                   int adjoint) {
-  __shared__ float2 ps[NT * NT];
-  for (int q = threadIdx.x; q < nt * nt; q += blockDim.x) ps[q] = psi[q];
-  __syncthreads();
-  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npix) return;
-  float2 a[NT];
+// stage 16 pixels' series (rows 2t, 2t+1 = re, im of frame t) into tile[KP][16]
+template <int KP>
+__device__ inline void tile_stage(float* tile, const float2* __restrict__ src, int nt, size_t npix, size_t p0,
+                                  int count, int lane) {
+  const int col = lane & 15, grp = lane >> 4;
+  for (int t = grp; t < KP / 2; t += 4) {
+    const float2 a = (t < nt && col < count) ? src[(size_t)t * npix + p0 + col] : make_float2(0.f, 0.f);
+    tile[(2 * t) * 16 + col] = a.x;
+    tile[(2 * t + 1) * 16 + col] = a.y;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+enum DftTileMode { kDftStep = 0, kDftForward = 1, kDftAdjoint = 2 };
+
+// One wave, pixels p0 .. p0 + count - 1 (count <= 16), frame stride npix.
+//   kDftStep:    w = Psi z (or w = wgiven); d <- d - (w - v) unless first;
+//                v <- soft(w - d, tau); u <- Psi'(v + d).  Writes d, v, u.
+//   kDftForward: out = Psi in; with dual != null also dual <- dual - (out - v).
+//   kDftAdjoint: out = Psi' in.
+template <int KP, int MODE>
+__device__ inline void dft_tile(const float* __restrict__ fragF, const float* __restrict__ fragH, float* tile,
+                                const float2* __restrict__ in, float2* __restrict__ d, float2* __restrict__ v,
+                                float2* __restrict__ out, const float2* __restrict__ wgiven, int nt, size_t npix,
+                                size_t p0, int count, float tau, int first, int lane) {
+  constexpr int MT = DftTile<KP>::MT;
+  const int col = lane & 15, grp = lane >> 4;
+  const bool pv = col < count;
+  const size_t p = p0 + col;
+  mfma_v4 acc[MT];
+  if (MODE == kDftStep && wgiven) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) a[t] = t < nt ? in[(size_t)t * npix + p] : make_float2(0.f, 0.f);
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-  for (int f = 0; f < NT; ++f) {
-    if (f < nt) {
-      float2 acc = make_float2(0.f, 0.f);
+      for (int h = 0; h < 2; ++h) {
+        const int f = 8 * m + 2 * grp + h;
+        const float2 w = (f < nt && pv) ? wgiven[(size_t)f * npix + p] : make_float2(0.f, 0.f);
+        acc[m][2 * h] = w.x;
+        acc[m][2 * h + 1] = w.y;
+      }
+  } else {
+    tile_stage<KP>(tile, in, nt, npix, p0, count, lane);
+    tile_gemm<KP>(MODE == kDftAdjoint ? fragH : fragF, tile, lane, acc);
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (MODE != kDftStep) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        if (t < nt) {
-          // Psi[f][t] is symmetric in (f, t); Psi'[f][t] = conj(Psi[t][f]) = conj(Psi[f][t])
-          acc = adjoint ? cfmac(ps[f * nt + t], a[t], acc) : cfma(ps[f * nt + t], a[t], acc);
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int f = 8 * m + 2 * grp + h;
+        if (f < nt && pv) {
+          const float2 w = make_float2(acc[m][2 * h], acc[m][2 * h + 1]);
+          out[(size_t)f * npix + p] = w;
+          if (MODE == kDftForward && d) {
+            const float2 vf = v[(size_t)f * npix + p];
+            const float2 df = d[(size_t)f * npix + p];
+            d[(size_t)f * npix + p] = make_float2(df.x - (w.x - vf.x), df.y - (w.y - vf.y));
+          }
         }
       }
-      out[(size_t)f * npix + p] = acc;
-      if (dual) {
-        const float2 vf = v[(size_t)f * npix + p];
-        float2 df = dual[(size_t)f * npix + p];
-        dual[(size_t)f * npix + p] = make_float2(df.x - (acc.x - vf.x), df.y - (acc.y - vf.y));
+    return;
+  }
+  // dual update, shrinkage and q = v + d, written back as the rows of qhat
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int f = 8 * m + 2 * grp + h;
+      const int row = 16 * m + 4 * grp + 2 * h;
+      float2 q = make_float2(0.f, 0.f);
+      if (f < nt && pv) {
+        const float2 w = make_float2(acc[m][2 * h], acc[m][2 * h + 1]);
+        float2 df = d[(size_t)f * npix + p];
+        if (!first) {
+          const float2 vp = v[(size_t)f * npix + p];
+          df = make_float2(df.x - (w.x - vp.x), df.y - (w.y - vp.y));
+        }
+        const float2 vf = soft_threshold(csub(w, df), tau);
+        d[(size_t)f * npix + p] = df;
+        v[(size_t)f * npix + p] = vf;
+        q = cadd(vf, df);
       }
+      tile[row * 16 + col] = q.x;
+      tile[(row + 1) * 16 + col] = q.y;
     }
+  __builtin_amdgcn_wave_barrier();
+  tile_gemm<KP>(fragH, tile, lane, acc);
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = 8 * m + 2 * grp + h;
+      if (t < nt && pv) out[(size_t)t * npix + p] = make_float2(acc[m][2 * h], acc[m][2 * h + 1]);
+    }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// copy both fragment matrices into LDS (all threads of the workgroup)
+template <int KP>
+__device__ inline void load_frags(float* dst, const float* __restrict__ src) {
+  for (int q = threadIdx.x; q < 2 * DftTile<KP>::FRAG; q += blockDim.x) dst[q] = src[q];
+}
+
+// phase-kernel form: blockDim/64 waves per workgroup, pixel tiles of 16 in a grid-stride loop
+template <int KP, int MODE>
+__global__ __launch_bounds__(256) void k_dft_tiles(const float* __restrict__ frags, const float2* __restrict__ in,
+                                                   float2* __restrict__ d, float2* __restrict__ v,
+                                                   float2* __restrict__ out, const float2* __restrict__ wgiven,
+                                                   int nt, size_t npix, float tau, int first) {
+  extern __shared__ float lds_f[];
+  float* fF = lds_f;
+  float* fH = lds_f + DftTile<KP>::FRAG;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float* tile = lds_f + 2 * DftTile<KP>::FRAG + wv * KP * 16;
+  load_frags<KP>(lds_f, frags);
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  const size_t ntiles = (npix + 15) / 16;
+  for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
+    const size_t p0 = tl * 16;
+    const int count = (int)std::min<size_t>(16, npix - p0);
+    dft_tile<KP, MODE>(fF, fH, tile, in, d, v, out, wgiven, nt, npix, p0, count, tau, first, lane);
   }
 }
 
-template <int NT>
-static void dft_step_launch(cs_plan* p, float tau, int first, const float2* wgiven, hipStream_t s) {
-  const size_t npix = (size_t)p->desc.nv * p->desc.nh;
-  hipLaunchKernelGGL(k_dft_step<NT>, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, p->s2, p->s0,
-                     p->s1, p->s3, p->psi_t, wgiven, p->desc.nt, npix, tau, first);
+// padded real dimension of the embedded temporal DFT: 2 nt rounded up to 16
+inline int dft_kp(int nt) { return (2 * nt + 15) / 16 * 16; }
+
+// waves per workgroup of the phase kernels: the fragments of both matrices
+// (8 KP^2 bytes) and one KP x 16 tile per wave must fit in LDS
+inline int dft_waves(int kp) { return kp <= 96 ? 4 : 2; }
+
+inline size_t dft_lds_bytes(int kp, int waves) {
+  return ((size_t)2 * (kp / 16) * (kp / 4) * 64 + (size_t)waves * kp * 16) * sizeof(float);
 }
 
-template <int NT>
-static void dft_apply_launch(cs_plan* p, const float2* in, float2* out, float2* dual, const float2* v,
-                             int adjoint, hipStream_t s) {
+template <int KP, int MODE>
+static int dft_tiles_launch(cs_plan* p, const float2* in, float2* d, float2* v, float2* out, const float2* wgiven,
+                            float tau, int first, hipStream_t s) {
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
-  hipLaunchKernelGGL(k_dft_apply<NT>, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, in, out, dual,
-                     v, p->psi_t, p->desc.nt, npix, adjoint);
+  const int waves = dft_waves(KP);
+  const size_t lds = dft_lds_bytes(KP, waves);
+  static bool attr = false;
+  if (lds > 65536 && !attr) {
+    CS_HIP(hipFuncSetAttribute((const void*)k_dft_tiles<KP, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    attr = true;
+  }
+  const size_t ntiles = (npix + 15) / 16;
+  const unsigned grid = (unsigned)std::min<size_t>((ntiles + waves - 1) / waves, 512);
+  hipLaunchKernelGGL((k_dft_tiles<KP, MODE>), dim3(grid), dim3(64 * waves), lds, s, p->dft_frags, in, d, v, out,
+                     wgiven, p->desc.nt, npix, tau, first);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
 }
 
+template <int MODE>
+static int dft_tiles_dispatch(cs_plan* p, const float2* in, float2* d, float2* v, float2* out,
+                              const float2* wgiven, float tau, int first, hipStream_t s) {
+  switch (dft_kp(p->desc.nt)) {
+    case 16: return dft_tiles_launch<16, MODE>(p, in, d, v, out, wgiven, tau, first, s);
+    case 32: return dft_tiles_launch<32, MODE>(p, in, d, v, out, wgiven, tau, first, s);
+    case 48: return dft_tiles_launch<48, MODE>(p, in, d, v, out, wgiven, tau, first, s);
+    case 64: return dft_tiles_launch<64, MODE>(p, in, d, v, out, wgiven, tau, first, s);
+    case 80: return dft_tiles_launch<80, MODE>(p, in, d, v, out, wgiven, tau, first, s);
+    case 96: return dft_tiles_launch<96, MODE>(p, in, d, v, out, wgiven, tau, first, s);
+    case 112: return dft_tiles_launch<112, MODE>(p, in, d, v, out, wgiven, tau, first, s);
+    default: return dft_tiles_launch<128, MODE>(p, in, d, v, out, wgiven, tau, first, s);
+  }
+}
+
+int launch_dft_step(cs_plan* p, float lambda, float mu, int first, const float2* wgiven, hipStream_t s) {
+  const float tau = lambda / (2.0f * mu);
+  return dft_tiles_dispatch<kDftStep>(p, p->s2, p->s0, p->s1, p->s3, wgiven, tau, first, s);
+}
+
+int launch_dft_apply(cs_plan* p, const float2* in, float2* out, float2* dual, const float2* v, int adjoint,
+                     hipStream_t s) {
+  if (adjoint) return dft_tiles_dispatch<kDftAdjoint>(p, in, nullptr, nullptr, out, nullptr, 0.f, 0, s);
+  return dft_tiles_dispatch<kDftForward>(p, in, dual, const_cast<float2*>(v), out, nullptr, 0.f, 0, s);
+}
+
+// Frame-count instantiations of the remaining per-pixel kernel (objective).
 #define CS_DISPATCH_NT(nt, FN, ...)            \
   do {                                         \
     if ((nt) <= 8) FN<8>(__VA_ARGS__);         \
@@ -394,18 +672,152 @@ static void dft_apply_launch(cs_plan* p, const float2* in, float2* out, float2* 
     else FN<64>(__VA_ARGS__);                  \
   } while (0)
 
-int launch_dft_step(cs_plan* p, float lambda, float mu, int first, const float2* wgiven, hipStream_t s) {
-  const float tau = lambda / (2.0f * mu);
-  CS_DISPATCH_NT(p->desc.nt, dft_step_launch, p, tau, first, wgiven, s);
+// ---------------------------------------------------------------- column-resident solve
+//
+// Temporal priors never couple readout columns: the temporal step couples the
+// frames of one pixel and the x-update the rows of one (column, frame) block.
+// Every column is therefore an independent ADMM problem for all iterations
+// (the paper's remark that the reconstruction separates along the horizontal
+// axis, Sec. V), and one workgroup can own column i for the whole solve:
+//   repeat iters times:
+//     temporal step (TV or DFT) for the nv pixels of column i
+//     x-update of the nt blocks (t, i), ngroups blocks at a time
+// with only workgroup barriers between the phases -- no grid-wide
+// synchronisation and no per-iteration launch.  The per-column state stays
+// in L2 / the memory-side cache while the factor streams past it with
+// non-temporal loads.
+struct ColumnSolveArgs {
+  const float2* W;
+  FactorLayout L;
+  const float2* hy;
+  float2 *s0, *s1, *s2, *s3;
+  const float* invden;
+  const float* dft_frags;
+  const float2* wgiven;  // DFT warm start: w for the first pass, or null
+  int nh, nt, iters;
+  int wave_floats;       // LDS floats per wave
+  float mu, tau, rho;
+};
+
+// MAXT: 512 threads (two waves per SIMD) while the temporal step fits in
+// 256 VGPRs (up to 40 frames), 256 threads beyond
+// NT: TV frame-count bound; for the DFT prior the padded embedding size KP.
+// Per-wave LDS: `wave_floats` floats (x-update staging, reused as the DFT
+// tile), then the DFT fragments of both matrices.
+template <int PRIOR, int NT, int RP, int MAXT = (PRIOR == CS_PRIOR_TEMPORAL_TV && NT > 40 ? 256 : 512)>
+__global__ __launch_bounds__(MAXT) void k_column_solve(ColumnSolveArgs a) {
+  extern __shared__ float2 lds[];
+  const int n = a.L.n;
+  const int nwaves = blockDim.x >> 6;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float2* bsh = lds + (size_t)w * (a.wave_floats / 2);
+  float2* dsh = bsh + n;
+  float* frags = reinterpret_cast<float*>(lds + (size_t)nwaves * (a.wave_floats / 2));
+  if constexpr (PRIOR == CS_PRIOR_TEMPORAL_DFT) {
+    load_frags<NT>(frags, a.dft_frags);
+    __syncthreads();
+  }
+  const int i = blockIdx.x;
+  const size_t npix = (size_t)n * a.nh;
+  for (int k = 0; k < a.iters; ++k) {
+    if constexpr (PRIOR == CS_PRIOR_TEMPORAL_TV) {
+      for (int j = threadIdx.x; j < n; j += blockDim.x)
+        tv_pixel<NT>(a.s0, a.s1, a.s2, a.s3, a.invden, a.nt, npix, (size_t)i * n + j, a.tau, a.rho);
+    } else {
+      for (int tl = w; tl * 16 < n; tl += nwaves)
+        dft_tile<NT, kDftStep>(frags, frags + DftTile<NT>::FRAG, reinterpret_cast<float*>(bsh), a.s2, a.s0, a.s1,
+                               a.s3, k == 0 ? a.wgiven : nullptr, a.nt, npix, (size_t)i * n + 16 * tl,
+                               std::min(16, n - 16 * tl), a.tau, k == 0, lane);
+    }
+    __syncthreads();
+    // x-update: wave w solves the blocks (t, i), t = w, w + nwaves, ...; no
+    // barrier is needed between them
+    for (int t = w; t < a.nt; t += nwaves) {
+      const size_t blk = (size_t)t * a.nh + i;
+      if (PRIOR == CS_PRIOR_TEMPORAL_TV)
+        xupdate_wave_block<kSolveTV, kXUnrollCol, RP>(a.W, a.L, blk, lane, bsh, dsh, a.hy, a.s0, a.s3, a.s2, a.mu);
+      else
+        xupdate_wave_block<kSolveDFT, kXUnrollCol, RP>(a.W, a.L, blk, lane, bsh, dsh, a.hy, a.s3, nullptr, a.s2,
+                                                       a.mu);
+    }
+    __syncthreads();
+  }
+}
+
+template <int PRIOR, int NT, int RP>
+static int column_launch_rp(cs_plan* p, const ColumnSolveArgs& a, int threads, size_t lds, hipStream_t s) {
+  static size_t lds_set = 0;  // largest dynamic LDS size enabled so far for this instantiation
+  if (lds > 65536 && lds > lds_set) {
+    CS_HIP(hipFuncSetAttribute((const void*)k_column_solve<PRIOR, NT, RP>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    lds_set = lds;
+  }
+  hipLaunchKernelGGL((k_column_solve<PRIOR, NT, RP>), dim3(p->desc.nh), dim3(threads), lds, s, a);
   CS_HIP(hipGetLastError());
   return CS_OK;
 }
 
-int launch_dft_apply(cs_plan* p, const float2* in, float2* out, float2* dual, const float2* v, int adjoint,
-                     hipStream_t s) {
-  CS_DISPATCH_NT(p->desc.nt, dft_apply_launch, p, in, out, dual, v, adjoint, s);
-  CS_HIP(hipGetLastError());
-  return CS_OK;
+template <int PRIOR, int NT>
+static int column_launch(cs_plan* p, const ColumnSolveArgs& a, int threads, size_t lds, hipStream_t s) {
+  const int rp = pairs_per_lane(p->desc.nv);
+  if (rp == 1) return column_launch_rp<PRIOR, NT, 1>(p, a, threads, lds, s);
+  if (rp == 2) return column_launch_rp<PRIOR, NT, 2>(p, a, threads, lds, s);
+  return column_launch_rp<PRIOR, NT, 4>(p, a, threads, lds, s);
+}
+
+bool column_solve_supported(const cs_plan* p) { return (p->desc.nv & 1) == 0; }
+
+int launch_column_solve(cs_plan* p, int iters, float lambda, float mu, const float2* wgiven, hipStream_t s) {
+  const int n = p->desc.nv, nt = p->desc.nt;
+  if (iters <= 0) return CS_OK;
+  const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
+  ColumnSolveArgs a;
+  a.W = p->factor;
+  a.L = p->flayout;
+  a.hy = p->hy;
+  a.s0 = p->s0;
+  a.s1 = p->s1;
+  a.s2 = p->s2;
+  a.s3 = p->s3;
+  a.invden = p->tv_invden;
+  a.dft_frags = p->dft_frags;
+  a.wgiven = wgiven;
+  a.nh = p->desc.nh;
+  a.nt = nt;
+  a.iters = iters;
+  a.mu = mu;
+  a.rho = p->desc.mu_ratio;
+  a.tau = tv ? lambda * a.rho / (2.0f * mu) : lambda / (2.0f * mu);
+  // two waves per SIMD fit the temporal step's registers up to 40 frames
+  const int max_threads = nt <= 40 ? 512 : 256;  // matches MAXT of k_column_solve
+  const int kp = dft_kp(nt);
+  const size_t frag_bytes = tv ? 0 : (size_t)2 * (kp / 16) * (kp / 4) * 64 * sizeof(float);
+  a.wave_floats = std::max(2 * (1 + kXUnrollCol) * n, tv ? 0 : kp * 16);
+  a.wave_floats = (a.wave_floats + 3) / 4 * 4;  // keep every wave's region 16-byte aligned
+  const size_t per_wave = (size_t)a.wave_floats * sizeof(float);
+  const size_t lds_budget = 160 * 1024;
+  const int nwaves = (int)std::max<size_t>(1, std::min<size_t>(max_threads / 64, (lds_budget - frag_bytes) / per_wave));
+  const int threads = nwaves * 64;
+  const size_t lds = nwaves * per_wave + frag_bytes;
+  if (tv) {
+    if (nt <= 8) return column_launch<CS_PRIOR_TEMPORAL_TV, 8>(p, a, threads, lds, s);
+    if (nt <= 16) return column_launch<CS_PRIOR_TEMPORAL_TV, 16>(p, a, threads, lds, s);
+    if (nt <= 24) return column_launch<CS_PRIOR_TEMPORAL_TV, 24>(p, a, threads, lds, s);
+    if (nt <= 32) return column_launch<CS_PRIOR_TEMPORAL_TV, 32>(p, a, threads, lds, s);
+    if (nt <= 40) return column_launch<CS_PRIOR_TEMPORAL_TV, 40>(p, a, threads, lds, s);
+    if (nt <= 48) return column_launch<CS_PRIOR_TEMPORAL_TV, 48>(p, a, threads, lds, s);
+    return column_launch<CS_PRIOR_TEMPORAL_TV, 64>(p, a, threads, lds, s);
+  }
+  switch (kp) {
+    case 16: return column_launch<CS_PRIOR_TEMPORAL_DFT, 16>(p, a, threads, lds, s);
+    case 32: return column_launch<CS_PRIOR_TEMPORAL_DFT, 32>(p, a, threads, lds, s);
+    case 48: return column_launch<CS_PRIOR_TEMPORAL_DFT, 48>(p, a, threads, lds, s);
+    case 64: return column_launch<CS_PRIOR_TEMPORAL_DFT, 64>(p, a, threads, lds, s);
+    case 80: return column_launch<CS_PRIOR_TEMPORAL_DFT, 80>(p, a, threads, lds, s);
+    case 96: return column_launch<CS_PRIOR_TEMPORAL_DFT, 96>(p, a, threads, lds, s);
+    case 112: return column_launch<CS_PRIOR_TEMPORAL_DFT, 112>(p, a, threads, lds, s);
+    default: return column_launch<CS_PRIOR_TEMPORAL_DFT, 128>(p, a, threads, lds, s);
+  }
 }
 
 // ---------------------------------------------------------------- fill

@@ -176,3 +176,80 @@ def test_full_size_dft_192x192x40_12c_sampled_columns():
     err = rel_l2(x.cpu().numpy()[:, :, cols], ref["x"])
     print("dft192 sampled rel_l2", err)
     assert err < TOL
+
+
+FORM_CASES = [((64, 32, 10, 4), "tv"), ((64, 32, 10, 4), "dft"), ((96, 24, 40, 3), "dft"),
+              ((96, 24, 40, 3), "tv"), ((192, 16, 32, 4), "dft"), ((192, 16, 24, 4), "tv"),
+              ((144, 12, 20, 3), "dft"), ((144, 12, 20, 3), "tv"), ((128, 16, 48, 2), "tv"),
+              ((64, 8, 64, 2), "dft"), ((2, 8, 6, 2), "tv"), ((6, 12, 5, 2), "dft")]
+
+
+@pytest.mark.parametrize("shape,prior", FORM_CASES, ids=[f"{s}-{p}" for s, p in FORM_CASES])
+def test_column_form_equals_phase_form(shape, prior):
+    """The single-launch column-resident solve and the two-launches-per-
+    iteration form run the same arithmetic: results must be bit-identical,
+    including the returned state, and both must match the oracle."""
+    from paper_1203_4587_amd import _lib
+    from paper_1203_4587_amd.api import Plan
+    nv, nh, nt, nc = shape
+    fam = "cardiac" if prior == "tv" else "periodic"
+    case = make_case(nv, nh, nt, nc, accel=3, ncenter=2, prior=prior, family=fam, seed=nv + nt)
+    coil, mask, y = case.device()
+    lam, mu, rho, iters = 0.02, 0.1, 0.5, 12
+    a = Plan(coil, mask, mu, prior=prior, mu_ratio=rho, flags=_lib.CS_FLAG_COLUMN_RESIDENT)
+    b = Plan(coil, mask, mu, prior=prior, mu_ratio=rho)
+    sa, sb = a.new_state(), b.new_state()
+    xa = a.solve(y, lam, iters, state=sa)
+    xb = b.solve(y, lam, iters, state=sb)
+    assert torch.equal(xa, xb)
+    for name in ("s0", "s1", "s2", "s3"):
+        if getattr(sa, name) is not None:
+            assert torch.equal(getattr(sa, name), getattr(sb, name)), name
+    # a second call resumes from the state in both forms
+    xa2 = a.solve(y, lam, 5, state=sa)
+    xb2 = b.solve(y, lam, 5, state=sb)
+    assert torch.equal(xa2, xb2)
+    ref = _oracle(case, prior, lam, mu, rho, iters)
+    assert rel_l2(xa.cpu().numpy(), ref["x"]) < TOL
+
+
+@pytest.mark.parametrize("prior", ["tv", "dft"])
+def test_graph_replay_matches_eager(prior):
+    """CS_FLAG_GRAPH captures the phase-kernel loop once and replays it; every
+    replay (with eager work and synchronisation between them) must equal the
+    eager result bit for bit."""
+    from paper_1203_4587_amd import _lib
+    from paper_1203_4587_amd.api import Plan
+    fam = "cardiac" if prior == "tv" else "periodic"
+    case = make_case(48, 16, 8, 3, prior=prior, family=fam, seed=99)
+    coil, mask, y = case.device()
+    eager = Plan(coil, mask, 0.1, prior=prior)
+    graph = Plan(coil, mask, 0.1, prior=prior, flags=_lib.CS_FLAG_GRAPH)
+    ref = eager.solve(y, 0.02, 15)
+    for rep in range(4):
+        x = graph.solve(y, 0.02, 15)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(x, ref), rep
+    # a different iteration count re-captures
+    assert torch.equal(graph.solve(y, 0.02, 7), eager.solve(y, 0.02, 7))
+    del junk
+
+
+@pytest.mark.parametrize("shape,prior", [((192, 24, 32, 4), "dft"), ((144, 24, 20, 3), "tv"),
+                                         ((256, 16, 32, 4), "tv")], ids=str)
+def test_column_form_is_deterministic(shape, prior):
+    """Workgroups of the column-resident solve hold several block solves in
+    turn (groups whose waves are unevenly loaded when nv/2 is not a multiple
+    of 64); repeated runs must agree bit for bit."""
+    from paper_1203_4587_amd import _lib
+    from paper_1203_4587_amd.api import Plan
+    nv, nh, nt, nc = shape
+    fam = "cardiac" if prior == "tv" else "periodic"
+    case = make_case(nv, nh, nt, nc, accel=3, ncenter=2, prior=prior, family=fam, seed=3)
+    coil, mask, y = case.device()
+    plan = Plan(coil, mask, 0.1, prior=prior, flags=_lib.CS_FLAG_COLUMN_RESIDENT)
+    ref = plan.solve(y, 0.02, 8)
+    for _ in range(3):
+        assert torch.equal(plan.solve(y, 0.02, 8), ref)
