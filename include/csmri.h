@@ -72,6 +72,11 @@ enum {
                                         and replay it (not while cs_kernel_timing is on) */
   CS_FLAG_COLUMN_RESIDENT = 1u << 2, /* run all iterations in one launch, one workgroup per readout
                                         column, instead of two launches per iteration; same results */
+  CS_FLAG_XU_WAVE = 1u << 3,         /* phase form, even nv: one 64-lane wave solves a block */
+  CS_FLAG_XU_GROUP = 1u << 4,        /* phase form, even nv: a workgroup of nv/2 lanes (rounded up to
+                                        whole waves) solves a block.  With neither XU flag the wave
+                                        form is used when nv/2 is a multiple of 64.  All x-update
+                                        forms give bit-identical results. */
 };
 
 /* Device-memory allocator used for everything the plan owns.  alloc returns
@@ -150,6 +155,61 @@ int cs_apply_block_inverse(cs_plan* plan, const cs_c64* b, cs_c64* x, cs_stream 
  * couple columns).  Both forms give bit-identical results. */
 int cs_admm_solve(cs_plan* plan, const cs_c64* y, float lambda, float mu, int32_t iters,
                   cs_c64* x_out, cs_state* state, float* J_trace, cs_stream stream);
+
+/* Read or replace the plan's flags (any CS_FLAG_* combination that
+ * cs_plan_create accepts).  The form flags only choose how iterations are
+ * launched, never what they compute. */
+int cs_plan_flags(const cs_plan* plan, uint32_t* flags);
+int cs_plan_set_flags(cs_plan* plan, uint32_t flags);
+
+/* Autotuner: times `iters` iterations (after as many untimed ones) of every
+ * execution form the plan supports -- phase form with each x-update form
+ * (graph-replayed), and the column-resident form -- on the data y, and keeps
+ * the fastest in the plan's flags (CS_FLAG_NO_REFACTOR is preserved).
+ * entries (host array of `cap`, may be NULL) receives the flags and measured
+ * ms per iteration of each candidate; *count (may be NULL) their number.
+ * Synchronises `stream`.  The plan's solver workspaces are overwritten. */
+typedef struct {
+  uint32_t flags;
+  float ms_per_iter;
+} cs_tune_entry;
+int cs_plan_tune(cs_plan* plan, const cs_c64* y, float lambda, int32_t iters, cs_tune_entry* entries,
+                 int32_t cap, int32_t* count, cs_stream stream);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent slices (uneven sizes, coil counts, sampling, priors) solved
+ * together.  Each slice is one plan (as cs_plan_create); cs_batch_solve runs
+ * every slice's whole solve -- H'y setup and `iters` iterations -- as one
+ * hipGraph launch in which the slices are independent branches, so the GPU
+ * overlaps them and the host pays one launch per call.  The graph is
+ * recorded on the first call and replayed while the pointers, lambdas and
+ * iteration count stay the same.  Results equal cs_admm_solve on each slice
+ * bit for bit. */
+typedef struct cs_batch cs_batch;
+
+typedef struct {
+  cs_plan_desc desc;    /* sizes, prior, mu_ratio of this slice; CS_FLAG_GRAPH is ignored */
+  const cs_c64* coil;   /* device [nc][nv][nh] */
+  const uint8_t* mask;  /* device [nt][nv] */
+  float mu;
+} cs_slice_desc;
+
+/* slices: host array of `count` descriptors.  Builds every plan (synchronous,
+ * like cs_plan_create).  On error no batch is returned. */
+int cs_batch_create(const cs_slice_desc* slices, int32_t count, const cs_allocator* alloc, cs_stream stream,
+                    cs_batch** out);
+int cs_batch_destroy(cs_batch* batch);
+int cs_batch_size(const cs_batch* batch, int32_t* count);
+/* The plan of slice `index` (owned by the batch: do not destroy it).  It may
+ * be used on its own (cs_apply_A, cs_plan_tune, ...); changing its flags makes
+ * the next cs_batch_solve record the graph again. */
+int cs_batch_plan(cs_batch* batch, int32_t index, cs_plan** plan);
+
+/* y, x_out: host arrays of `count` device pointers (k-space and image of each
+ * slice, layouts as for cs_admm_solve); lambda: host array of `count` values.
+ * Each slice runs with its plan's mu, from the algorithm's initialisation. */
+int cs_batch_solve(cs_batch* batch, const cs_c64* const* y, const float* lambda, int32_t iters,
+                   cs_c64* const* x_out, cs_stream stream);
 
 /* Per-kernel device timing, a profiling aid for callers that report kernel
  * throughput.  cs_kernel_timing(plan, 1) starts bracketing every launch of

@@ -23,6 +23,8 @@ CS_PRIOR_TEMPORAL_DFT = 1
 CS_FLAG_NO_REFACTOR = 1 << 0
 CS_FLAG_GRAPH = 1 << 1
 CS_FLAG_COLUMN_RESIDENT = 1 << 2
+CS_FLAG_XU_WAVE = 1 << 3
+CS_FLAG_XU_GROUP = 1 << 4
 
 # every function declared in include/csmri.h
 EXPORTED = (
@@ -38,6 +40,14 @@ EXPORTED = (
     "cs_version",
     "cs_kernel_timing",
     "cs_kernel_times",
+    "cs_plan_flags",
+    "cs_plan_set_flags",
+    "cs_plan_tune",
+    "cs_batch_create",
+    "cs_batch_destroy",
+    "cs_batch_size",
+    "cs_batch_plan",
+    "cs_batch_solve",
 )
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -74,6 +84,15 @@ class CsKernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
+class CsTuneEntry(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("ms_per_iter", ctypes.c_float)]
+
+
+class CsSliceDesc(ctypes.Structure):
+    _fields_ = [("desc", CsPlanDesc), ("coil", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+                ("mu", ctypes.c_float)]
+
+
 class CsmriError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         self.status = status
@@ -104,10 +123,18 @@ def load() -> ctypes.CDLL:
     lib.cs_admm_solve.argtypes = [vp, vp, f32, f32, i32, vp, ctypes.POINTER(CsState), vp, vp]
     lib.cs_kernel_timing.argtypes = [vp, ctypes.c_int]
     lib.cs_kernel_times.argtypes = [vp, ctypes.POINTER(CsKernelTime), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-    for name in ("cs_plan_create", "cs_plan_destroy", "cs_plan_bytes", "cs_apply_A", "cs_apply_AH",
-                 "cs_apply_block_inverse", "cs_admm_solve", "cs_version", "cs_kernel_timing",
-                 "cs_kernel_times"):
-        getattr(lib, name).restype = ctypes.c_int
+    lib.cs_plan_flags.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
+    lib.cs_plan_set_flags.argtypes = [vp, ctypes.c_uint32]
+    lib.cs_plan_tune.argtypes = [vp, vp, f32, i32, ctypes.POINTER(CsTuneEntry), i32, ctypes.POINTER(i32), vp]
+    lib.cs_batch_create.argtypes = [ctypes.POINTER(CsSliceDesc), i32, ctypes.POINTER(CsAllocator), vp,
+                                    ctypes.POINTER(vp)]
+    lib.cs_batch_destroy.argtypes = [vp]
+    lib.cs_batch_size.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.cs_batch_plan.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    lib.cs_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(f32), i32, ctypes.POINTER(vp), vp]
+    for name in EXPORTED:
+        if name not in ("cs_status_string", "cs_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
     lib.cs_version.argtypes = []
     lib.cs_status_string.argtypes = [ctypes.c_int]
     lib.cs_status_string.restype = ctypes.c_char_p

@@ -191,6 +191,43 @@ class Plan:
         check(_lib.load().cs_kernel_times(self.handle, recs, 8, ctypes.byref(n)), "cs_kernel_times")
         return {recs[i].name.decode(): (int(recs[i].launches), float(recs[i].ms)) for i in range(min(n.value, 8))}
 
+    @property
+    def flags(self) -> int:
+        f = ctypes.c_uint32()
+        check(_lib.load().cs_plan_flags(self.handle, ctypes.byref(f)), "cs_plan_flags")
+        return f.value
+
+    @flags.setter
+    def flags(self, value: int) -> None:
+        check(_lib.load().cs_plan_set_flags(self.handle, int(value)), "cs_plan_set_flags")
+
+    def tune(self, y: torch.Tensor, lam: float, iters: int = 10, cache: str | None = None,
+             stream=None) -> dict:
+        """cs_plan_tune: time every execution form on y, keep the fastest.
+
+        With `cache` (a JSON file path), a previous result for the same device
+        and slice shape is reused instead of timing again, and new results are
+        stored there.  Returns {"flags": chosen, "candidates": [(flags, ms/iter)]}.
+        """
+        _need(y, "y", torch.complex64, self.kspace_shape)
+        key = "|".join(map(str, (torch.cuda.get_device_name(self.device), self.nv, self.nh, self.nt, self.nc,
+                                 self.prior)))
+        if cache is not None:
+            entry = _tune_cache_read(cache).get(key)
+            if entry is not None:
+                keep = self.flags & _lib.CS_FLAG_NO_REFACTOR
+                self.flags = keep | (int(entry["flags"]) & ~_lib.CS_FLAG_NO_REFACTOR)
+                return {"flags": self.flags, "candidates": [tuple(c) for c in entry["candidates"]], "cached": True}
+        recs = (_lib.CsTuneEntry * 8)()
+        n = ctypes.c_int32()
+        check(_lib.load().cs_plan_tune(self.handle, _ptr(y), float(lam), int(iters), recs, 8, ctypes.byref(n),
+                                       _stream(stream)), "cs_plan_tune")
+        cands = [(int(recs[i].flags), float(recs[i].ms_per_iter)) for i in range(min(n.value, 8))]
+        result = {"flags": self.flags, "candidates": cands, "cached": False}
+        if cache is not None:
+            _tune_cache_write(cache, key, {"flags": result["flags"], "candidates": cands})
+        return result
+
     def new_state(self) -> State:
         return State.empty(self.prior, self.nt, self.nv, self.nh, self.device)
 
@@ -220,6 +257,147 @@ class Plan:
         if cstate is not None:
             state.iter = int(cstate.iter)
         return (x, J[:iters]) if trace else x
+
+
+def _tune_cache_read(path: str) -> dict:
+    import json
+    import os
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def _tune_cache_write(path: str, key: str, entry: dict) -> None:
+    import json
+    import os
+    data = _tune_cache_read(path)
+    data[key] = entry
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+@dataclass
+class Slice:
+    """One slice of a batch: coil maps (nc, nv, nh), mask (nt, nv), prior, mu."""
+    coil: torch.Tensor
+    mask: torch.Tensor
+    prior: str = "tv"
+    mu: float = 0.1
+    mu_ratio: float = 0.5
+    flags: int = 0
+
+
+class _BorrowedPlan(Plan):
+    """A plan owned by a batch (cs_batch_plan): usable, never destroyed here."""
+
+    def __init__(self, handle: ctypes.c_void_p, sl: Slice, batch: "Batch"):
+        self._h = handle
+        self._batch = batch  # keeps the batch alive
+        nc, nv, nh = sl.coil.shape
+        self.nv, self.nh, self.nt, self.nc = int(nv), int(nh), int(sl.mask.shape[0]), int(nc)
+        self.prior = sl.prior
+        self.device = sl.coil.device
+        self.mu = float(sl.mu)
+
+    def close(self) -> None:
+        self._h = ctypes.c_void_p()
+
+
+class Batch:
+    """Many independent slices solved by one graph launch (cs_batch_create / cs_batch_solve)."""
+
+    def __init__(self, slices, use_torch_allocator: bool = True, stream=None):
+        lib = _lib.load()
+        slices = list(slices)
+        if not slices:
+            raise ValueError("a batch needs at least one slice")
+        descs = (_lib.CsSliceDesc * len(slices))()
+        for i, sl in enumerate(slices):
+            if sl.prior not in PRIORS:
+                raise ValueError(f"slice {i}: prior must be one of {sorted(PRIORS)}")
+            if sl.coil.dim() != 3 or sl.mask.dim() != 2:
+                raise ValueError(f"slice {i}: coil must be (nc, nv, nh) and mask (nt, nv)")
+            nc, nv, nh = sl.coil.shape
+            nt = sl.mask.shape[0]
+            _need(sl.coil, f"slices[{i}].coil", torch.complex64, (nc, nv, nh))
+            _need(sl.mask, f"slices[{i}].mask", torch.uint8, (nt, nv))
+            descs[i] = _lib.CsSliceDesc(CsPlanDesc(int(nv), int(nh), int(nt), int(nc), PRIORS[sl.prior],
+                                                   float(sl.mu_ratio), int(sl.flags)),
+                                        sl.coil.data_ptr(), sl.mask.data_ptr(), float(sl.mu))
+        self.slices = slices
+        self.device = slices[0].coil.device
+        self._alloc = _TorchAllocator(self.device.index or 0) if use_torch_allocator else None
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.cs_batch_create(descs, len(slices), ctypes.byref(self._alloc.struct) if self._alloc else None,
+                                     _stream(stream), ctypes.byref(handle))
+        check(st, "cs_batch_create")
+        self._h = handle
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.load().cs_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __len__(self) -> int:
+        return len(self.slices)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h or not self._h.value:
+            raise RuntimeError("batch is closed")
+        return self._h
+
+    def plan(self, i: int) -> Plan:
+        h = ctypes.c_void_p()
+        check(_lib.load().cs_batch_plan(self.handle, int(i), ctypes.byref(h)), "cs_batch_plan")
+        return _BorrowedPlan(h, self.slices[i], self)
+
+    def image_shape(self, i: int):
+        sl = self.slices[i]
+        return (int(sl.mask.shape[0]), int(sl.coil.shape[1]), int(sl.coil.shape[2]))
+
+    def kspace_shape(self, i: int):
+        sl = self.slices[i]
+        return (int(sl.mask.shape[0]), int(sl.coil.shape[0]), int(sl.coil.shape[1]), int(sl.coil.shape[2]))
+
+    def solve(self, ys, lams, iters: int, outs=None, stream=None):
+        """cs_batch_solve: ys[i] is slice i's k-space, lams[i] its lambda; returns the images."""
+        n = len(self.slices)
+        ys = list(ys)
+        if len(ys) != n:
+            raise ValueError(f"need {n} k-space arrays, got {len(ys)}")
+        if isinstance(lams, (int, float)):
+            lams = [float(lams)] * n
+        lams = [float(v) for v in lams]
+        if len(lams) != n:
+            raise ValueError(f"need {n} lambdas, got {len(lams)}")
+        if outs is None:
+            outs = [torch.empty(self.image_shape(i), dtype=torch.complex64, device=self.device) for i in range(n)]
+        outs = list(outs)
+        for i in range(n):
+            _need(ys[i], f"ys[{i}]", torch.complex64, self.kspace_shape(i))
+            _need(outs[i], f"outs[{i}]", torch.complex64, self.image_shape(i))
+        yp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in ys])
+        xp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in outs])
+        lp = (ctypes.c_float * n)(*lams)
+        check(_lib.load().cs_batch_solve(self.handle, yp, lp, int(iters), xp, _stream(stream)), "cs_batch_solve")
+        return outs
 
 
 def to_device(a, device="cuda", dtype=None) -> torch.Tensor:

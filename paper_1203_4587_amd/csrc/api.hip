@@ -1,4 +1,5 @@
 // C ABI entry points of libcsmri (declared in include/csmri.h).
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -67,6 +68,16 @@ static void plan_release(cs_plan* p) {
   delete p;
 }
 
+static constexpr uint32_t kAllFlags =
+    CS_FLAG_NO_REFACTOR | CS_FLAG_GRAPH | CS_FLAG_COLUMN_RESIDENT | CS_FLAG_XU_WAVE | CS_FLAG_XU_GROUP;
+
+static int validate_flags(uint32_t f) {
+  if (f & ~kAllFlags) return set_error(CS_EINVAL, "unknown flag bits");
+  if ((f & CS_FLAG_XU_WAVE) && (f & CS_FLAG_XU_GROUP))
+    return set_error(CS_EINVAL, "CS_FLAG_XU_WAVE and CS_FLAG_XU_GROUP are exclusive");
+  return CS_OK;
+}
+
 static int validate_desc(const cs_plan_desc* d) {
   if (d->nv < 2 || d->nh < 2 || d->nt < 1 || d->nc < 1)
     return set_error(CS_EINVAL, "nv, nh must be >= 2 and nt, nc >= 1");
@@ -80,7 +91,7 @@ static int validate_desc(const cs_plan_desc* d) {
     return set_error(CS_EUNSUPPORTED, "nv and nh must be of the form 2^a 3^b and at most 512");
   if (d->nt > 64) return set_error(CS_EUNSUPPORTED, "nt must be at most 64");
   if (d->nc > 64) return set_error(CS_EUNSUPPORTED, "nc must be at most 64");
-  return CS_OK;
+  return validate_flags(d->flags);
 }
 
 static inline hipStream_t S(cs_stream s) { return reinterpret_cast<hipStream_t>(s); }
@@ -487,7 +498,6 @@ int cs_admm_solve(cs_plan* p, const cs_c64* y, float lambda, float mu, int32_t i
   // setup: hybrid data F_h' y (kept for the objective) and H'y in solver layout
   CK(launch_adjoint_rows(p, reinterpret_cast<const float2*>(y), s));
   CK(launch_adjoint_image(p, p->hy, true, s));
-  const size_t img_bytes = nimg * sizeof(float2);
   if (tv) {
     if (warm) {
       CK(in_t(state->s0, p->s0, nt));
@@ -495,8 +505,8 @@ int cs_admm_solve(cs_plan* p, const cs_c64* y, float lambda, float mu, int32_t i
       CK(in_t(state->s2, p->s2, nt));
       CK(in_t(state->s3, p->s3, nt));
     } else {
-      CS_HIP(hipMemcpyAsync(p->s0, p->hy, img_bytes, hipMemcpyDeviceToDevice, s));  // m = x
-      CS_HIP(hipMemcpyAsync(p->s2, p->hy, img_bytes, hipMemcpyDeviceToDevice, s));  // x = H'y
+      CK(launch_copy(p->hy, p->s0, nimg, s));  // m = x
+      CK(launch_copy(p->hy, p->s2, nimg, s));  // x = H'y
       CK(launch_fill(p->s1, nimg, zero, s));
       CK(launch_fill(p->s3, nimg, zero, s));
     }
@@ -507,7 +517,7 @@ int cs_admm_solve(cs_plan* p, const cs_c64* y, float lambda, float mu, int32_t i
       CK(in_t(state->s1, p->s1, nt));                      // v
       CK(in_t(state->s2, p->s0, nt));                      // d
     } else {
-      CS_HIP(hipMemcpyAsync(p->s2, p->hy, img_bytes, hipMemcpyDeviceToDevice, s));  // Psi' w_0 = H'y
+      CK(launch_copy(p->hy, p->s2, nimg, s));  // Psi' w_0 = H'y
       CK(launch_fill(p->s0, nimg, zero, s));
       CK(launch_fill(p->s1, nimg, zero, s));
     }
@@ -532,6 +542,254 @@ int cs_admm_solve(cs_plan* p, const cs_c64* y, float lambda, float mu, int32_t i
     state->iter += iters;
   }
 #undef CK
+  return CS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- flags and tuning
+
+static void set_plan_flags(cs_plan* p, uint32_t flags) {
+  if (flags == p->desc.flags) return;
+  if (p->graph) {  // the cached graph holds the kernels of the old form
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  p->desc.flags = flags;
+}
+
+extern "C" {
+
+int cs_plan_flags(const cs_plan* p, uint32_t* flags) {
+  if (!p || !flags) return set_error(CS_EINVAL, "plan and flags must not be NULL");
+  *flags = p->desc.flags;
+  return CS_OK;
+}
+
+int cs_plan_set_flags(cs_plan* p, uint32_t flags) {
+  if (!p) return set_error(CS_EINVAL, "plan is NULL");
+  int st = validate_flags(flags);
+  if (st != CS_OK) return st;
+  CS_HIP(hipSetDevice(p->device));
+  set_plan_flags(p, flags);
+  return CS_OK;
+}
+
+int cs_plan_tune(cs_plan* p, const cs_c64* y, float lambda, int32_t iters, cs_tune_entry* entries, int32_t cap,
+                 int32_t* count, cs_stream stream) {
+  if (!p || !y) return set_error(CS_EINVAL, "plan and y must not be NULL");
+  if (iters < 1) return set_error(CS_EINVAL, "iters must be >= 1");
+  if (!(lambda >= 0.f && std::isfinite(lambda))) return set_error(CS_EINVAL, "lambda must be finite and >= 0");
+  if (cap < 0) return set_error(CS_EINVAL, "cap must be >= 0");
+  if (p->timing) return set_error(CS_EINVAL, "kernel timing is on; switch it off before tuning");
+  CS_HIP(hipSetDevice(p->device));
+  hipStream_t s = S(stream);
+  const uint32_t keep = p->desc.flags & CS_FLAG_NO_REFACTOR;
+  const uint32_t forms = CS_FLAG_GRAPH | CS_FLAG_COLUMN_RESIDENT | CS_FLAG_XU_WAVE | CS_FLAG_XU_GROUP;
+  const uint32_t original = p->desc.flags;
+  std::vector<uint32_t> cand;
+  if (p->desc.nv % 2 == 0) {
+    cand.push_back(CS_FLAG_GRAPH | CS_FLAG_XU_WAVE);
+    cand.push_back(CS_FLAG_GRAPH | CS_FLAG_XU_GROUP);
+    if (column_solve_supported(p)) cand.push_back(CS_FLAG_COLUMN_RESIDENT);
+  } else {
+    cand.push_back(CS_FLAG_GRAPH);
+  }
+  // a fresh start on y: state in the plan's workspaces, x written to img_tmp
+  int st = cs_admm_solve(p, y, lambda, p->mu, 0, reinterpret_cast<cs_c64*>(p->img_tmp), nullptr, nullptr, stream);
+  if (st != CS_OK) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  CS_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return set_error(CS_EDEVICE, "hipEventCreate failed");
+  }
+  uint32_t best = original;
+  float best_ms = 0.f;
+  int32_t n = 0;
+  for (uint32_t c : cand) {
+    set_plan_flags(p, keep | c | (original & ~(forms | keep)));
+    if ((st = run_iterations(p, iters, lambda, p->mu, nullptr, nullptr, s)) != CS_OK) break;  // warm-up
+    hipError_t e = hipEventRecord(e0, s);
+    if (e == hipSuccess) st = run_iterations(p, iters, lambda, p->mu, nullptr, nullptr, s);
+    if (e == hipSuccess && st == CS_OK) e = hipEventRecord(e1, s);
+    if (e == hipSuccess && st == CS_OK) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess && st == CS_OK) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) st = hip_fail(e, "timing a tuning candidate");
+    if (st != CS_OK) break;
+    const float per = ms / (float)iters;
+    if (entries && n < cap) entries[n] = cs_tune_entry{p->desc.flags, per};
+    ++n;
+    if (n == 1 || per < best_ms) {
+      best_ms = per;
+      best = p->desc.flags;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  set_plan_flags(p, st == CS_OK ? best : original);
+  if (count) *count = n;
+  return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+
+struct cs_batch {
+  std::vector<cs_plan*> plans;
+  std::vector<hipStream_t> streams;  // one per slice, used only while recording
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork = nullptr;
+  hipStream_t capture = nullptr;
+  hipGraphExec_t graph = nullptr;
+  std::vector<const void*> key;
+};
+
+static void batch_release(cs_batch* b) {
+  if (!b) return;
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  for (hipEvent_t e : b->joins) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  for (cs_plan* p : b->plans) (void)cs_plan_destroy(p);
+  delete b;
+}
+
+extern "C" {
+
+int cs_batch_create(const cs_slice_desc* slices, int32_t count, const cs_allocator* alloc, cs_stream stream,
+                    cs_batch** out) {
+  if (!out) return set_error(CS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!slices || count <= 0) return set_error(CS_EINVAL, "slices must be a non-empty array");
+  cs_batch* b = new (std::nothrow) cs_batch();
+  if (!b) return set_error(CS_ENOMEM, "host allocation of the batch failed");
+  for (int32_t i = 0; i < count; ++i) {
+    cs_plan_desc d = slices[i].desc;
+    d.flags &= ~(uint32_t)CS_FLAG_GRAPH;  // the batch records its own graph
+    cs_plan* p = nullptr;
+    const int st = cs_plan_create(&d, slices[i].coil, slices[i].mask, slices[i].mu, alloc, stream, &p);
+    if (st != CS_OK) {
+      const std::string msg = "slice " + std::to_string(i) + ": " + g_last_error;
+      batch_release(b);
+      return set_error(st, msg);
+    }
+    b->plans.push_back(p);
+  }
+  *out = b;
+  return CS_OK;
+}
+
+int cs_batch_destroy(cs_batch* b) {
+  if (!b) return CS_OK;
+  if (!b->plans.empty()) {
+    (void)hipSetDevice(b->plans[0]->device);
+    (void)hipDeviceSynchronize();
+  }
+  batch_release(b);
+  return CS_OK;
+}
+
+int cs_batch_size(const cs_batch* b, int32_t* count) {
+  if (!b || !count) return set_error(CS_EINVAL, "batch and count must not be NULL");
+  *count = (int32_t)b->plans.size();
+  return CS_OK;
+}
+
+int cs_batch_plan(cs_batch* b, int32_t index, cs_plan** plan) {
+  if (!b || !plan) return set_error(CS_EINVAL, "batch and plan must not be NULL");
+  if (index < 0 || (size_t)index >= b->plans.size()) return set_error(CS_EINVAL, "slice index out of range");
+  *plan = b->plans[(size_t)index];
+  return CS_OK;
+}
+
+int cs_batch_solve(cs_batch* b, const cs_c64* const* y, const float* lambda, int32_t iters, cs_c64* const* x_out,
+                   cs_stream stream) {
+  if (!b || !y || !lambda || !x_out) return set_error(CS_EINVAL, "batch, y, lambda and x_out must not be NULL");
+  if (iters < 0) return set_error(CS_EINVAL, "iters must be >= 0");
+  const size_t n = b->plans.size();
+  for (size_t i = 0; i < n; ++i) {
+    if (!y[i] || !x_out[i]) return set_error(CS_EINVAL, "slice " + std::to_string(i) + ": NULL array");
+    if (!(lambda[i] >= 0.f && std::isfinite(lambda[i])))
+      return set_error(CS_EINVAL, "slice " + std::to_string(i) + ": lambda must be finite and >= 0");
+  }
+  CS_HIP(hipSetDevice(b->plans[0]->device));
+  hipStream_t s = S(stream);
+  std::vector<const void*> key;
+  key.push_back(reinterpret_cast<const void*>((intptr_t)iters));
+  for (size_t i = 0; i < n; ++i) {
+    uint32_t lb;
+    std::memcpy(&lb, &lambda[i], sizeof(lb));
+    key.push_back(y[i]);
+    key.push_back(x_out[i]);
+    key.push_back(reinterpret_cast<const void*>((intptr_t)lb));
+    key.push_back(reinterpret_cast<const void*>((intptr_t)b->plans[i]->desc.flags));
+  }
+  if (!b->graph || key != b->key) {
+    if (b->graph) {
+      CS_HIP(hipStreamSynchronize(s));
+      CS_HIP(hipGraphExecDestroy(b->graph));
+      b->graph = nullptr;
+    }
+    if (!b->capture) {
+      CS_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+      CS_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+      for (size_t i = 0; i < n; ++i) {
+        hipStream_t st;
+        hipEvent_t e;
+        CS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        b->streams.push_back(st);
+        CS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->joins.push_back(e);
+      }
+    }
+    // record: fork every slice's stream off the capture stream, run each
+    // slice's solve on its stream, join them back.  Slices are recorded in
+    // decreasing order of factor size (longest first, as in LPT scheduling),
+    // so the largest solves are the first to reach the GPU.
+    std::vector<size_t> order(n);
+    for (size_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) {
+      return factor_elems(b->plans[a]->flayout) > factor_elems(b->plans[c]->flayout);
+    });
+    CS_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    int st = CS_OK;
+    hipError_t e = hipEventRecord(b->fork, b->capture);
+    for (size_t oi = 0; oi < n && st == CS_OK && e == hipSuccess; ++oi) {
+      const size_t i = order[oi];
+      e = hipStreamWaitEvent(b->streams[i], b->fork, 0);
+      if (e != hipSuccess) break;
+      cs_plan* p = b->plans[i];
+      const bool saved_timing = p->timing;
+      const uint32_t saved_flags = p->desc.flags;
+      p->timing = false;
+      p->desc.flags &= ~(uint32_t)CS_FLAG_GRAPH;  // no nested capture
+      st = cs_admm_solve(p, y[i], lambda[i], p->mu, iters, x_out[i], nullptr, nullptr, b->streams[i]);
+      p->timing = saved_timing;
+      p->desc.flags = saved_flags;
+      if (st == CS_OK) e = hipEventRecord(b->joins[i], b->streams[i]);
+      if (st == CS_OK && e == hipSuccess) e = hipStreamWaitEvent(b->capture, b->joins[i], 0);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->capture, &g);
+    if (st != CS_OK || e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      if (st != CS_OK) return st;
+      return hip_fail(e != hipSuccess ? e : e2, "recording the batch graph");
+    }
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b->graph = nullptr;
+      return hip_fail(e, "hipGraphInstantiate(batch)");
+    }
+    b->key = key;
+  }
+  CS_HIP(hipGraphLaunch(b->graph, s));
   return CS_OK;
 }
 

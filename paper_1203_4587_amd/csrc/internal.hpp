@@ -216,6 +216,7 @@ int launch_dft_step(cs_plan* p, float lambda, float mu, int first, const float2*
 int launch_dft_apply(cs_plan* p, const float2* in, float2* out, float2* dual, const float2* v, int adjoint,
                      hipStream_t s);
 int launch_fill(float2* ptr, size_t n, float2 v, hipStream_t s);
+int launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s);
 // all iterations in one launch, one workgroup per readout column (even nv)
 bool column_solve_supported(const cs_plan* p);
 int launch_column_solve(cs_plan* p, int iters, float lambda, float mu, const float2* wgiven, hipStream_t s);

@@ -298,7 +298,9 @@ static void xupdate_launch(cs_plan* p, const float2* hy, const float2* m, float2
                            hipStream_t s) {
   const FactorLayout& L = p->flayout;
   const int n = L.n;
-  if ((n & 1) == 0 && (n / 2) % 64 == 0) {
+  const uint32_t f = p->desc.flags;
+  const bool wave = (n & 1) == 0 && !(f & CS_FLAG_XU_GROUP) && ((f & CS_FLAG_XU_WAVE) || (n / 2) % 64 == 0);
+  if (wave) {
     const int rp = pairs_per_lane(n);
     if (rp == 1) xupdate_wave_launch<MODE, 1>(p, hy, m, d2, x, mu, s);
     else if (rp == 2) xupdate_wave_launch<MODE, 2>(p, hy, m, d2, x, mu, s);
@@ -831,6 +833,19 @@ int launch_fill(float2* ptr, size_t n, float2 v, hipStream_t s) {
   if (n == 0) return CS_OK;
   const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, ptr, n, v);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
+__global__ void k_copy(const float2* __restrict__ src, float2* __restrict__ dst, size_t n) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
+    dst[q] = src[q];
+}
+
+int launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s) {
+  if (n == 0) return CS_OK;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, src, dst, n);
   CS_HIP(hipGetLastError());
   return CS_OK;
 }

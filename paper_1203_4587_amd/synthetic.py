@@ -270,7 +270,8 @@ def _cfg5():
                         sigma=0.005, iters=20, period=12.0, name="tv-192x192x24-12c-unrolled")
 
 
-def _batch_slice(s):
+def batch_slice(s: int):
+    """The seeded problem of slice s (0..23) of the 24-slice uneven batch."""
     sp = batch_slice_spec(s)
     return make_problem(sp["nv"], sp["nh"], sp["nt"], sp["nc"], sp["accel"], sp["ncenter"],
                         sp["prior"], sp["family"], sp["seed"], sigma=0.005, iters=100,

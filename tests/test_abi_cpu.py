@@ -111,3 +111,43 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         _lib.load()
+
+
+@pytest.mark.parametrize("flags", [
+    _lib.CS_FLAG_XU_WAVE | _lib.CS_FLAG_XU_GROUP,   # exclusive x-update forms
+    1 << 12,                                        # unknown bit
+])
+def test_plan_create_rejects_bad_flags(lib, flags):
+    d = _desc()
+    d.flags = flags
+    st, h = _create(lib, d)
+    assert st == _lib.CS_EINVAL
+    assert h.value is None
+
+
+def test_flag_and_tune_calls_reject_nulls(lib):
+    f = ctypes.c_uint32()
+    assert lib.cs_plan_flags(None, ctypes.byref(f)) == _lib.CS_EINVAL
+    assert lib.cs_plan_set_flags(None, 0) == _lib.CS_EINVAL
+    assert lib.cs_plan_tune(None, FAKE, 0.01, 5, None, 0, None, None) == _lib.CS_EINVAL
+
+
+def test_batch_calls_reject_bad_arguments(lib):
+    h = ctypes.c_void_p()
+    assert lib.cs_batch_create(None, 1, None, None, ctypes.byref(h)) == _lib.CS_EINVAL
+    sl = (_lib.CsSliceDesc * 2)()
+    sl[0] = _lib.CsSliceDesc(_desc(), FAKE.value, FAKE.value, 0.1)
+    sl[1] = _lib.CsSliceDesc(_desc(), FAKE.value, FAKE.value, 0.1)
+    assert lib.cs_batch_create(sl, 0, None, None, ctypes.byref(h)) == _lib.CS_EINVAL
+    assert lib.cs_batch_create(sl, 2, None, None, None) == _lib.CS_EINVAL
+    # a bad descriptor fails the whole batch before any device work, naming the slice
+    sl[0] = _lib.CsSliceDesc(_desc(nv=100), FAKE.value, FAKE.value, 0.1)
+    assert lib.cs_batch_create(sl, 2, None, None, ctypes.byref(h)) == _lib.CS_EUNSUPPORTED
+    assert h.value is None
+    assert b"slice 0" in lib.cs_last_error()
+    n = ctypes.c_int32()
+    p = ctypes.c_void_p()
+    assert lib.cs_batch_size(None, ctypes.byref(n)) == _lib.CS_EINVAL
+    assert lib.cs_batch_plan(None, 0, ctypes.byref(p)) == _lib.CS_EINVAL
+    assert lib.cs_batch_solve(None, None, None, 10, None, None) == _lib.CS_EINVAL
+    assert lib.cs_batch_destroy(None) == _lib.CS_OK
