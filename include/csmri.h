@@ -211,6 +211,43 @@ int cs_batch_plan(cs_batch* batch, int32_t index, cs_plan** plan);
 int cs_batch_solve(cs_batch* batch, const cs_c64* const* y, const float* lambda, int32_t iters,
                    cs_c64* const* x_out, cs_stream stream);
 
+/* ---------------------------------------------------------------- gradients
+ * Reverse-mode derivative of K unrolled iterations of Algorithm 2 (temporal TV
+ * prior, Sec. IV-B) from its initialisation, for training or tuning through
+ * the reconstruction: given dL/dx_K of a real loss L, returns dL/dy, dL/dlambda
+ * and dL/dmu (mu = mu_2; rho = mu_ratio is held fixed).  Complex gradients use
+ * the convention g = dL/dRe z + i dL/dIm z (that of torch.autograd).
+ *
+ * The forward keeps the solver state every `ckpt_every` iterations; the
+ * backward recomputes one segment at a time from its checkpoint and sweeps the
+ * transposed Jacobian of each line of the algorithm in reverse (the x-update
+ * kernel applies the Hermitian (mu I + H'H)^{-1}; one per-pixel kernel does
+ * the transposed temporal step, soft threshold and dual updates).  Memory:
+ * about 4 images per checkpoint plus 3 per iteration of a segment plus 7.
+ * dL/dy = A(dL/dH'y) is zero on rows the mask does not sample.  Where some
+ * |D m + d1| equals tau exactly the map is not differentiable; the derivative
+ * of the inactive side is returned. */
+typedef struct cs_grad cs_grad;
+
+/* Workspace for `iters` unrolled iterations on `plan` (TV prior only, else
+ * CS_EUNSUPPORTED), allocated through the plan's allocator; it must be
+ * destroyed before the plan.  ckpt_every >= 1. */
+int cs_grad_create(cs_plan* plan, int32_t iters, int32_t ckpt_every, cs_grad** out);
+int cs_grad_destroy(cs_grad* grad);
+
+/* x_out = x_K of cs_admm_solve(plan, y, lambda, mu, iters) (bit-identical),
+ * keeping checkpoints and H'y in the workspace for one cs_admm_backward. */
+int cs_admm_forward_ckpt(cs_grad* grad, const cs_c64* y, float lambda, float mu, cs_c64* x_out,
+                         cs_stream stream);
+
+/* grad_x: device image dL/dx_K; grad_y: device k-space [nt][nc][nv][nh]
+ * receiving dL/dy; grad_lambda_mu: device float[2] receiving dL/dlambda and
+ * dL/dmu (FP64 accumulation).  Uses the lambda and mu of the last
+ * cs_admm_forward_ckpt (CS_EINVAL if there was none); overwrites the plan's
+ * solver workspaces. */
+int cs_admm_backward(cs_grad* grad, const cs_c64* grad_x, cs_c64* grad_y, float* grad_lambda_mu,
+                     cs_stream stream);
+
 /* Per-kernel device timing, a profiling aid for callers that report kernel
  * throughput.  cs_kernel_timing(plan, 1) starts bracketing every launch of
  * the per-iteration kernels made by cs_admm_solve with a pair of hipEvents on

@@ -48,6 +48,10 @@ EXPORTED = (
     "cs_batch_size",
     "cs_batch_plan",
     "cs_batch_solve",
+    "cs_grad_create",
+    "cs_grad_destroy",
+    "cs_admm_forward_ckpt",
+    "cs_admm_backward",
 )
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -132,6 +136,10 @@ def load() -> ctypes.CDLL:
     lib.cs_batch_size.argtypes = [vp, ctypes.POINTER(i32)]
     lib.cs_batch_plan.argtypes = [vp, i32, ctypes.POINTER(vp)]
     lib.cs_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(f32), i32, ctypes.POINTER(vp), vp]
+    lib.cs_grad_create.argtypes = [vp, i32, i32, ctypes.POINTER(vp)]
+    lib.cs_grad_destroy.argtypes = [vp]
+    lib.cs_admm_forward_ckpt.argtypes = [vp, vp, f32, f32, vp, vp]
+    lib.cs_admm_backward.argtypes = [vp, vp, vp, vp, vp]
     for name in EXPORTED:
         if name not in ("cs_status_string", "cs_last_error"):
             getattr(lib, name).restype = ctypes.c_int

@@ -165,7 +165,7 @@ static int run_phase_graph(cs_plan* p, int32_t iters, float lambda, float mu, fl
   return CS_OK;
 }
 
-static int run_iterations(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
+int run_iterations(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
                           const float2* wgiven, hipStream_t s) {
   if (!J_trace && (p->desc.flags & CS_FLAG_COLUMN_RESIDENT) && column_solve_supported(p)) {
     if (iters == 0) return CS_OK;

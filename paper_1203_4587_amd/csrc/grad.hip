@@ -1,0 +1,387 @@
+// Reverse-mode differentiation of unrolled Algorithm 2 (temporal TV): the
+// checkpointed forward and the adjoint sweep behind cs_admm_forward_ckpt /
+// cs_admm_backward.
+//
+// One iteration of Algorithm 2 (Sec. IV-B), with D = D_t (eq. TV),
+// T = rho I + D'D, W = (mu I + H'H)^{-1} (eq. eigen_mu), tau = lambda/(2 mu1):
+//     a = D m + d1;  v = soft(a, tau);  m' = T^{-1}[D'(v - d1) + rho (x + d2)]
+//     x' = W [H'y + mu (m' - d2)];  d1' = d1 - (v - D m');  d2' = d2 - (m' - x')
+// Its transposed Jacobian, given the adjoints (mb', d1b', d2b', xb') of the
+// state after it (gradients in the dL/dRe + i dL/dIm convention):
+//     bb  = W (xb' + d2b')                          W Hermitian
+//     q   = mb' - d2b' + D' d1b' + mu bb           adjoint of m', T^{-1} applied next
+//     rb  = T^{-1} q                                T real symmetric
+//     vb  = D rb - d1b'
+//     ab  = (dsoft/da)^T vb                         real 2x2 Jacobian on |a| > tau
+//     mb  = D' ab;  d1b = d1b' - D rb + ab;  xb = rho rb;  d2b = d2b' - mu bb + rho rb
+//     dL/dH'y += bb;  dL/dtau += -sum_{|a|>tau} Re(conj(a/|a|) vb)
+//     dL/dmu  += Re<bb, m' - d2 - x'> = -Re<bb, d2'>     (the rhs term plus dW/dmu = -W^2)
+// and at the end x_0 = m_0 = H'y adds mb + xb to dL/dH'y, tau = lambda rho/(2 mu)
+// turns dL/dtau into dL/dlambda and dL/dmu, and dL/dy = A(dL/dH'y).
+//
+// Kernels: the x-update kernel applies W (bb = W e with e = xb' + d2b'); one
+// per-pixel kernel does everything else (three passes over the pixel's frames:
+// the Thomas sweep, the back substitution, then the elementwise tail), with
+// per-workgroup FP64 partial sums of dL/dtau and dL/dmu that each workgroup
+// accumulates in its own slot (no atomics; summed in a fixed order at the end).
+#include <algorithm>
+#include <new>
+
+#include "internal.hpp"
+
+namespace csmri {
+
+int run_iterations(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace, const float2* wgiven,
+                   hipStream_t s);
+
+constexpr int kAdjThreads = 64;
+
+template <int NT>
+__global__ __launch_bounds__(kAdjThreads) void k_tv_adjoint(
+    float2* __restrict__ mb, float2* __restrict__ d1b, float2* __restrict__ d2b, float2* __restrict__ e,
+    const float2* __restrict__ bb, float2* __restrict__ hyb, const float2* __restrict__ m,
+    const float2* __restrict__ d1, const float2* __restrict__ d2n, const float* __restrict__ invden,
+    double* __restrict__ partial, int nt, size_t npix, float tau, float rho, float mu, int last) {
+  const size_t p = (size_t)blockIdx.x * kAdjThreads + threadIdx.x;
+  double tsum = 0.0, msum = 0.0;
+  if (p < npix) {
+    float2 C[NT];
+    // pass 1: q_t = mb'_t - d2b'_t + (D' d1b')_t + mu bb_t, forward Thomas sweep
+    float2 wprev = make_float2(0.f, 0.f), c = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (t < nt) {
+        const size_t o = (size_t)t * npix + p;
+        const float2 w = t < nt - 1 ? d1b[o] : make_float2(0.f, 0.f);
+        const float2 a = mb[o], z = d2b[o], b = bb[o];
+        const float2 q = make_float2(fmaf(mu, b.x, (a.x - z.x) + (wprev.x - w.x)),
+                                     fmaf(mu, b.y, (a.y - z.y) + (wprev.y - w.y)));
+        wprev = w;
+        const float iv = invden[t];
+        c = make_float2((q.x + c.x) * iv, (q.y + c.y) * iv);
+        C[t] = c;
+      }
+    }
+    // pass 2: back substitution rb_t = c_t + invden_t rb_{t+1}
+    float2 rnext = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int t = NT - 1; t >= 0; --t) {
+      if (t < nt) {
+        float2 r = C[t];
+        if (t < nt - 1) {
+          const float iv = invden[t];
+          r = make_float2(fmaf(iv, rnext.x, r.x), fmaf(iv, rnext.y, r.y));
+        }
+        C[t] = r;
+        rnext = r;
+      }
+    }
+    // pass 3: soft-threshold adjoint, new adjoint state, accumulators
+    float2 abprev = make_float2(0.f, 0.f);
+    float2 mcur = m[p];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (t < nt) {
+        const size_t o = (size_t)t * npix + p;
+        float2 ab = make_float2(0.f, 0.f);
+        if (t + 1 < NT && t < nt - 1) {
+          const float2 dr = csub(C[t + 1], C[t]);
+          const float2 w = d1b[o];
+          const float2 vb = csub(dr, w);
+          const float2 mnext = m[o + npix];
+          const float2 dd = d1[o];
+          // same arithmetic as the forward step, so the same |a| > tau decision
+          const float2 a = make_float2(mnext.x - mcur.x + dd.x, mnext.y - mcur.y + dd.y);
+          mcur = mnext;
+          const float mag = sqrtf(fmaf(a.x, a.x, a.y * a.y));
+          if (mag > tau) {
+            const float sdot = fmaf(a.x, vb.x, a.y * vb.y) / mag;  // Re(conj(a/|a|) vb)
+            const float k = tau / mag;
+            const float ks = k * sdot / mag;
+            ab = make_float2(fmaf(1.f - k, vb.x, ks * a.x), fmaf(1.f - k, vb.y, ks * a.y));
+            tsum -= (double)sdot;
+          }
+          d1b[o] = cadd(csub(w, dr), ab);
+        }
+        const float2 mnew = csub(abprev, ab);  // (D' ab)_t = ab_{t-1} - ab_t
+        abprev = ab;
+        const float2 b = bb[o], z = d2b[o], r = C[t], dn = d2n[o];
+        const float2 xb = make_float2(rho * r.x, rho * r.y);
+        const float2 z2 = make_float2(fmaf(-mu, b.x, z.x) + xb.x, fmaf(-mu, b.y, z.y) + xb.y);
+        d2b[o] = z2;
+        e[o] = cadd(xb, z2);
+        mb[o] = mnew;
+        float2 h = cadd(hyb[o], b);
+        if (last) h = cadd(h, cadd(mnew, xb));  // x_0 = m_0 = H'y
+        hyb[o] = h;
+        msum -= (double)fmaf(b.x, dn.x, b.y * dn.y);
+      }
+    }
+  }
+  __shared__ double red[2][kAdjThreads];
+  red[0][threadIdx.x] = tsum;
+  red[1][threadIdx.x] = msum;
+  __syncthreads();
+  for (int w = kAdjThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] += red[0][0];
+    partial[2 * blockIdx.x + 1] += red[1][0];
+  }
+}
+
+// dL/dlambda and dL/dmu from the accumulated dL/dtau and direct dL/dmu
+__global__ __launch_bounds__(256) void k_grad_finish(const double* __restrict__ partial, int nslots,
+                                                     float* __restrict__ out, double lambda, double mu,
+                                                     double rho) {
+  __shared__ double red[2][256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nslots; i += 256) {
+    a += partial[2 * i];
+    b += partial[2 * i + 1];
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double gtau = red[0][0], gmu = red[1][0];
+    out[0] = (float)(gtau * rho / (2.0 * mu));
+    out[1] = (float)(gmu - gtau * lambda * rho / (2.0 * mu * mu));
+  }
+}
+
+template <int NT>
+static void adjoint_launch(unsigned blocks, hipStream_t s, float2* mb, float2* d1b, float2* d2b, float2* e,
+                           const float2* bb, float2* hyb, const float2* m, const float2* d1, const float2* d2n,
+                           const float* invden, double* partial, int nt, size_t npix, float tau, float rho,
+                           float mu, int last) {
+  hipLaunchKernelGGL(k_tv_adjoint<NT>, dim3(blocks), dim3(kAdjThreads), 0, s, mb, d1b, d2b, e, bb, hyb, m, d1,
+                     d2n, invden, partial, nt, npix, tau, rho, mu, last);
+}
+
+}  // namespace csmri
+
+using namespace csmri;
+
+struct cs_grad {
+  cs_plan* plan = nullptr;
+  int iters = 0, every = 1, nseg = 0;
+  size_t nimg = 0, npix = 0;
+  float lambda = 0.f, mu = 0.f;
+  bool ready = false;
+  std::vector<void*> owned;
+  float2* hy = nullptr;
+  std::vector<float2*> ck;          // [nseg][4]: m, d1, x, d2 at the start of each segment
+  std::vector<float2*> tm, td1, td2;  // [every + 1]: m_j, d1_j (before step j+1), d2_j
+  float2 *mb = nullptr, *d1b = nullptr, *d2b = nullptr, *e = nullptr, *bb = nullptr, *hyb = nullptr;
+  double* partial = nullptr;
+  int nslots = 0;
+};
+
+static void grad_release(cs_grad* g) {
+  if (!g) return;
+  for (void* ptr : g->owned) g->plan->alloc.put(ptr);
+  delete g;
+}
+
+static int grad_alloc(cs_grad* g, float2** out, size_t count) {
+  void* ptr = g->plan->alloc.get(std::max<size_t>(count * sizeof(float2), 256));
+  if (!ptr) return set_error(CS_ENOMEM, "allocator returned NULL for the gradient workspace");
+  g->owned.push_back(ptr);
+  *out = static_cast<float2*>(ptr);
+  return CS_OK;
+}
+
+// one Algorithm 2 iteration on the plan's state, exactly as cs_admm_solve runs it
+static int one_iteration(cs_plan* p, float lambda, float mu, hipStream_t s) {
+  return run_iterations(p, 1, lambda, mu, nullptr, nullptr, s);
+}
+
+static int ensure_mu(cs_plan* p, float mu, hipStream_t s) {
+  if (mu == p->mu) return CS_OK;
+  if (p->desc.flags & CS_FLAG_NO_REFACTOR) return set_error(CS_EMU_MISMATCH, "mu differs from the plan's mu");
+  return build_factor(p, mu, s);
+}
+
+extern "C" {
+
+int cs_grad_create(cs_plan* p, int32_t iters, int32_t every, cs_grad** out) {
+  if (!out) return set_error(CS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p) return set_error(CS_EINVAL, "plan is NULL");
+  if (p->desc.prior != CS_PRIOR_TEMPORAL_TV)
+    return set_error(CS_EUNSUPPORTED, "differentiation is implemented for the temporal TV prior");
+  if (iters < 0) return set_error(CS_EINVAL, "iters must be >= 0");
+  if (every < 1) return set_error(CS_EINVAL, "ckpt_every must be >= 1");
+  cs_grad* g = new (std::nothrow) cs_grad();
+  if (!g) return set_error(CS_ENOMEM, "host allocation failed");
+  g->plan = p;
+  g->iters = iters;
+  g->every = std::min(every, std::max(iters, 1));
+  g->nseg = (iters + g->every - 1) / g->every;
+  g->npix = (size_t)p->desc.nv * p->desc.nh;
+  g->nimg = g->npix * p->desc.nt;
+  g->nslots = (int)((g->npix + kAdjThreads - 1) / kAdjThreads);
+  int st = CS_OK;
+  auto A = [&](float2** q) {
+    if (st == CS_OK) st = grad_alloc(g, q, g->nimg);
+  };
+  CS_HIP(hipSetDevice(p->device));
+  A(&g->hy);
+  g->ck.assign((size_t)g->nseg * 4, nullptr);
+  for (auto& q : g->ck) A(&q);
+  g->tm.assign(g->every + 1, nullptr);
+  g->td1.assign(g->every + 1, nullptr);
+  g->td2.assign(g->every + 1, nullptr);
+  for (int j = 0; j <= g->every; ++j) {
+    if (j < g->every) {
+      A(&g->tm[j]);
+      A(&g->td1[j]);
+    }
+    if (j > 0) A(&g->td2[j]);
+  }
+  A(&g->mb);
+  A(&g->d1b);
+  A(&g->d2b);
+  A(&g->e);
+  A(&g->bb);
+  A(&g->hyb);
+  if (st == CS_OK) {
+    float2* part = nullptr;
+    st = grad_alloc(g, &part, (size_t)g->nslots * 2);  // 2 doubles per slot
+    g->partial = reinterpret_cast<double*>(part);
+  }
+  if (st != CS_OK) {
+    grad_release(g);
+    return st;
+  }
+  *out = g;
+  return CS_OK;
+}
+
+int cs_grad_destroy(cs_grad* g) {
+  if (!g) return CS_OK;
+  (void)hipSetDevice(g->plan->device);
+  (void)hipDeviceSynchronize();
+  grad_release(g);
+  return CS_OK;
+}
+
+int cs_admm_forward_ckpt(cs_grad* g, const cs_c64* y, float lambda, float mu, cs_c64* x_out, cs_stream stream) {
+  if (!g || !y || !x_out) return set_error(CS_EINVAL, "grad, y and x_out must not be NULL");
+  if (!(lambda >= 0.f && std::isfinite(lambda))) return set_error(CS_EINVAL, "lambda must be finite and >= 0");
+  if (!(mu > 0.f && std::isfinite(mu))) return set_error(CS_EINVAL, "mu must be finite and > 0");
+  cs_plan* p = g->plan;
+  CS_HIP(hipSetDevice(p->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  g->ready = false;
+  int st = ensure_mu(p, mu, s);
+  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
+  const size_t n = g->nimg;
+  const float2 zero = make_float2(0.f, 0.f);
+#define CK(expr)                              \
+  do {                                        \
+    if (st == CS_OK) st = (expr);             \
+  } while (0)
+  CK(launch_adjoint_rows(p, reinterpret_cast<const float2*>(y), s));
+  CK(launch_adjoint_image(p, p->hy, true, s));
+  CK(launch_copy(p->hy, g->hy, n, s));
+  CK(launch_copy(p->hy, p->s0, n, s));  // m = x
+  CK(launch_copy(p->hy, p->s2, n, s));  // x = H'y
+  CK(launch_fill(p->s1, n, zero, s));
+  CK(launch_fill(p->s3, n, zero, s));
+  float2* state[4] = {p->s0, p->s1, p->s2, p->s3};
+  for (int seg = 0; seg < g->nseg && st == CS_OK; ++seg) {
+    for (int a = 0; a < 4; ++a) CK(launch_copy(state[a], g->ck[(size_t)seg * 4 + a], n, s));
+    const int L = std::min(g->every, g->iters - seg * g->every);
+    CK(run_iterations(p, L, lambda, mu, nullptr, nullptr, s));
+  }
+  CK(launch_transpose(p->s2, reinterpret_cast<float2*>(x_out), nt, nh, nv, s));
+#undef CK
+  if (st != CS_OK) return st;
+  g->lambda = lambda;
+  g->mu = mu;
+  g->ready = true;
+  return CS_OK;
+}
+
+int cs_admm_backward(cs_grad* g, const cs_c64* grad_x, cs_c64* grad_y, float* grad_lambda_mu, cs_stream stream) {
+  if (!g || !grad_x || !grad_y || !grad_lambda_mu)
+    return set_error(CS_EINVAL, "grad, grad_x, grad_y and grad_lambda_mu must not be NULL");
+  if (!g->ready) return set_error(CS_EINVAL, "cs_admm_backward needs a preceding cs_admm_forward_ckpt");
+  cs_plan* p = g->plan;
+  CS_HIP(hipSetDevice(p->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const float lambda = g->lambda, mu = g->mu, rho = p->desc.mu_ratio;
+  const float tau = lambda * rho / (2.0f * mu);  // as the forward step computes it
+  int st = ensure_mu(p, mu, s);
+  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
+  const size_t n = g->nimg;
+  const float2 zero = make_float2(0.f, 0.f);
+#define CK(expr)                              \
+  do {                                        \
+    if (st == CS_OK) st = (expr);             \
+  } while (0)
+  CK(launch_transpose(reinterpret_cast<const float2*>(grad_x), g->e, nt, nv, nh, s));  // e = xb_K + d2b_K
+  CK(launch_fill(g->mb, n, zero, s));
+  CK(launch_fill(g->d1b, n, zero, s));
+  CK(launch_fill(g->d2b, n, zero, s));
+  CK(launch_fill(g->hyb, n, zero, s));
+  CK(launch_fill(reinterpret_cast<float2*>(g->partial), (size_t)g->nslots * 2, zero, s));
+  CK(launch_copy(g->hy, p->hy, n, s));  // the plan may have solved something else since
+  float2* state[4] = {p->s0, p->s1, p->s2, p->s3};
+  const unsigned blocks = (unsigned)g->nslots;
+  for (int seg = g->nseg - 1; seg >= 0 && st == CS_OK; --seg) {
+    const int L = std::min(g->every, g->iters - seg * g->every);
+    for (int a = 0; a < 4; ++a) CK(launch_copy(g->ck[(size_t)seg * 4 + a], state[a], n, s));
+    for (int j = 0; j < L; ++j) {  // recompute the segment, keeping what the adjoint needs
+      CK(launch_copy(p->s0, g->tm[j], n, s));
+      CK(launch_copy(p->s1, g->td1[j], n, s));
+      CK(one_iteration(p, lambda, mu, s));
+      CK(launch_copy(p->s3, g->td2[j + 1], n, s));
+    }
+    for (int j = L - 1; j >= 0 && st == CS_OK; --j) {
+      CK(launch_block_solve(p, kSolvePlain, g->e, nullptr, nullptr, g->bb, mu, s));  // bb = W e
+      if (st != CS_OK) break;
+      const int last = (seg == 0 && j == 0) ? 1 : 0;
+      auto go = [&](auto tag) {
+        constexpr int NT = decltype(tag)::value;
+        adjoint_launch<NT>(blocks, s, g->mb, g->d1b, g->d2b, g->e, g->bb, g->hyb, g->tm[j], g->td1[j],
+                           g->td2[j + 1], p->tv_invden, g->partial, nt, g->npix, tau, rho, mu, last);
+      };
+      if (nt <= 8) go(std::integral_constant<int, 8>{});
+      else if (nt <= 16) go(std::integral_constant<int, 16>{});
+      else if (nt <= 24) go(std::integral_constant<int, 24>{});
+      else if (nt <= 32) go(std::integral_constant<int, 32>{});
+      else if (nt <= 40) go(std::integral_constant<int, 40>{});
+      else if (nt <= 48) go(std::integral_constant<int, 48>{});
+      else go(std::integral_constant<int, 64>{});
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) st = hip_fail(e, "k_tv_adjoint");
+    }
+  }
+  if (g->iters == 0) CK(launch_copy(g->e, g->hyb, n, s));  // x_K = x_0 = H'y
+  if (st == CS_OK) {
+    hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(256), 0, s, g->partial, g->nslots, grad_lambda_mu,
+                       (double)lambda, (double)mu, (double)rho);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) st = hip_fail(e, "k_grad_finish");
+  }
+  CK(launch_forward(p, g->hyb, true, reinterpret_cast<float2*>(grad_y), s));  // dL/dy = A(dL/dH'y)
+#undef CK
+  return st;
+}
+
+}  // extern "C"

@@ -151,3 +151,12 @@ def test_batch_calls_reject_bad_arguments(lib):
     assert lib.cs_batch_plan(None, 0, ctypes.byref(p)) == _lib.CS_EINVAL
     assert lib.cs_batch_solve(None, None, None, 10, None, None) == _lib.CS_EINVAL
     assert lib.cs_batch_destroy(None) == _lib.CS_OK
+
+
+def test_gradient_calls_reject_bad_arguments(lib):
+    h = ctypes.c_void_p()
+    assert lib.cs_grad_create(None, 20, 5, ctypes.byref(h)) == _lib.CS_EINVAL
+    assert lib.cs_grad_create(FAKE, 20, 5, None) == _lib.CS_EINVAL
+    assert lib.cs_admm_forward_ckpt(None, FAKE, 0.01, 0.1, FAKE, None) == _lib.CS_EINVAL
+    assert lib.cs_admm_backward(None, FAKE, FAKE, FAKE, None) == _lib.CS_EINVAL
+    assert lib.cs_grad_destroy(None) == _lib.CS_OK
