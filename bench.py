@@ -101,6 +101,116 @@ def cpu_baseline(problem, cols: int, iters: int) -> dict:
     }
 
 
+def _median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def batched_vs_plain(iters: int, reps: int = 3) -> dict:
+    """The 24-slice uneven workload (128x96x16 8-coil R=4 up to 256x256x40
+    16-coil R=10, both priors): one cs_batch_solve of `iters` iterations per
+    slice against the 24 plain cs_admm_solve calls back to back on the same
+    plans, each tuned first (cs_plan_tune).  Slice-iterations per second,
+    median of `reps` timed runs after one warm-up each."""
+    import torch
+    from paper_1203_4587_amd import synthetic as S
+    from paper_1203_4587_amd.api import Batch, Slice, to_device
+
+    probs = [S.batch_slice(s) for s in range(24)]
+    slices = [Slice(to_device(p.coil), to_device(p.mask, dtype=torch.uint8), p.prior, p.mu, p.rho) for p in probs]
+    t0 = time.perf_counter()
+    batch = Batch(slices)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    plans = [batch.plan(i) for i in range(24)]
+    ys = [plans[i].apply_A(to_device(p.x_true)) + to_device(p.noise) for i, p in enumerate(probs)]
+    lams = [p.lam for p in probs]
+    for i in range(24):
+        plans[i].tune(ys[i], lams[i], iters=5)
+    outs = [torch.empty(plans[i].image_shape, dtype=torch.complex64, device="cuda") for i in range(24)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return _median(ts)
+
+    t_batch = timed(lambda: batch.solve(ys, lams, iters, outs=outs))
+    t_plain = timed(lambda: [plans[i].solve(ys[i], lams[i], iters, out=outs[i]) for i in range(24)])
+    alg = 0
+    for p in probs:
+        nt, nv, nh = p.x_true.shape
+        img = 8 * nv * nh * nt
+        alg += 8 * nh * nt * nv * (nv + 1) // 2 + (11 if p.prior == "tv" else 9) * img
+    total = 24 * iters
+    res = {
+        "workload": "24 uneven slices, 128x96x16 8c R4 .. 256x256x40 16c R10, TV and DFT alternating",
+        "iterations_per_slice": iters,
+        "batched_slice_iter_per_s": round(total / t_batch, 1),
+        "plain_slice_iter_per_s": round(total / t_plain, 1),
+        "speedup": round(t_plain / t_batch, 3),
+        "batched_iter_per_s": round(iters / t_batch, 2),
+        "algorithmic_GBps": round(alg * iters / t_batch / 1e9, 1),
+        "hbm_frac": round(alg * iters / t_batch / 1e9 / HBM_PEAK_GBS, 4),
+        "algorithmic_bytes_per_batched_iteration": alg,
+        "plans_s": round(t_plan, 2),
+        "forms": sorted({int(p.flags) for p in plans}),
+        "timing": f"median of {reps} runs, setup H'y included, host clock around device sync",
+    }
+    batch.close()
+    return res
+
+
+def unrolled_throughput(reps: int) -> dict:
+    """K = 20 unrolled temporal-TV iterations on the 192x192x24, 12-coil, R=8
+    workload with a checkpoint every 5: forward (cs_admm_forward_ckpt) and
+    forward + backward (cs_admm_backward) passes per second, median of reps."""
+    import torch
+    from paper_1203_4587_amd import synthetic as S
+    from paper_1203_4587_amd.api import Plan, to_device
+    from paper_1203_4587_amd.autograd import Unrolled
+
+    pr = S.CONFIGS["tv192_unrolled"]()
+    plan = Plan(to_device(pr.coil), to_device(pr.mask, dtype=torch.uint8), pr.mu, prior="tv", mu_ratio=pr.rho)
+    y = plan.apply_A(to_device(pr.x_true)) + to_device(pr.noise)
+    un = Unrolled(plan, pr.iters, 5)
+    g = torch.randn(plan.image_shape, dtype=torch.complex64, device="cuda")
+
+    def fwd():
+        un.forward_raw(y, pr.lam, pr.mu)
+
+    def fb():
+        un.forward_raw(y, pr.lam, pr.mu)
+        un.backward_raw(g)
+
+    res = {}
+    for name, fn in (("forward", fwd), ("forward_backward", fb)):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        res[f"{name}_per_s"] = round(1.0 / _median(ts), 2)
+        res[f"{name}_ms"] = round(1e3 * _median(ts), 3)
+    nt, nv, nh = pr.x_true.shape
+    res.update({
+        "workload": "tv-192x192x24-12c R8, K=20 unrolled, checkpoint every 5",
+        "backward_over_forward": round(res["forward_backward_ms"] / res["forward_ms"] - 1.0, 3),
+        "factor_bytes": 8 * nh * nt * nv * (nv + 1) // 2,
+    })
+    un.close()
+    plan.close()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +222,10 @@ def main() -> int:
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--batched-iters", type=int, default=100, help="iterations per slice in that comparison")
+    ap.add_argument("--no-unrolled", action="store_true", help="skip the differentiated-solve measurement")
+    ap.add_argument("--unrolled-reps", type=int, default=10, help="timed forward+backward passes")
     ap.add_argument("--column-resident", action="store_true",
                     help="one launch for all iterations (a workgroup per readout column) instead of two "
                          "launches per iteration")
@@ -242,11 +356,21 @@ def main() -> int:
         },
         "plan_s": round(t_plan, 3),
     }
+    plan.close()
+    del x, y
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        log("batched vs plain: 24 uneven slices ...")
+        line["batched"] = batched_vs_plain(args.batched_iters)
+        torch.cuda.empty_cache()
+    if not args.no_unrolled:
+        log("differentiated unrolled solve ...")
+        line["unrolled"] = unrolled_throughput(args.unrolled_reps)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a column sample ...")
         line["cpu_baseline"] = cpu_baseline(problem, args.cpu_cols, args.cpu_iters)
     print(json.dumps(line), flush=True)
-    plan.close()
     return 0
 
 

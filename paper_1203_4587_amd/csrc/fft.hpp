@@ -20,14 +20,14 @@ constexpr int kFftMaxBfly = 8;        // kFftElems / 2 / kFftThreads: butterflie
                                       // a radix-2 pass, the most of any radix
 
 template <int SIGN>
-__device__ inline float2 twiddle(float2 u, float2 w) {
+__device__ __forceinline__ float2 twiddle(float2 u, float2 w) {
   // w = exp(-2 pi i q / n) from the table; the inverse transform uses conj(w)
   return SIGN < 0 ? cmul(u, w) : cmulc(w, u);
 }
 
 // Loads one butterfly's inputs, applies twiddles and the r-point DFT.
 template <int SIGN>
-__device__ inline void fft_butterfly(const float2* s, int nr, int r, int tq, const float2* tw,
+__device__ __forceinline__ void fft_butterfly(const float2* s, int nr, int r, int tq, const float2* tw,
                                      float2* v) {
   if (r == 4) {
     float2 u0 = s[0], u1 = s[nr], u2 = s[2 * nr], u3 = s[3 * nr];

@@ -15,20 +15,20 @@
 namespace csmri {
 
 // ---------------------------------------------------------------- complex
-__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 // complex products with explicit FMAs (the library is built without implicit
 // contraction, so these round identically in every kernel)
-__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 // conj(a) * b
-__host__ __device__ inline float2 cmulc(float2 a, float2 b) {
+__host__ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.x, b.y, -(a.y * b.x)));
 }
 // acc + a * b
-__host__ __device__ inline float2 cfma(float2 a, float2 b, float2 acc) {
+__host__ __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 acc) {
   acc.x = fmaf(a.x, b.x, acc.x);
   acc.x = fmaf(-a.y, b.y, acc.x);
   acc.y = fmaf(a.x, b.y, acc.y);
@@ -36,18 +36,18 @@ __host__ __device__ inline float2 cfma(float2 a, float2 b, float2 acc) {
   return acc;
 }
 // acc + conj(a) * b
-__host__ __device__ inline float2 cfmac(float2 a, float2 b, float2 acc) {
+__host__ __device__ __forceinline__ float2 cfmac(float2 a, float2 b, float2 acc) {
   acc.x = fmaf(a.x, b.x, acc.x);
   acc.x = fmaf(a.y, b.y, acc.x);
   acc.y = fmaf(a.x, b.y, acc.y);
   acc.y = fmaf(-a.y, b.x, acc.y);
   return acc;
 }
-__host__ __device__ inline double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__host__ __device__ inline double2 zmul(double2 a, double2 b) {
+__host__ __device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
-__host__ __device__ inline double2 zfma(double2 a, double2 b, double2 acc) {
+__host__ __device__ __forceinline__ double2 zfma(double2 a, double2 b, double2 acc) {
   acc.x = fma(a.x, b.x, acc.x);
   acc.x = fma(-a.y, b.y, acc.x);
   acc.y = fma(a.x, b.y, acc.y);
@@ -55,20 +55,20 @@ __host__ __device__ inline double2 zfma(double2 a, double2 b, double2 acc) {
   return acc;
 }
 // acc - a * b
-__host__ __device__ inline double2 zfms(double2 a, double2 b, double2 acc) {
+__host__ __device__ __forceinline__ double2 zfms(double2 a, double2 b, double2 acc) {
   acc.x = fma(-a.x, b.x, acc.x);
   acc.x = fma(a.y, b.y, acc.x);
   acc.y = fma(-a.x, b.y, acc.y);
   acc.y = fma(-a.y, b.x, acc.y);
   return acc;
 }
-__host__ __device__ inline double2 zrecip(double2 a) {
+__host__ __device__ __forceinline__ double2 zrecip(double2 a) {
   double d = fma(a.x, a.x, a.y * a.y);
   return make_double2(a.x / d, -a.y / d);
 }
 
 // Complex soft threshold: (|a| - tau) a / |a| if |a| > tau, else 0.
-__device__ inline float2 soft_threshold(float2 a, float tau) {
+__device__ __forceinline__ float2 soft_threshold(float2 a, float tau) {
   float mag = sqrtf(fmaf(a.x, a.x, a.y * a.y));
   if (!(mag > tau)) return make_float2(0.f, 0.f);
   float s = (mag - tau) / mag;
@@ -91,10 +91,10 @@ struct FactorLayout {
   int glog;
   size_t nblk;
 };
-__host__ __device__ inline size_t diag_offset(const FactorLayout& L, size_t blk, int s) {
+__host__ __device__ __forceinline__ size_t diag_offset(const FactorLayout& L, size_t blk, int s) {
   return ((((size_t)(s >> L.glog) * L.nblk + blk) << L.glog) + (size_t)(s & ((1 << L.glog) - 1))) * L.n;
 }
-__host__ __device__ inline size_t half_offset(const FactorLayout& L, size_t blk) {
+__host__ __device__ __forceinline__ size_t half_offset(const FactorLayout& L, size_t blk) {
   return (size_t)L.F * L.n * L.nblk + blk * (size_t)(L.n / 2);
 }
 inline FactorLayout make_factor_layout(int n, size_t nblk) {

@@ -27,13 +27,13 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // streaming (non-temporal) 16-byte load: the factor is read once per
 // iteration and is far larger than the caches, so it should not evict the
 // iterates, which are reused by the next kernel
-__device__ inline float4 ld_stream4(const float2* p) {
+__device__ __forceinline__ float4 ld_stream4(const float2* p) {
   const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
   return make_float4(v.x, v.y, v.z, v.w);
 }
 
 template <int MODE>
-__device__ inline float2 rhs_value(const float2* hy, const float2* m, const float2* d2, size_t q, float mu,
+__device__ __forceinline__ float2 rhs_value(const float2* hy, const float2* m, const float2* d2, size_t q, float mu,
                                    float2& mk, float2& dk) {
   const float2 h = hy[q];
   if (MODE == kSolvePlain) return h;
@@ -131,7 +131,7 @@ struct DiagChunk {
 };
 
 template <int UNR, int RP>
-__device__ inline void load_chunk(DiagChunk<UNR, RP>& ch, const float2* __restrict__ W, const FactorLayout& L,
+__device__ __forceinline__ void load_chunk(DiagChunk<UNR, RP>& ch, const float2* __restrict__ W, const FactorLayout& L,
                                   size_t blk, int s0, int lane) {
   const int h = L.n >> 1;
 #pragma unroll
@@ -145,7 +145,7 @@ __device__ inline void load_chunk(DiagChunk<UNR, RP>& ch, const float2* __restri
 }
 
 template <int UNR, int RP>
-__device__ inline void apply_chunk(const DiagChunk<UNR, RP>& ch, const FactorLayout& L, int s0, int lane,
+__device__ __forceinline__ void apply_chunk(const DiagChunk<UNR, RP>& ch, const FactorLayout& L, int s0, int lane,
                                    const float2* bsh, float2* dsh, float2 (&a0)[RP], float2 (&a1)[RP]) {
   const int n = L.n, h = n >> 1;
 #pragma unroll
@@ -183,7 +183,7 @@ __device__ inline void apply_chunk(const DiagChunk<UNR, RP>& ch, const FactorLay
 }
 
 template <int MODE, int UNR, int RP>
-__device__ inline void xupdate_wave_block(const float2* __restrict__ W, const FactorLayout& L, size_t blk, int lane,
+__device__ __forceinline__ void xupdate_wave_block(const float2* __restrict__ W, const FactorLayout& L, size_t blk, int lane,
                                           float2* bsh, float2* dsh, const float2* hy, const float2* __restrict__ m,
                                           float2* __restrict__ d2, float2* x, float mu) {
   const int n = L.n, h = n >> 1, F = L.F;
@@ -341,7 +341,7 @@ int launch_block_solve(cs_plan* p, int mode, const float2* hy, const float2* m, 
 // arithmetic so that all its loads are in flight together: a 256x256 image
 // has only one wave per SIMD, so latency has to be hidden inside the wave.
 template <int NT>
-__device__ inline void tv_pixel(float2* __restrict__ m, float2* __restrict__ d1, const float2* __restrict__ x,
+__device__ __forceinline__ void tv_pixel(float2* __restrict__ m, float2* __restrict__ d1, const float2* __restrict__ x,
                                 const float2* __restrict__ d2, const float* __restrict__ invden, int nt,
                                 size_t npix, size_t p, float tau, float rho) {
   float2 M[NT], E[NT], R[NT];
@@ -394,7 +394,7 @@ __device__ inline void tv_pixel(float2* __restrict__ m, float2* __restrict__ d1,
 }
 
 template <int NT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tv_step(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_tv_step(
     float2* __restrict__ m, float2* __restrict__ d1, const float2* __restrict__ x, const float2* __restrict__ d2,
     const float* __restrict__ invden, int nt, size_t npix, float tau, float rho) {
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -464,7 +464,7 @@ struct DftTile {
 
 // acc[m] = sum_k Ahat(m, k) Bhat(k), Bhat = tile[KP][16] in LDS
 template <int KP>
-__device__ inline void tile_gemm(const float* __restrict__ frag, const float* tile, int lane,
+__device__ __forceinline__ void tile_gemm(const float* __restrict__ frag, const float* tile, int lane,
                                  mfma_v4 (&acc)[DftTile<KP>::MT]) {
   constexpr int MT = DftTile<KP>::MT, KS = DftTile<KP>::KS;
 #pragma unroll
@@ -481,13 +481,21 @@ __device__ inline void tile_gemm(const float* __restrict__ frag, const float* ti
 
 // stage 16 pixels' series (rows 2t, 2t+1 = re, im of frame t) into tile[KP][16]
 template <int KP>
-__device__ inline void tile_stage(float* tile, const float2* __restrict__ src, int nt, size_t npix, size_t p0,
+__device__ __forceinline__ void tile_stage(float* tile, const float2* __restrict__ src, int nt, size_t npix, size_t p0,
                                   int count, int lane) {
   const int col = lane & 15, grp = lane >> 4;
-  for (int t = grp; t < KP / 2; t += 4) {
-    const float2 a = (t < nt && col < count) ? src[(size_t)t * npix + p0 + col] : make_float2(0.f, 0.f);
-    tile[(2 * t) * 16 + col] = a.x;
-    tile[(2 * t + 1) * 16 + col] = a.y;
+  constexpr int NK = KP / 8;  // frames t = grp + 4k per lane
+  float2 r[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {  // every load in flight before the first LDS store
+    const int t = grp + 4 * k;
+    r[k] = (t < nt && col < count) ? src[(size_t)t * npix + p0 + col] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int t = grp + 4 * k;
+    tile[(2 * t) * 16 + col] = r[k].x;
+    tile[(2 * t + 1) * 16 + col] = r[k].y;
   }
   __builtin_amdgcn_wave_barrier();
 }
@@ -500,7 +508,7 @@ enum DftTileMode { kDftStep = 0, kDftForward = 1, kDftAdjoint = 2 };
 //   kDftForward: out = Psi in; with dual != null also dual <- dual - (out - v).
 //   kDftAdjoint: out = Psi' in.
 template <int KP, int MODE>
-__device__ inline void dft_tile(const float* __restrict__ fragF, const float* __restrict__ fragH, float* tile,
+__device__ __forceinline__ void dft_tile(const float* __restrict__ fragF, const float* __restrict__ fragH, float* tile,
                                 const float2* __restrict__ in, float2* __restrict__ d, float2* __restrict__ v,
                                 float2* __restrict__ out, const float2* __restrict__ wgiven, int nt, size_t npix,
                                 size_t p0, int count, float tau, int first, int lane) {
@@ -509,6 +517,20 @@ __device__ inline void dft_tile(const float* __restrict__ fragF, const float* __
   const bool pv = col < count;
   const size_t p = p0 + col;
   mfma_v4 acc[MT];
+  // the step's dual and shrinkage operands of this lane's frequencies are
+  // loaded up front, so that their latency overlaps the staging and the MFMAs
+  float2 dpre[MT][2], vpre[MT][2];
+  if (MODE == kDftStep) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int f = 8 * m + 2 * grp + h;
+        const bool ok = f < nt && pv;
+        dpre[m][h] = ok ? d[(size_t)f * npix + p] : make_float2(0.f, 0.f);
+        vpre[m][h] = (ok && !first) ? v[(size_t)f * npix + p] : make_float2(0.f, 0.f);
+      }
+  }
   if (MODE == kDftStep && wgiven) {
 #pragma unroll
     for (int m = 0; m < MT; ++m)
@@ -552,9 +574,9 @@ __device__ inline void dft_tile(const float* __restrict__ fragF, const float* __
       float2 q = make_float2(0.f, 0.f);
       if (f < nt && pv) {
         const float2 w = make_float2(acc[m][2 * h], acc[m][2 * h + 1]);
-        float2 df = d[(size_t)f * npix + p];
+        float2 df = dpre[m][h];
         if (!first) {
-          const float2 vp = v[(size_t)f * npix + p];
+          const float2 vp = vpre[m][h];
           df = make_float2(df.x - (w.x - vp.x), df.y - (w.y - vp.y));
         }
         const float2 vf = soft_threshold(csub(w, df), tau);
@@ -578,9 +600,26 @@ __device__ inline void dft_tile(const float* __restrict__ fragF, const float* __
 }
 
 // copy both fragment matrices into LDS (all threads of the workgroup)
+// (16-byte aligned on both sides; batches of loads in flight before their stores)
 template <int KP>
-__device__ inline void load_frags(float* dst, const float* __restrict__ src) {
-  for (int q = threadIdx.x; q < 2 * DftTile<KP>::FRAG; q += blockDim.x) dst[q] = src[q];
+__device__ __forceinline__ void load_frags(float* dst, const float* __restrict__ src) {
+  constexpr int N4 = 2 * DftTile<KP>::FRAG / 4;
+  constexpr int BATCH = 8;
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+  float4* d4 = reinterpret_cast<float4*>(dst);
+  for (int q0 = threadIdx.x; q0 < N4; q0 += BATCH * blockDim.x) {
+    float4 r[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int q = q0 + u * blockDim.x;
+      r[u] = q < N4 ? s4[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int q = q0 + u * blockDim.x;
+      if (q < N4) d4[q] = r[u];
+    }
+  }
 }
 
 // phase-kernel form: blockDim/64 waves per workgroup, pixel tiles of 16 in a grid-stride loop
@@ -861,7 +900,7 @@ int launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s) {
 constexpr int kJBlocks = 512;
 constexpr int kJThreads = 256;
 
-__device__ inline void block_reduce_store(double v, double* out) {
+__device__ __forceinline__ void block_reduce_store(double v, double* out) {
   __shared__ double red[kJThreads];
   red[threadIdx.x] = v;
   __syncthreads();
