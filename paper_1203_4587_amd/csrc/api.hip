@@ -305,7 +305,7 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
   // fragment (m, k) holds A[16 m + l % 16][4 k + l / 16].
   const int kp = (2 * nt + 15) / 16 * 16;
   const int kmt = kp / 16, kks = kp / 4;
-  std::vector<float> hfrag((size_t)2 * kmt * kks * 64, 0.f);
+  std::vector<float> hfrag((size_t)kmt * kks * 64, 0.f);
   {
     std::vector<double> E((size_t)kp * kp, 0.0);
     for (int f = 0; f < nt; ++f)
@@ -317,14 +317,12 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
         E[(size_t)(2 * f + 1) * kp + 2 * t] = im;
         E[(size_t)(2 * f + 1) * kp + 2 * t + 1] = re;
       }
-    for (int mat = 0; mat < 2; ++mat)
-      for (int mm = 0; mm < kmt; ++mm)
-        for (int kk = 0; kk < kks; ++kk)
-          for (int l = 0; l < 64; ++l) {
-            const int r = 16 * mm + l % 16, c = 4 * kk + l / 16;
-            const double val = mat == 0 ? E[(size_t)r * kp + c] : E[(size_t)c * kp + r];
-            hfrag[(size_t)mat * kmt * kks * 64 + ((size_t)mm * kks + kk) * 64 + l] = (float)val;
-          }
+    for (int mm = 0; mm < kmt; ++mm)
+      for (int kk = 0; kk < kks; ++kk)
+        for (int l = 0; l < 64; ++l) {
+          const int r = 16 * mm + l % 16, c = 4 * kk + l / 16;
+          hfrag[((size_t)mm * kks + kk) * 64 + l] = (float)E[(size_t)r * kp + c];
+        }
   }
   // Thomas pivots of rho I + D'D: den_0 = b_0, den_t = b_t - 1/den_{t-1}
   std::vector<float> hinv(nt, 0.f);

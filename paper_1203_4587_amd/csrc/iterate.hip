@@ -277,7 +277,9 @@ __global__ __launch_bounds__(512) void k_xupdate_rows(const float2* __restrict__
   if (MODE == kSolveTV) d2[base + k] = make_float2(dk.x - (mk.x - acc.x), dk.y - (mk.y - acc.y));
 }
 
-constexpr int kXUnroll = 8;   // diagonals per chunk, phase-form x-update
+// diagonals per chunk of the phase-form x-update: 4 streams faster than 8 on
+// gfx950 (256-row blocks: 353 vs 373 us per 2.24 GB launch), 16 starves occupancy
+constexpr int kXUnroll = 4;
 constexpr int kXUnrollCol = 4;  // diagonals per chunk, column-resident solve (8 waves share a CU's LDS)
 
 // row pairs per lane: nv/2 pairs over 64 lanes
@@ -287,7 +289,7 @@ template <int MODE, int RP>
 static void xupdate_wave_launch(cs_plan* p, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
                                 hipStream_t s) {
   const FactorLayout& L = p->flayout;
-  constexpr int UNR = RP <= 2 ? kXUnroll : kXUnroll / 2;
+  constexpr int UNR = kXUnroll;
   const size_t lds = (size_t)(1 + UNR) * L.n * sizeof(float2);
   hipLaunchKernelGGL((k_xupdate_wave<MODE, UNR, RP>), dim3((unsigned)L.nblk), dim3(64), lds, s, p->factor, L, hy,
                      m, d2, x, mu);
@@ -450,8 +452,9 @@ int launch_tv_step(cs_plan* p, float lambda, float mu, hipStream_t s) {
 // (lane l holds A[l % 16][l / 16]), B = 4 rows x 16 pixels of zhat staged in
 // LDS (lane l holds B[l / 16][l % 16]), accumulator lane l holds
 // D[4 (l / 16) + v][l % 16], v < 4, i.e. the real and imaginary parts of two
-// consecutive frequencies of pixel l % 16.  The A fragments of Psihat and of
-// Psihat' (adjoint) are built on the host in FP64 and held in LDS.
+// consecutive frequencies of pixel l % 16.  The A fragments of Psihat are
+// built on the host in FP64 and held in LDS; the adjoint reuses them (see
+// tile_gemm).
 
 typedef float mfma_v4 __attribute__((ext_vector_type(4)));
 
@@ -462,20 +465,27 @@ struct DftTile {
   static constexpr int FRAG = MT * KS * 64;  // floats per matrix
 };
 
-// acc[m] = sum_k Ahat(m, k) Bhat(k), Bhat = tile[KP][16] in LDS
-template <int KP>
+// acc[m] = sum_k Ahat(m, k) Bhat(k), Bhat = tile[KP][16] in LDS.  Only the
+// fragments of Psihat are stored: Psi is symmetric, so the embedding of
+// Psi' = conj(Psi) is Psihat with its off-diagonal entries of every 2x2 block
+// negated, which for the A operand is a per-lane sign (row parity l & 1 against
+// column parity (l >> 4) & 1) applied when ADJ.
+template <int KP, bool ADJ>
 __device__ __forceinline__ void tile_gemm(const float* __restrict__ frag, const float* tile, int lane,
-                                 mfma_v4 (&acc)[DftTile<KP>::MT]) {
+                                          mfma_v4 (&acc)[DftTile<KP>::MT]) {
   constexpr int MT = DftTile<KP>::MT, KS = DftTile<KP>::KS;
 #pragma unroll
   for (int m = 0; m < MT; ++m) acc[m] = mfma_v4{0.f, 0.f, 0.f, 0.f};
   const int col = lane & 15, grp = lane >> 4;
+  const unsigned flip = (ADJ && ((lane ^ (lane >> 4)) & 1)) ? 0x80000000u : 0u;
 #pragma unroll 4
   for (int k = 0; k < KS; ++k) {
     const float b = tile[(4 * k + grp) * 16 + col];
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
-      acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(m * KS + k) * 64 + lane], b, acc[m], 0, 0, 0);
+    for (int m = 0; m < MT; ++m) {
+      const float a = __uint_as_float(__float_as_uint(frag[(m * KS + k) * 64 + lane]) ^ flip);
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[m], 0, 0, 0);
+    }
   }
 }
 
@@ -508,7 +518,7 @@ enum DftTileMode { kDftStep = 0, kDftForward = 1, kDftAdjoint = 2 };
 //   kDftForward: out = Psi in; with dual != null also dual <- dual - (out - v).
 //   kDftAdjoint: out = Psi' in.
 template <int KP, int MODE>
-__device__ __forceinline__ void dft_tile(const float* __restrict__ fragF, const float* __restrict__ fragH, float* tile,
+__device__ __forceinline__ void dft_tile(const float* __restrict__ frag, float* tile,
                                 const float2* __restrict__ in, float2* __restrict__ d, float2* __restrict__ v,
                                 float2* __restrict__ out, const float2* __restrict__ wgiven, int nt, size_t npix,
                                 size_t p0, int count, float tau, int first, int lane) {
@@ -543,7 +553,7 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ fragF, const 
       }
   } else {
     tile_stage<KP>(tile, in, nt, npix, p0, count, lane);
-    tile_gemm<KP>(MODE == kDftAdjoint ? fragH : fragF, tile, lane, acc);
+    tile_gemm<KP, MODE == kDftAdjoint>(frag, tile, lane, acc);
     __builtin_amdgcn_wave_barrier();
   }
   if (MODE != kDftStep) {
@@ -588,7 +598,7 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ fragF, const 
       tile[(row + 1) * 16 + col] = q.y;
     }
   __builtin_amdgcn_wave_barrier();
-  tile_gemm<KP>(fragH, tile, lane, acc);
+  tile_gemm<KP, true>(frag, tile, lane, acc);
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -599,11 +609,11 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ fragF, const 
   __builtin_amdgcn_wave_barrier();
 }
 
-// copy both fragment matrices into LDS (all threads of the workgroup)
+// copy the fragment matrix into LDS (all threads of the workgroup)
 // (16-byte aligned on both sides; batches of loads in flight before their stores)
 template <int KP>
 __device__ __forceinline__ void load_frags(float* dst, const float* __restrict__ src) {
-  constexpr int N4 = 2 * DftTile<KP>::FRAG / 4;
+  constexpr int N4 = DftTile<KP>::FRAG / 4;
   constexpr int BATCH = 8;
   const float4* s4 = reinterpret_cast<const float4*>(src);
   float4* d4 = reinterpret_cast<float4*>(dst);
@@ -629,10 +639,9 @@ __global__ __launch_bounds__(256) void k_dft_tiles(const float* __restrict__ fra
                                                    float2* __restrict__ out, const float2* __restrict__ wgiven,
                                                    int nt, size_t npix, float tau, int first) {
   extern __shared__ float lds_f[];
-  float* fF = lds_f;
-  float* fH = lds_f + DftTile<KP>::FRAG;
+  float* frag = lds_f;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  float* tile = lds_f + 2 * DftTile<KP>::FRAG + wv * KP * 16;
+  float* tile = lds_f + DftTile<KP>::FRAG + wv * KP * 16;
   load_frags<KP>(lds_f, frags);
   __syncthreads();
   const int nw = blockDim.x >> 6;
@@ -640,19 +649,19 @@ __global__ __launch_bounds__(256) void k_dft_tiles(const float* __restrict__ fra
   for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
     const size_t p0 = tl * 16;
     const int count = (int)std::min<size_t>(16, npix - p0);
-    dft_tile<KP, MODE>(fF, fH, tile, in, d, v, out, wgiven, nt, npix, p0, count, tau, first, lane);
+    dft_tile<KP, MODE>(frag, tile, in, d, v, out, wgiven, nt, npix, p0, count, tau, first, lane);
   }
 }
 
 // padded real dimension of the embedded temporal DFT: 2 nt rounded up to 16
 inline int dft_kp(int nt) { return (2 * nt + 15) / 16 * 16; }
 
-// waves per workgroup of the phase kernels: the fragments of both matrices
-// (8 KP^2 bytes) and one KP x 16 tile per wave must fit in LDS
+// waves per workgroup of the phase kernels: the fragment matrix (4 KP^2
+// bytes) and one KP x 16 tile per wave share the workgroup's LDS
 inline int dft_waves(int kp) { return kp <= 96 ? 4 : 2; }
 
 inline size_t dft_lds_bytes(int kp, int waves) {
-  return ((size_t)2 * (kp / 16) * (kp / 4) * 64 + (size_t)waves * kp * 16) * sizeof(float);
+  return ((size_t)(kp / 16) * (kp / 4) * 64 + (size_t)waves * kp * 16) * sizeof(float);
 }
 
 template <int KP, int MODE>
@@ -668,7 +677,9 @@ static int dft_tiles_launch(cs_plan* p, const float2* in, float2* d, float2* v, 
     attr = true;
   }
   const size_t ntiles = (npix + 15) / 16;
-  const unsigned grid = (unsigned)std::min<size_t>((ntiles + waves - 1) / waves, 512);
+  // one tile per wave where the grid fits on the chip at once (the grid-stride
+  // loop covers larger images)
+  const unsigned grid = (unsigned)std::min<size_t>((ntiles + waves - 1) / waves, 2048);
   hipLaunchKernelGGL((k_dft_tiles<KP, MODE>), dim3(grid), dim3(64 * waves), lds, s, p->dft_frags, in, d, v, out,
                      wgiven, p->desc.nt, npix, tau, first);
   CS_HIP(hipGetLastError());
@@ -744,7 +755,7 @@ struct ColumnSolveArgs {
 // 256 VGPRs (up to 40 frames), 256 threads beyond
 // NT: TV frame-count bound; for the DFT prior the padded embedding size KP.
 // Per-wave LDS: `wave_floats` floats (x-update staging, reused as the DFT
-// tile), then the DFT fragments of both matrices.
+// tile), then the DFT fragment matrix.
 template <int PRIOR, int NT, int RP, int MAXT = (PRIOR == CS_PRIOR_TEMPORAL_TV && NT > 40 ? 256 : 512)>
 __global__ __launch_bounds__(MAXT) void k_column_solve(ColumnSolveArgs a) {
   extern __shared__ float2 lds[];
@@ -766,7 +777,7 @@ __global__ __launch_bounds__(MAXT) void k_column_solve(ColumnSolveArgs a) {
         tv_pixel<NT>(a.s0, a.s1, a.s2, a.s3, a.invden, a.nt, npix, (size_t)i * n + j, a.tau, a.rho);
     } else {
       for (int tl = w; tl * 16 < n; tl += nwaves)
-        dft_tile<NT, kDftStep>(frags, frags + DftTile<NT>::FRAG, reinterpret_cast<float*>(bsh), a.s2, a.s0, a.s1,
+        dft_tile<NT, kDftStep>(frags, reinterpret_cast<float*>(bsh), a.s2, a.s0, a.s1,
                                a.s3, k == 0 ? a.wgiven : nullptr, a.nt, npix, (size_t)i * n + 16 * tl,
                                std::min(16, n - 16 * tl), a.tau, k == 0, lane);
     }
@@ -832,7 +843,7 @@ int launch_column_solve(cs_plan* p, int iters, float lambda, float mu, const flo
   // two waves per SIMD fit the temporal step's registers up to 40 frames
   const int max_threads = nt <= 40 ? 512 : 256;  // matches MAXT of k_column_solve
   const int kp = dft_kp(nt);
-  const size_t frag_bytes = tv ? 0 : (size_t)2 * (kp / 16) * (kp / 4) * 64 * sizeof(float);
+  const size_t frag_bytes = tv ? 0 : (size_t)(kp / 16) * (kp / 4) * 64 * sizeof(float);
   a.wave_floats = std::max(2 * (1 + kXUnrollCol) * n, tv ? 0 : kp * 16);
   a.wave_floats = (a.wave_floats + 3) / 4 * 4;  // keep every wave's region 16-byte aligned
   const size_t per_wave = (size_t)a.wave_floats * sizeof(float);
