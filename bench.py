@@ -8,13 +8,16 @@ complex Gaussian noise sigma = 0.005, lambda = 0.01, mu2 = 0.1, mu2/mu1 = 0.5.
 One step = one ADMM iteration (TV step + exact x-update).  The timed region is
 one cs_admm_solve call of --steps iterations from the algorithm's
 initialisation (so it includes the H'y setup and the output write), with every
-input already in HBM; the plan (FP64 factor of (mu I + H'H)^{-1}) is built
-before it, as the paper excludes its SVD time.
+input already in HBM, in the execution form the library's autotuner picked
+beforehand; the plan (FP64 factor of (mu I + H'H)^{-1}) is built before it, as
+the paper excludes its SVD time.
 
 Prints one JSON line on stdout.  Also reports the dominant kernel's roofline
-(x-update, HBM bound) from HIP events recorded on its launch stream during the
-timed region, and the FP64 CPU oracle timed on the host cores on a bounded
-sample of the same workload.
+(x-update, HBM bound) from HIP events recorded on its launch stream around
+every launch of a second timed solve of the same length (events cannot sit
+inside a replayed graph, so that solve runs the single-stream phase form), the
+24-slice batched-vs-plain comparison, the unrolled derivative's rate, and the
+FP64 CPU oracle timed on the host cores on a bounded sample of the workload.
 """
 from __future__ import annotations
 
@@ -226,6 +229,7 @@ def main() -> int:
     ap.add_argument("--batched-iters", type=int, default=100, help="iterations per slice in that comparison")
     ap.add_argument("--no-unrolled", action="store_true", help="skip the differentiated-solve measurement")
     ap.add_argument("--unrolled-reps", type=int, default=10, help="timed forward+backward passes")
+    ap.add_argument("--no-tune", action="store_true", help="time the default form instead of the tuned one")
     ap.add_argument("--column-resident", action="store_true",
                     help="one launch for all iterations (a workgroup per readout column) instead of two "
                          "launches per iteration")
@@ -271,17 +275,32 @@ def main() -> int:
         torch.cuda.synchronize()
         del a, b
 
+    tuned = None
+    if not args.column_resident and not args.no_tune:
+        # the library's autotuner picks the execution form (x-update form, graph
+        # replay, column groups on concurrent branches) on this data, untimed
+        tuned = plan.tune(y, problem.lam, iters=10)
+        log(f"tuned form: flags {tuned['flags']} of {len(tuned['candidates'])} candidates")
     if args.warmup:
         plan.solve(y, problem.lam, args.warmup)
     x = torch.empty(plan.image_shape, dtype=torch.complex64, device="cuda")
     torch.cuda.synchronize()
 
-    plan.kernel_timing(True)
-    torch.cuda.synchronize()
+    # timed region: one solve of --steps iterations in the chosen form
     t0 = time.perf_counter()
     plan.solve(y, problem.lam, args.steps, out=x)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+
+    # second timed solve of the same length with HIP events around every
+    # launch (single-stream phase form, since events cannot sit inside a
+    # replayed graph): per-kernel durations for the roofline
+    plan.kernel_timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.solve(y, problem.lam, args.steps, out=x)
+    torch.cuda.synchronize()
+    elapsed_events = time.perf_counter() - t1
     ktimes = plan.kernel_times()
     plan.kernel_timing(False)
 
@@ -355,6 +374,12 @@ def main() -> int:
             "iteration_algorithmic_GBps": round((x_bytes + t_bytes) * value / 1e9, 1),
         },
         "plan_s": round(t_plan, 3),
+        "form": {
+            "flags": int(plan.flags),
+            "tuned": tuned is not None,
+            "candidates_ms_per_iter": [[int(f), round(m, 4)] for f, m in tuned["candidates"]] if tuned else None,
+            "event_timed_iter_per_s": round(args.steps / elapsed_events, 2),
+        },
     }
     plan.close()
     del x, y

@@ -51,8 +51,18 @@ __device__ __forceinline__ float2 rhs_value(const float2* hy, const float2* m, c
 // UNR diagonals at a time are staged in LDS behind workgroup barriers.  Used
 // when n/2 is not a multiple of 64, where the wave-per-block form below would
 // leave part of a wave idle on every load.
+// Columns [i0, i0 + w) of an image with nh columns: the launch's block b
+// solves factor/image block (t, i) = (b / w, i0 + b % w), index t * nh + i.
+// The full image is i0 = 0, w = nh, where the mapping is the identity.
+struct ColRange {
+  int i0, w, nh;
+};
+__device__ __forceinline__ size_t range_block(const ColRange& c, unsigned b) {
+  return (size_t)(b / (unsigned)c.w) * c.nh + c.i0 + b % (unsigned)c.w;
+}
+
 template <int MODE, int UNR>
-__global__ __launch_bounds__(256) void k_xupdate_pairs(const float2* __restrict__ W, FactorLayout L,
+__global__ __launch_bounds__(256) void k_xupdate_pairs(const float2* __restrict__ W, FactorLayout L, ColRange cr,
                                                        const float2* hy, const float2* __restrict__ m,
                                                        float2* __restrict__ d2, float2* x, float mu) {
   extern __shared__ float2 lds[];
@@ -61,7 +71,7 @@ __global__ __launch_bounds__(256) void k_xupdate_pairs(const float2* __restrict_
   float2* dsh = lds + n;  // [UNR][n] staged diagonals
   const int l = threadIdx.x;
   const bool act = l < h;
-  const size_t blk = blockIdx.x;
+  const size_t blk = range_block(cr, blockIdx.x);
   const size_t base = blk * (size_t)n;
   const int k0 = 2 * l, k1 = 2 * l + 1;
   float2 b0 = make_float2(0.f, 0.f), b1 = b0, m0 = b0, m1 = b0, e0 = b0, e1 = b0;
@@ -237,23 +247,24 @@ __device__ __forceinline__ void xupdate_wave_block(const float2* __restrict__ W,
 }
 
 template <int MODE, int UNR, int RP>
-__global__ __launch_bounds__(64) void k_xupdate_wave(const float2* __restrict__ W, FactorLayout L, const float2* hy,
-                                                     const float2* __restrict__ m, float2* __restrict__ d2, float2* x,
-                                                     float mu) {
+__global__ __launch_bounds__(64) void k_xupdate_wave(const float2* __restrict__ W, FactorLayout L, ColRange cr,
+                                                     const float2* hy, const float2* __restrict__ m,
+                                                     float2* __restrict__ d2, float2* x, float mu) {
   extern __shared__ float2 lds[];
-  xupdate_wave_block<MODE, UNR, RP>(W, L, blockIdx.x, threadIdx.x, lds, lds + L.n, hy, m, d2, x, mu);
+  xupdate_wave_block<MODE, UNR, RP>(W, L, range_block(cr, blockIdx.x), threadIdx.x, lds, lds + L.n, hy, m, d2, x,
+                                    mu);
 }
 
 // Odd n: lane k owns row k; the rotated c_s[k-s] is re-read from the same
 // diagonal run, which the vector cache serves.
 template <int MODE>
-__global__ __launch_bounds__(512) void k_xupdate_rows(const float2* __restrict__ W, FactorLayout L,
+__global__ __launch_bounds__(512) void k_xupdate_rows(const float2* __restrict__ W, FactorLayout L, ColRange cr,
                                                       const float2* hy, const float2* __restrict__ m,
                                                       float2* __restrict__ d2, float2* x, float mu) {
   extern __shared__ float2 bsh[];
   const int n = L.n;
   const int k = threadIdx.x;
-  const size_t blk = blockIdx.x;
+  const size_t blk = range_block(cr, blockIdx.x);
   const size_t base = blk * (size_t)n;
   float2 bk = make_float2(0.f, 0.f), mk = bk, dk = bk;
   if (k < n) {
@@ -286,46 +297,55 @@ constexpr int kXUnrollCol = 4;  // diagonals per chunk, column-resident solve (8
 inline int pairs_per_lane(int n) { return ((n >> 1) + 63) / 64; }
 
 template <int MODE, int RP>
-static void xupdate_wave_launch(cs_plan* p, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
-                                hipStream_t s) {
+static void xupdate_wave_launch(cs_plan* p, const ColRange& cr, const float2* hy, const float2* m, float2* d2,
+                                float2* x, float mu, hipStream_t s) {
   const FactorLayout& L = p->flayout;
   constexpr int UNR = kXUnroll;
   const size_t lds = (size_t)(1 + UNR) * L.n * sizeof(float2);
-  hipLaunchKernelGGL((k_xupdate_wave<MODE, UNR, RP>), dim3((unsigned)L.nblk), dim3(64), lds, s, p->factor, L, hy,
-                     m, d2, x, mu);
+  const unsigned grid = (unsigned)cr.w * (unsigned)p->desc.nt;
+  hipLaunchKernelGGL((k_xupdate_wave<MODE, UNR, RP>), dim3(grid), dim3(64), lds, s, p->factor, L, cr, hy, m, d2, x,
+                     mu);
 }
 
 template <int MODE>
-static void xupdate_launch(cs_plan* p, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
-                           hipStream_t s) {
+static void xupdate_launch(cs_plan* p, const ColRange& cr, const float2* hy, const float2* m, float2* d2, float2* x,
+                           float mu, hipStream_t s) {
   const FactorLayout& L = p->flayout;
   const int n = L.n;
   const uint32_t f = p->desc.flags;
+  const unsigned grid = (unsigned)cr.w * (unsigned)p->desc.nt;
   const bool wave = (n & 1) == 0 && !(f & CS_FLAG_XU_GROUP) && ((f & CS_FLAG_XU_WAVE) || (n / 2) % 64 == 0);
   if (wave) {
     const int rp = pairs_per_lane(n);
-    if (rp == 1) xupdate_wave_launch<MODE, 1>(p, hy, m, d2, x, mu, s);
-    else if (rp == 2) xupdate_wave_launch<MODE, 2>(p, hy, m, d2, x, mu, s);
-    else xupdate_wave_launch<MODE, 4>(p, hy, m, d2, x, mu, s);
+    if (rp == 1) xupdate_wave_launch<MODE, 1>(p, cr, hy, m, d2, x, mu, s);
+    else if (rp == 2) xupdate_wave_launch<MODE, 2>(p, cr, hy, m, d2, x, mu, s);
+    else xupdate_wave_launch<MODE, 4>(p, cr, hy, m, d2, x, mu, s);
   } else if ((n & 1) == 0) {
     const int wg = (std::max(n / 2, 1) + 63) / 64 * 64;
     const size_t lds = (size_t)(1 + kXUnroll) * n * sizeof(float2);
-    hipLaunchKernelGGL((k_xupdate_pairs<MODE, kXUnroll>), dim3((unsigned)L.nblk), dim3(wg), lds, s, p->factor, L,
-                       hy, m, d2, x, mu);
+    hipLaunchKernelGGL((k_xupdate_pairs<MODE, kXUnroll>), dim3(grid), dim3(wg), lds, s, p->factor, L, cr, hy, m, d2,
+                       x, mu);
   } else {
     const int wg = (n + 63) / 64 * 64;
-    hipLaunchKernelGGL(k_xupdate_rows<MODE>, dim3((unsigned)L.nblk), dim3(wg), (size_t)n * sizeof(float2), s,
-                       p->factor, L, hy, m, d2, x, mu);
+    hipLaunchKernelGGL(k_xupdate_rows<MODE>, dim3(grid), dim3(wg), (size_t)n * sizeof(float2), s, p->factor, L, cr,
+                       hy, m, d2, x, mu);
   }
+}
+
+int launch_block_solve_cols(cs_plan* p, int mode, const float2* hy, const float2* m, float2* d2, float2* x,
+                            float mu, int i0, int i1, hipStream_t s) {
+  if (i1 <= i0) return CS_OK;
+  const ColRange cr{i0, i1 - i0, p->desc.nh};
+  if (mode == kSolveTV) xupdate_launch<kSolveTV>(p, cr, hy, m, d2, x, mu, s);
+  else if (mode == kSolveDFT) xupdate_launch<kSolveDFT>(p, cr, hy, m, d2, x, mu, s);
+  else xupdate_launch<kSolvePlain>(p, cr, hy, m, d2, x, mu, s);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
 }
 
 int launch_block_solve(cs_plan* p, int mode, const float2* hy, const float2* m, float2* d2, float2* x,
                        float mu, hipStream_t s) {
-  if (mode == kSolveTV) xupdate_launch<kSolveTV>(p, hy, m, d2, x, mu, s);
-  else if (mode == kSolveDFT) xupdate_launch<kSolveDFT>(p, hy, m, d2, x, mu, s);
-  else xupdate_launch<kSolvePlain>(p, hy, m, d2, x, mu, s);
-  CS_HIP(hipGetLastError());
-  return CS_OK;
+  return launch_block_solve_cols(p, mode, hy, m, d2, x, mu, 0, p->desc.nh, s);
 }
 
 // ---------------------------------------------------------------- TV step
@@ -398,31 +418,38 @@ __device__ __forceinline__ void tv_pixel(float2* __restrict__ m, float2* __restr
 template <int NT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_tv_step(
     float2* __restrict__ m, float2* __restrict__ d1, const float2* __restrict__ x, const float2* __restrict__ d2,
-    const float* __restrict__ invden, int nt, size_t npix, float tau, float rho) {
-  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < npix) tv_pixel<NT>(m, d1, x, d2, invden, nt, npix, p, tau, rho);
+    const float* __restrict__ invden, int nt, size_t npix, size_t pix0, size_t pix1, float tau, float rho) {
+  const size_t p = pix0 + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < pix1) tv_pixel<NT>(m, d1, x, d2, invden, nt, npix, p, tau, rho);
 }
 
+// pixels of columns [i0, i1): the solver layout puts column i's rows at i*nv .. i*nv + nv - 1
 template <int NT>
-static void tv_launch(cs_plan* p, float tau, float rho, hipStream_t s) {
+static void tv_launch(cs_plan* p, float tau, float rho, int i0, int i1, hipStream_t s) {
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
-  hipLaunchKernelGGL(k_tv_step<NT>, dim3((unsigned)((npix + 63) / 64)), dim3(64), 0, s, p->s0, p->s1, p->s2,
-                     p->s3, p->tv_invden, p->desc.nt, npix, tau, rho);
+  const size_t pix0 = (size_t)i0 * p->desc.nv, pix1 = (size_t)i1 * p->desc.nv;
+  hipLaunchKernelGGL(k_tv_step<NT>, dim3((unsigned)((pix1 - pix0 + 63) / 64)), dim3(64), 0, s, p->s0, p->s1, p->s2,
+                     p->s3, p->tv_invden, p->desc.nt, npix, pix0, pix1, tau, rho);
 }
 
-int launch_tv_step(cs_plan* p, float lambda, float mu, hipStream_t s) {
+int launch_tv_step_cols(cs_plan* p, float lambda, float mu, int i0, int i1, hipStream_t s) {
+  if (i1 <= i0) return CS_OK;
   const float rho = p->desc.mu_ratio;
   const float tau = lambda * rho / (2.0f * mu);  // lambda / (2 mu1), mu1 = mu / rho
   const int nt = p->desc.nt;
-  if (nt <= 8) tv_launch<8>(p, tau, rho, s);
-  else if (nt <= 16) tv_launch<16>(p, tau, rho, s);
-  else if (nt <= 24) tv_launch<24>(p, tau, rho, s);
-  else if (nt <= 32) tv_launch<32>(p, tau, rho, s);
-  else if (nt <= 40) tv_launch<40>(p, tau, rho, s);
-  else if (nt <= 48) tv_launch<48>(p, tau, rho, s);
-  else tv_launch<64>(p, tau, rho, s);
+  if (nt <= 8) tv_launch<8>(p, tau, rho, i0, i1, s);
+  else if (nt <= 16) tv_launch<16>(p, tau, rho, i0, i1, s);
+  else if (nt <= 24) tv_launch<24>(p, tau, rho, i0, i1, s);
+  else if (nt <= 32) tv_launch<32>(p, tau, rho, i0, i1, s);
+  else if (nt <= 40) tv_launch<40>(p, tau, rho, i0, i1, s);
+  else if (nt <= 48) tv_launch<48>(p, tau, rho, i0, i1, s);
+  else tv_launch<64>(p, tau, rho, i0, i1, s);
   CS_HIP(hipGetLastError());
   return CS_OK;
+}
+
+int launch_tv_step(cs_plan* p, float lambda, float mu, hipStream_t s) {
+  return launch_tv_step_cols(p, lambda, mu, 0, p->desc.nh, s);
 }
 
 // ---------------------------------------------------------------- DFT step
@@ -637,7 +664,8 @@ template <int KP, int MODE>
 __global__ __launch_bounds__(256) void k_dft_tiles(const float* __restrict__ frags, const float2* __restrict__ in,
                                                    float2* __restrict__ d, float2* __restrict__ v,
                                                    float2* __restrict__ out, const float2* __restrict__ wgiven,
-                                                   int nt, size_t npix, float tau, int first) {
+                                                   int nt, size_t npix, size_t pix0, size_t pix1, float tau,
+                                                   int first) {
   extern __shared__ float lds_f[];
   float* frag = lds_f;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -645,10 +673,10 @@ __global__ __launch_bounds__(256) void k_dft_tiles(const float* __restrict__ fra
   load_frags<KP>(lds_f, frags);
   __syncthreads();
   const int nw = blockDim.x >> 6;
-  const size_t ntiles = (npix + 15) / 16;
+  const size_t ntiles = (pix1 - pix0 + 15) / 16;
   for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
-    const size_t p0 = tl * 16;
-    const int count = (int)std::min<size_t>(16, npix - p0);
+    const size_t p0 = pix0 + tl * 16;
+    const int count = (int)std::min<size_t>(16, pix1 - p0);
     dft_tile<KP, MODE>(frag, tile, in, d, v, out, wgiven, nt, npix, p0, count, tau, first, lane);
   }
 }
@@ -666,8 +694,9 @@ inline size_t dft_lds_bytes(int kp, int waves) {
 
 template <int KP, int MODE>
 static int dft_tiles_launch(cs_plan* p, const float2* in, float2* d, float2* v, float2* out, const float2* wgiven,
-                            float tau, int first, hipStream_t s) {
+                            float tau, int first, int i0, int i1, hipStream_t s) {
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
+  const size_t pix0 = (size_t)i0 * p->desc.nv, pix1 = (size_t)i1 * p->desc.nv;
   const int waves = dft_waves(KP);
   const size_t lds = dft_lds_bytes(KP, waves);
   static bool attr = false;
@@ -676,40 +705,47 @@ static int dft_tiles_launch(cs_plan* p, const float2* in, float2* d, float2* v, 
                                (int)lds));
     attr = true;
   }
-  const size_t ntiles = (npix + 15) / 16;
+  const size_t ntiles = (pix1 - pix0 + 15) / 16;
   // one tile per wave where the grid fits on the chip at once (the grid-stride
   // loop covers larger images)
   const unsigned grid = (unsigned)std::min<size_t>((ntiles + waves - 1) / waves, 2048);
   hipLaunchKernelGGL((k_dft_tiles<KP, MODE>), dim3(grid), dim3(64 * waves), lds, s, p->dft_frags, in, d, v, out,
-                     wgiven, p->desc.nt, npix, tau, first);
+                     wgiven, p->desc.nt, npix, pix0, pix1, tau, first);
   CS_HIP(hipGetLastError());
   return CS_OK;
 }
 
 template <int MODE>
 static int dft_tiles_dispatch(cs_plan* p, const float2* in, float2* d, float2* v, float2* out,
-                              const float2* wgiven, float tau, int first, hipStream_t s) {
+                              const float2* wgiven, float tau, int first, int i0, int i1, hipStream_t s) {
+  if (i1 <= i0) return CS_OK;
   switch (dft_kp(p->desc.nt)) {
-    case 16: return dft_tiles_launch<16, MODE>(p, in, d, v, out, wgiven, tau, first, s);
-    case 32: return dft_tiles_launch<32, MODE>(p, in, d, v, out, wgiven, tau, first, s);
-    case 48: return dft_tiles_launch<48, MODE>(p, in, d, v, out, wgiven, tau, first, s);
-    case 64: return dft_tiles_launch<64, MODE>(p, in, d, v, out, wgiven, tau, first, s);
-    case 80: return dft_tiles_launch<80, MODE>(p, in, d, v, out, wgiven, tau, first, s);
-    case 96: return dft_tiles_launch<96, MODE>(p, in, d, v, out, wgiven, tau, first, s);
-    case 112: return dft_tiles_launch<112, MODE>(p, in, d, v, out, wgiven, tau, first, s);
-    default: return dft_tiles_launch<128, MODE>(p, in, d, v, out, wgiven, tau, first, s);
+    case 16: return dft_tiles_launch<16, MODE>(p, in, d, v, out, wgiven, tau, first, i0, i1, s);
+    case 32: return dft_tiles_launch<32, MODE>(p, in, d, v, out, wgiven, tau, first, i0, i1, s);
+    case 48: return dft_tiles_launch<48, MODE>(p, in, d, v, out, wgiven, tau, first, i0, i1, s);
+    case 64: return dft_tiles_launch<64, MODE>(p, in, d, v, out, wgiven, tau, first, i0, i1, s);
+    case 80: return dft_tiles_launch<80, MODE>(p, in, d, v, out, wgiven, tau, first, i0, i1, s);
+    case 96: return dft_tiles_launch<96, MODE>(p, in, d, v, out, wgiven, tau, first, i0, i1, s);
+    case 112: return dft_tiles_launch<112, MODE>(p, in, d, v, out, wgiven, tau, first, i0, i1, s);
+    default: return dft_tiles_launch<128, MODE>(p, in, d, v, out, wgiven, tau, first, i0, i1, s);
   }
 }
 
-int launch_dft_step(cs_plan* p, float lambda, float mu, int first, const float2* wgiven, hipStream_t s) {
+int launch_dft_step_cols(cs_plan* p, float lambda, float mu, int first, const float2* wgiven, int i0, int i1,
+                         hipStream_t s) {
   const float tau = lambda / (2.0f * mu);
-  return dft_tiles_dispatch<kDftStep>(p, p->s2, p->s0, p->s1, p->s3, wgiven, tau, first, s);
+  return dft_tiles_dispatch<kDftStep>(p, p->s2, p->s0, p->s1, p->s3, wgiven, tau, first, i0, i1, s);
+}
+
+int launch_dft_step(cs_plan* p, float lambda, float mu, int first, const float2* wgiven, hipStream_t s) {
+  return launch_dft_step_cols(p, lambda, mu, first, wgiven, 0, p->desc.nh, s);
 }
 
 int launch_dft_apply(cs_plan* p, const float2* in, float2* out, float2* dual, const float2* v, int adjoint,
                      hipStream_t s) {
-  if (adjoint) return dft_tiles_dispatch<kDftAdjoint>(p, in, nullptr, nullptr, out, nullptr, 0.f, 0, s);
-  return dft_tiles_dispatch<kDftForward>(p, in, dual, const_cast<float2*>(v), out, nullptr, 0.f, 0, s);
+  const int nh = p->desc.nh;
+  if (adjoint) return dft_tiles_dispatch<kDftAdjoint>(p, in, nullptr, nullptr, out, nullptr, 0.f, 0, 0, nh, s);
+  return dft_tiles_dispatch<kDftForward>(p, in, dual, const_cast<float2*>(v), out, nullptr, 0.f, 0, 0, nh, s);
 }
 
 // Frame-count instantiations of the remaining per-pixel kernel (objective).
