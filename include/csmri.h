@@ -77,13 +77,6 @@ enum {
                                         whole waves) solves a block.  With neither XU flag the wave
                                         form is used when nv/2 is a multiple of 64.  All x-update
                                         forms give bit-identical results. */
-  CS_FLAG_SPLIT2 = 1u << 5,          /* phase form: the readout columns are split into 2 (SPLIT4: 4) groups
-                                        whose iterations are recorded as concurrent branches of one graph
-                                        (cached like CS_FLAG_GRAPH); the groups' kernels fill each other's
-                                        launch gaps.  Not while cs_kernel_timing is on, with a J_trace,
-                                        or inside a caller's stream capture such as a batch (the plain
-                                        loop is used there).  Same results. */
-  CS_FLAG_SPLIT4 = 1u << 6,
 };
 
 /* Device-memory allocator used for everything the plan owns.  alloc returns

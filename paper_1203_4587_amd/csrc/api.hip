@@ -63,27 +63,18 @@ static void plan_release(cs_plan* p) {
   if (!p) return;
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
-  if (p->split_fork) {
-    (void)hipEventDestroy(p->split_fork);
-    for (int r = 0; r < cs_plan::kMaxSplits; ++r) {
-      if (p->split_stream[r]) (void)hipStreamDestroy(p->split_stream[r]);
-      if (p->split_join[r]) (void)hipEventDestroy(p->split_join[r]);
-    }
-  }
   for (void* ptr : p->owned) p->alloc.put(ptr);
   p->owned.clear();
   delete p;
 }
 
-static constexpr uint32_t kAllFlags = CS_FLAG_NO_REFACTOR | CS_FLAG_GRAPH | CS_FLAG_COLUMN_RESIDENT |
-                                      CS_FLAG_XU_WAVE | CS_FLAG_XU_GROUP | CS_FLAG_SPLIT2 | CS_FLAG_SPLIT4;
+static constexpr uint32_t kAllFlags =
+    CS_FLAG_NO_REFACTOR | CS_FLAG_GRAPH | CS_FLAG_COLUMN_RESIDENT | CS_FLAG_XU_WAVE | CS_FLAG_XU_GROUP;
 
 static int validate_flags(uint32_t f) {
   if (f & ~kAllFlags) return set_error(CS_EINVAL, "unknown flag bits");
   if ((f & CS_FLAG_XU_WAVE) && (f & CS_FLAG_XU_GROUP))
     return set_error(CS_EINVAL, "CS_FLAG_XU_WAVE and CS_FLAG_XU_GROUP are exclusive");
-  if ((f & CS_FLAG_SPLIT2) && (f & CS_FLAG_SPLIT4))
-    return set_error(CS_EINVAL, "CS_FLAG_SPLIT2 and CS_FLAG_SPLIT4 are exclusive");
   return CS_OK;
 }
 
@@ -135,65 +126,13 @@ static int timed_launch(cs_plan* p, int kind, hipStream_t s, F launch) {
 static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
                           const float2* wgiven, hipStream_t s);
 
-static int split_count(const cs_plan* p) {
-  if (p->desc.flags & CS_FLAG_SPLIT4) return std::min(4, p->desc.nh);
-  if (p->desc.flags & CS_FLAG_SPLIT2) return std::min(2, p->desc.nh);
-  return 1;
-}
-
-// The phase-kernel loop on `splits` groups of readout columns, each group's
-// iterations on its own stream forked from and joined back to `s` (used while
-// recording a graph, where the groups become independent branches).  Columns
-// never interact under a temporal prior, so the groups need no synchronisation
-// with each other and every value is computed exactly as in the single loop.
-static int run_split_loop(cs_plan* p, int32_t iters, float lambda, float mu, const float2* wgiven, int splits,
-                          hipStream_t s) {
-  const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
-  const int nh = p->desc.nh;
-  if (!p->split_fork) return set_error(CS_EDEVICE, "column-split streams were not created before recording");
-  CS_HIP(hipEventRecord(p->split_fork, s));
-  int st = CS_OK;
-  for (int r = 0; r < splits && st == CS_OK; ++r) {
-    hipStream_t sr = p->split_stream[r];
-    CS_HIP(hipStreamWaitEvent(sr, p->split_fork, 0));
-    const int i0 = (int)((int64_t)nh * r / splits), i1 = (int)((int64_t)nh * (r + 1) / splits);
-    for (int k = 0; k < iters && st == CS_OK; ++k) {
-      if (tv) {
-        st = launch_tv_step_cols(p, lambda, mu, i0, i1, sr);
-        if (st == CS_OK) st = launch_block_solve_cols(p, kSolveTV, p->hy, p->s0, p->s3, p->s2, mu, i0, i1, sr);
-      } else {
-        st = launch_dft_step_cols(p, lambda, mu, k == 0 ? 1 : 0, k == 0 ? wgiven : nullptr, i0, i1, sr);
-        if (st == CS_OK) st = launch_block_solve_cols(p, kSolveDFT, p->hy, p->s3, nullptr, p->s2, mu, i0, i1, sr);
-      }
-    }
-    if (st == CS_OK) {
-      CS_HIP(hipEventRecord(p->split_join[r], sr));
-      CS_HIP(hipStreamWaitEvent(s, p->split_join[r], 0));
-    }
-  }
-  return st;
-}
-
-// streams and events of the column-split form, created outside any capture
-static int ensure_split_streams(cs_plan* p) {
-  if (p->split_fork) return CS_OK;
-  for (int r = 0; r < cs_plan::kMaxSplits; ++r) {
-    CS_HIP(hipStreamCreateWithFlags(&p->split_stream[r], hipStreamNonBlocking));
-    CS_HIP(hipEventCreateWithFlags(&p->split_join[r], hipEventDisableTiming));
-  }
-  CS_HIP(hipEventCreateWithFlags(&p->split_fork, hipEventDisableTiming));
-  return CS_OK;
-}
-
-// CS_FLAG_GRAPH / CS_FLAG_SPLIT2 / CS_FLAG_SPLIT4: the phase-kernel loop is
-// captured once per distinct (iters, lambda, mu, J_trace, wgiven, splits) and
-// replayed from the plan's cache
+// CS_FLAG_GRAPH: the phase-kernel loop is captured once per distinct
+// (iters, lambda, mu, J_trace, wgiven) and replayed from the plan's cache
 static int run_phase_graph(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
-                           const float2* wgiven, int splits, hipStream_t s) {
+                           const float2* wgiven, hipStream_t s) {
   float lm[2] = {lambda, mu};
   void* key[8] = {reinterpret_cast<void*>((intptr_t)iters), nullptr, J_trace, const_cast<float2*>(wgiven),
-                  reinterpret_cast<void*>((intptr_t)(wgiven != nullptr)), reinterpret_cast<void*>((intptr_t)splits),
-                  nullptr, nullptr};
+                  reinterpret_cast<void*>((intptr_t)(wgiven != nullptr)), nullptr, nullptr, nullptr};
   std::memcpy(&key[1], lm, sizeof(lm));
   if (!p->graph || std::memcmp(key, p->graph_key, sizeof(key)) != 0) {
     if (p->graph) {
@@ -204,14 +143,9 @@ static int run_phase_graph(cs_plan* p, int32_t iters, float lambda, float mu, fl
     // recording runs nothing, so it happens on a private stream: the caller's
     // stream may be the null stream, which cannot be captured
     if (!p->capture_stream) CS_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
-    if (splits > 1) {
-      const int es = ensure_split_streams(p);
-      if (es != CS_OK) return es;
-    }
     hipStream_t cs = p->capture_stream;
     CS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    int st = splits > 1 ? run_split_loop(p, iters, lambda, mu, wgiven, splits, cs)
-                        : run_phase_loop(p, iters, lambda, mu, J_trace, wgiven, cs);
+    int st = run_phase_loop(p, iters, lambda, mu, J_trace, wgiven, cs);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     if (st != CS_OK) {
@@ -238,14 +172,11 @@ int run_iterations(cs_plan* p, int32_t iters, float lambda, float mu, float* J_t
     return timed_launch(p, kKindColumn, s, [&] { return launch_column_solve(p, iters, lambda, mu, wgiven, s); });
   }
   // inside a caller's stream capture (a batch, or the caller's own graph) the
-  // plain loop is recorded into that graph: no cached graph, no column split
+  // plain loop is recorded into that graph instead of a cached one
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   CS_HIP(hipStreamIsCapturing(s, &cap));
-  if (cap != hipStreamCaptureStatusNone || p->timing || iters == 0)
-    return run_phase_loop(p, iters, lambda, mu, J_trace, wgiven, s);
-  const int splits = split_count(p);
-  if (!J_trace && splits > 1) return run_phase_graph(p, iters, lambda, mu, nullptr, wgiven, splits, s);
-  if (p->desc.flags & CS_FLAG_GRAPH) return run_phase_graph(p, iters, lambda, mu, J_trace, wgiven, 1, s);
+  if ((p->desc.flags & CS_FLAG_GRAPH) && cap == hipStreamCaptureStatusNone && !p->timing && iters > 0)
+    return run_phase_graph(p, iters, lambda, mu, J_trace, wgiven, s);
   return run_phase_loop(p, iters, lambda, mu, J_trace, wgiven, s);
 }
 
@@ -657,19 +588,14 @@ int cs_plan_tune(cs_plan* p, const cs_c64* y, float lambda, int32_t iters, cs_tu
   CS_HIP(hipSetDevice(p->device));
   hipStream_t s = S(stream);
   const uint32_t keep = p->desc.flags & CS_FLAG_NO_REFACTOR;
-  const uint32_t forms = CS_FLAG_GRAPH | CS_FLAG_COLUMN_RESIDENT | CS_FLAG_XU_WAVE | CS_FLAG_XU_GROUP |
-                         CS_FLAG_SPLIT2 | CS_FLAG_SPLIT4;
+  const uint32_t forms = CS_FLAG_GRAPH | CS_FLAG_COLUMN_RESIDENT | CS_FLAG_XU_WAVE | CS_FLAG_XU_GROUP;
   const uint32_t original = p->desc.flags;
   std::vector<uint32_t> cand;
-  const uint32_t split_opts[3] = {0u, (uint32_t)CS_FLAG_SPLIT2, (uint32_t)CS_FLAG_SPLIT4};
-  for (uint32_t sp : split_opts) {
-    if (sp && p->desc.nh < 2) continue;
-    if (p->desc.nv % 2 == 0) {
-      cand.push_back(CS_FLAG_GRAPH | CS_FLAG_XU_WAVE | sp);
-      cand.push_back(CS_FLAG_GRAPH | CS_FLAG_XU_GROUP | sp);
-    } else {
-      cand.push_back(CS_FLAG_GRAPH | sp);
-    }
+  if (p->desc.nv % 2 == 0) {
+    cand.push_back(CS_FLAG_GRAPH | CS_FLAG_XU_WAVE);
+    cand.push_back(CS_FLAG_GRAPH | CS_FLAG_XU_GROUP);
+  } else {
+    cand.push_back(CS_FLAG_GRAPH);
   }
   if (column_solve_supported(p)) cand.push_back(CS_FLAG_COLUMN_RESIDENT);
   // a fresh start on y: state in the plan's workspaces, x written to img_tmp

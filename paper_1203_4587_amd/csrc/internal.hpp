@@ -182,11 +182,6 @@ struct cs_plan {
   hipGraphExec_t graph = nullptr;  // cached iteration graph
   void* graph_key[8] = {};
   hipStream_t capture_stream = nullptr;  // private stream used only to record graphs
-  // streams and events of the column-split form (CS_FLAG_SPLIT2 / CS_FLAG_SPLIT4), used only while recording
-  static constexpr int kMaxSplits = 4;
-  hipStream_t split_stream[kMaxSplits] = {};
-  hipEvent_t split_join[kMaxSplits] = {};
-  hipEvent_t split_fork = nullptr;
 
   // per-kernel event timing (cs_kernel_timing)
   bool timing = false;
@@ -214,7 +209,7 @@ int build_factor(cs_plan* p, float mu, hipStream_t s);
 int launch_block_solve(cs_plan* p, int mode, const float2* hy, const float2* m, float2* d2,
                        float2* x, float mu, hipStream_t s);
 int launch_tv_step(cs_plan* p, float lambda, float mu, hipStream_t s);
-// the same kernels restricted to the readout columns [i0, i1) (columns never interact)
+// the same kernels restricted to the readout columns [i0, i1) (columns never interact under a temporal prior)
 int launch_block_solve_cols(cs_plan* p, int mode, const float2* hy, const float2* m, float2* d2, float2* x,
                             float mu, int i0, int i1, hipStream_t s);
 int launch_tv_step_cols(cs_plan* p, float lambda, float mu, int i0, int i1, hipStream_t s);

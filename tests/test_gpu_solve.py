@@ -254,39 +254,3 @@ def test_column_form_is_deterministic(shape, prior):
     for _ in range(3):
         assert torch.equal(plan.solve(y, 0.02, 8), ref)
 
-
-SPLIT_CASES = [((64, 32, 10, 4), "tv"), ((64, 32, 12, 3), "dft"), ((96, 9, 8, 3), "tv"), ((48, 3, 6, 2), "dft"),
-               ((27, 12, 5, 2), "tv"), ((192, 16, 40, 3), "dft"), ((128, 2, 4, 2), "tv")]
-
-
-@pytest.mark.parametrize("shape,prior", SPLIT_CASES, ids=[f"{s}-{p}" for s, p in SPLIT_CASES])
-def test_column_split_forms_equal_phase_form(shape, prior):
-    """CS_FLAG_SPLIT2 / CS_FLAG_SPLIT4 run groups of readout columns as
-    concurrent graph branches (uneven groups when nh is not divisible, fewer
-    groups than requested when nh < 4): results, returned state and a resumed
-    solve must equal the single-stream form bit for bit."""
-    from paper_1203_4587_amd import _lib
-    from paper_1203_4587_amd.api import Plan
-    nv, nh, nt, nc = shape
-    fam = "cardiac" if prior == "tv" else "periodic"
-    case = make_case(nv, nh, nt, nc, accel=3, ncenter=2, prior=prior, family=fam, seed=nv * nh + nt)
-    coil, mask, y = case.device()
-    lam, mu, rho = 0.02, 0.1, 0.5
-    names = ("s0", "s1", "s2", "s3")
-    ref = Plan(coil, mask, mu, prior=prior, mu_ratio=rho)
-    sr = ref.new_state()
-    xr = ref.solve(y, lam, 9, state=sr)
-    sr9 = {n: getattr(sr, n).clone() for n in names if getattr(sr, n) is not None}
-    xr2 = ref.solve(y, lam, 4, state=sr)
-    wave = _lib.CS_FLAG_XU_WAVE if nv % 2 == 0 else 0
-    for flags in (_lib.CS_FLAG_SPLIT2, _lib.CS_FLAG_SPLIT4, _lib.CS_FLAG_SPLIT4 | wave):
-        p = Plan(coil, mask, mu, prior=prior, mu_ratio=rho, flags=flags)
-        for rep in range(2):   # the second pass replays the cached graph
-            st = p.new_state()
-            x = p.solve(y, lam, 9, state=st)
-            torch.cuda.synchronize()
-            assert torch.equal(x, xr), (flags, rep)
-            for n, t in sr9.items():
-                assert torch.equal(getattr(st, n), t), (flags, n)
-        x2 = p.solve(y, lam, 4, state=st)   # warm start (the wgiven path for the DFT prior)
-        assert torch.equal(x2, xr2), flags
