@@ -230,6 +230,8 @@ def main() -> int:
     ap.add_argument("--no-unrolled", action="store_true", help="skip the differentiated-solve measurement")
     ap.add_argument("--unrolled-reps", type=int, default=10, help="timed forward+backward passes")
     ap.add_argument("--no-tune", action="store_true", help="time the default form instead of the tuned one")
+    ap.add_argument("--xu-form", choices=["wave", "group"], default=None,
+                    help="force an x-update form (implies --no-tune; used for per-kernel counter passes)")
     ap.add_argument("--column-resident", action="store_true",
                     help="one launch for all iterations (a workgroup per readout column) instead of two "
                          "launches per iteration")
@@ -259,6 +261,9 @@ def main() -> int:
     t0 = time.perf_counter()
     from paper_1203_4587_amd import _lib
     flags = _lib.CS_FLAG_COLUMN_RESIDENT if args.column_resident else 0
+    if args.xu_form:
+        args.no_tune = True
+        flags |= _lib.CS_FLAG_XU_WAVE if args.xu_form == "wave" else _lib.CS_FLAG_XU_GROUP
     plan = Plan(coil, mask, problem.mu, prior=wl["prior"], mu_ratio=problem.rho, flags=flags)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
@@ -332,7 +337,19 @@ def main() -> int:
     achieved = alg_bytes / avg_s / 1e9 if launches else None
     tl, tms = ktimes.get(tkind, (0, 0.0))
     xl, xms = ktimes.get("x_update", (0, 0.0))
-    traffic = measured_traffic(kind, args.workload, args.steps)
+    if kind == "x_update":
+        # which x-update kernel ran (the forms move the same bytes; counters are per kernel)
+        f = plan.flags
+        if nv % 2:
+            family = "rows"
+        elif not (f & _lib.CS_FLAG_XU_GROUP) and ((f & _lib.CS_FLAG_XU_WAVE) or (nv // 2) % 64 == 0):
+            family = "wave"
+        else:
+            family = "pairs"
+        kdesc += f"; kernel k_xupdate_{family}"
+        traffic = measured_traffic(f"x_update_{family}", args.workload, args.steps)
+    else:
+        traffic = measured_traffic(kind, args.workload, args.steps)
 
     line = {
         "metric": METRIC,
