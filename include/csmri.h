@@ -176,6 +176,22 @@ typedef struct {
 int cs_plan_tune(cs_plan* plan, const cs_c64* y, float lambda, int32_t iters, cs_tune_entry* entries,
                  int32_t cap, int32_t* count, cs_stream stream);
 
+/* The paper's stopping rule (Sec. V, eq. r_ratio): iterate until
+ * Delta(k) = (J(k-1) - J(k)) / J(k) < tol, or max_iters iterations.  Delta is
+ * checked every `check_every` iterations (J is evaluated at the last two
+ * iterations of each block of check_every, or at every iteration when
+ * check_every == 1, J(0) being taken at the initial iterate), so the solve
+ * stops at the first multiple of check_every (or at max_iters) where the
+ * test holds.  *iters_done (host) receives the number of iterations run and
+ * *delta (host, nullable) the last Delta evaluated.  Same arguments otherwise
+ * as cs_admm_solve (without J_trace); x_out and state equal what
+ * cs_admm_solve returns for *iters_done iterations, bit for bit.  The phase
+ * form is used whatever the plan's flags.  Synchronises `stream` once per
+ * block to read J back. */
+int cs_admm_solve_until(cs_plan* plan, const cs_c64* y, float lambda, float mu, int32_t max_iters, float tol,
+                        int32_t check_every, cs_c64* x_out, cs_state* state, int32_t* iters_done, float* delta,
+                        cs_stream stream);
+
 /* ---------------------------------------------------------------- batches
  * Many independent slices (uneven sizes, coil counts, sampling, priors) solved
  * together.  Each slice is one plan (as cs_plan_create); cs_batch_solve runs

@@ -35,6 +35,7 @@ EXPORTED = (
     "cs_apply_AH",
     "cs_apply_block_inverse",
     "cs_admm_solve",
+    "cs_admm_solve_until",
     "cs_status_string",
     "cs_last_error",
     "cs_version",
@@ -125,6 +126,8 @@ def load() -> ctypes.CDLL:
     lib.cs_apply_AH.argtypes = [vp, vp, vp, vp]
     lib.cs_apply_block_inverse.argtypes = [vp, vp, vp, vp]
     lib.cs_admm_solve.argtypes = [vp, vp, f32, f32, i32, vp, ctypes.POINTER(CsState), vp, vp]
+    lib.cs_admm_solve_until.argtypes = [vp, vp, f32, f32, i32, f32, i32, vp, ctypes.POINTER(CsState),
+                                         ctypes.POINTER(i32), ctypes.POINTER(f32), vp]
     lib.cs_kernel_timing.argtypes = [vp, ctypes.c_int]
     lib.cs_kernel_times.argtypes = [vp, ctypes.POINTER(CsKernelTime), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.cs_plan_flags.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]

@@ -228,6 +228,28 @@ class Plan:
             _tune_cache_write(cache, key, {"flags": result["flags"], "candidates": cands})
         return result
 
+    def solve_until(self, y: torch.Tensor, lam: float, max_iters: int, tol: float = 1e-3,
+                    check_every: int = 5, mu: float | None = None, state: State | None = None,
+                    out: torch.Tensor | None = None, stream=None):
+        """cs_admm_solve_until: iterate until Delta(k) < tol (checked every
+        `check_every` iterations) or max_iters.  Returns (x, iterations, Delta)."""
+        _need(y, "y", torch.complex64, self.kspace_shape)
+        x = out if out is not None else torch.empty(self.image_shape, dtype=torch.complex64, device=y.device)
+        _need(x, "out", torch.complex64, self.image_shape)
+        cstate = _state_struct(self, state)
+        done = ctypes.c_int32()
+        delta = ctypes.c_float()
+        st = _lib.load().cs_admm_solve_until(self.handle, _ptr(y), float(lam), float(self.mu if mu is None else mu),
+                                             int(max_iters), float(tol), int(check_every), _ptr(x),
+                                             ctypes.byref(cstate) if cstate else None, ctypes.byref(done),
+                                             ctypes.byref(delta), _stream(stream))
+        check(st, "cs_admm_solve_until")
+        if mu is not None:
+            self.mu = float(mu)
+        if cstate is not None:
+            state.iter = int(cstate.iter)
+        return x, int(done.value), float(delta.value)
+
     def new_state(self) -> State:
         return State.empty(self.prior, self.nt, self.nv, self.nh, self.device)
 
@@ -257,6 +279,17 @@ class Plan:
         if cstate is not None:
             state.iter = int(cstate.iter)
         return (x, J[:iters]) if trace else x
+
+
+def _state_struct(plan: "Plan", state: "State | None"):
+    if state is None:
+        return None
+    fr = {"tv": (plan.nt, plan.nt - 1, plan.nt, plan.nt), "dft": (plan.nt, plan.nt, plan.nt, None)}[plan.prior]
+    for name, frames in zip(("s0", "s1", "s2", "s3"), fr):
+        if frames is not None:
+            _need(getattr(state, name), f"state.{name}", torch.complex64, (frames, plan.nv, plan.nh))
+    return CsState(state.s0.data_ptr(), state.s1.data_ptr(), state.s2.data_ptr(),
+                   state.s3.data_ptr() if state.s3 is not None else None, int(state.iter))
 
 
 def _tune_cache_read(path: str) -> dict:

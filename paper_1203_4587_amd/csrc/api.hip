@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <new>
 
 #include "internal.hpp"
@@ -61,6 +62,7 @@ static int plan_alloc(cs_plan* p, T** out, size_t count, const char* what) {
 
 static void plan_release(cs_plan* p) {
   if (!p) return;
+  if (p->jhost) (void)hipHostFree(p->jhost);
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   for (void* ptr : p->owned) p->alloc.put(ptr);
@@ -124,7 +126,7 @@ static int timed_launch(cs_plan* p, int kind, hipStream_t s, F launch) {
 }
 
 static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
-                          const float2* wgiven, hipStream_t s);
+                          const float2* wgiven, hipStream_t s, bool cont = false);
 
 // CS_FLAG_GRAPH: the phase-kernel loop is captured once per distinct
 // (iters, lambda, mu, J_trace, wgiven) and replayed from the plan's cache
@@ -180,8 +182,11 @@ int run_iterations(cs_plan* p, int32_t iters, float lambda, float mu, float* J_t
   return run_phase_loop(p, iters, lambda, mu, J_trace, wgiven, s);
 }
 
+// cont: these iterations continue a loop of the same solve, so the temporal
+// DFT step's first pass also completes the previous iteration's deferred dual
+// update (instead of treating the pass as the solve's first)
 static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
-                          const float2* wgiven, hipStream_t s) {
+                          const float2* wgiven, hipStream_t s, bool cont) {
   const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
   int st = CS_OK;
   for (int k = 0; k < iters && st == CS_OK; ++k) {
@@ -192,7 +197,8 @@ static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, flo
                           [&] { return launch_block_solve(p, kSolveTV, p->hy, p->s0, p->s3, p->s2, mu, s); });
     } else {
       st = timed_launch(p, kKindDFT, s, [&] {
-        return launch_dft_step(p, lambda, mu, k == 0 ? 1 : 0, k == 0 ? wgiven : nullptr, s);
+        const bool first = k == 0 && !cont;
+        return launch_dft_step(p, lambda, mu, first ? 1 : 0, first ? wgiven : nullptr, s);
       });
       if (st == CS_OK)
         st = timed_launch(p, kKindX, s,
@@ -204,6 +210,107 @@ static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, flo
   return st;
 }
 
+
+// ---------------------------------------------------------------- solve pieces
+
+static int solve_check(cs_plan* p, float lambda, float mu, const cs_state* state) {
+  if (!(lambda >= 0.f && std::isfinite(lambda))) return set_error(CS_EINVAL, "lambda must be finite and >= 0");
+  if (!(mu > 0.f && std::isfinite(mu))) return set_error(CS_EINVAL, "mu must be finite and > 0");
+  const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
+  if (state && (!state->s0 || !state->s1 || !state->s2 || (tv && !state->s3)))
+    return set_error(CS_EINVAL, "state arrays must not be NULL");
+  if (state && state->iter < 0) return set_error(CS_EINVAL, "state->iter must be >= 0");
+  return CS_OK;
+}
+
+// refactor if mu changed; H'y (and the hybrid data kept for the objective);
+// the algorithm's initial state or the caller's warm state.  *wgiven is the
+// saved w a warm DFT start hands to its first pass.
+static int solve_setup(cs_plan* p, const cs_c64* y, float mu, const cs_state* state, const float2** wgiven,
+                       hipStream_t s) {
+  const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
+  const bool warm = state && state->iter > 0;
+  int st = CS_OK;
+  if (mu != p->mu) {
+    if (p->desc.flags & CS_FLAG_NO_REFACTOR) return set_error(CS_EMU_MISMATCH, "mu differs from the plan's mu");
+    if ((st = build_factor(p, mu, s)) != CS_OK) return st;
+  }
+  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
+  const size_t nimg = (size_t)nv * nh * nt;
+  const float2 zero = make_float2(0.f, 0.f);
+  auto in_t = [&](const cs_c64* src, float2* dst, int frames) {
+    return launch_transpose(reinterpret_cast<const float2*>(src), dst, frames, nv, nh, s);
+  };
+#define CK(expr)                           \
+  do {                                     \
+    if ((st = (expr)) != CS_OK) return st; \
+  } while (0)
+  CK(launch_adjoint_rows(p, reinterpret_cast<const float2*>(y), s));
+  CK(launch_adjoint_image(p, p->hy, true, s));
+  *wgiven = nullptr;
+  if (tv) {
+    if (warm) {
+      CK(in_t(state->s0, p->s0, nt));
+      CK(in_t(state->s1, p->s1, nt - 1));
+      CK(in_t(state->s2, p->s2, nt));
+      CK(in_t(state->s3, p->s3, nt));
+    } else {
+      CK(launch_copy(p->hy, p->s0, nimg, s));  // m = x
+      CK(launch_copy(p->hy, p->s2, nimg, s));  // x = H'y
+      CK(launch_fill(p->s1, nimg, zero, s));
+      CK(launch_fill(p->s3, nimg, zero, s));
+    }
+  } else {
+    if (warm) {
+      CK(in_t(state->s0, p->img_tmp, nt));                 // w, used as is by the first pass
+      CK(launch_dft_apply(p, p->img_tmp, p->s2, nullptr, nullptr, 1, s));  // z = Psi' w (x_out if iters == 0)
+      CK(in_t(state->s1, p->s1, nt));                      // v
+      CK(in_t(state->s2, p->s0, nt));                      // d
+      *wgiven = p->img_tmp;
+    } else {
+      CK(launch_copy(p->hy, p->s2, nimg, s));  // Psi' w_0 = H'y
+      CK(launch_fill(p->s0, nimg, zero, s));
+      CK(launch_fill(p->s1, nimg, zero, s));
+    }
+  }
+#undef CK
+  return CS_OK;
+}
+
+// x_out and the returned state after `iters` iterations of this call
+static int solve_finish(cs_plan* p, int32_t iters, cs_c64* x_out, cs_state* state, hipStream_t s) {
+  const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
+  const bool warm = state && state->iter > 0;
+  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
+  auto out_t = [&](const float2* src, cs_c64* dst, int frames) {
+    return launch_transpose(src, reinterpret_cast<float2*>(dst), frames, nh, nv, s);
+  };
+  int st = CS_OK;
+#define CK(expr)                           \
+  do {                                     \
+    if ((st = (expr)) != CS_OK) return st; \
+  } while (0)
+  CK(out_t(p->s2, x_out, nt));
+  if (state) {
+    if (tv) {
+      CK(out_t(p->s0, state->s0, nt));
+      CK(out_t(p->s1, state->s1, nt - 1));
+      CK(out_t(p->s2, state->s2, nt));
+      CK(out_t(p->s3, state->s3, nt));
+    } else if (iters > 0 || !warm) {
+      // w = Psi z; after iterations this also completes the deferred dual
+      // update d <- d - (w - v) of the last one.  A warm start with no
+      // iteration leaves the caller's state untouched.
+      CK(launch_dft_apply(p, p->s2, p->img_tmp, iters > 0 ? p->s0 : nullptr, p->s1, 0, s));
+      CK(out_t(p->img_tmp, state->s0, nt));
+      CK(out_t(p->s1, state->s1, nt));
+      CK(out_t(p->s0, state->s2, nt));
+    }
+    state->iter += iters;
+  }
+#undef CK
+  return CS_OK;
+}
 
 }  // namespace csmri
 
@@ -359,7 +466,8 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
       (st = plan_alloc(p, &p->s2, nimg, "state")) ||
       (st = plan_alloc(p, &p->s3, nimg, "state")) ||
       (st = plan_alloc(p, &p->img_tmp, nimg, "image workspace")) ||
-      (st = plan_alloc(p, &p->jpart, (size_t)objective_partial_count(), "objective partials")))
+      (st = plan_alloc(p, &p->jpart, (size_t)objective_partial_count(), "objective partials")) ||
+      (st = plan_alloc(p, &p->jdev, 2, "objective values")))
     return fail(st);
   p->jpart_len = objective_partial_count();
 
@@ -468,83 +576,76 @@ int cs_apply_block_inverse(cs_plan* p, const cs_c64* b, cs_c64* x, cs_stream str
 int cs_admm_solve(cs_plan* p, const cs_c64* y, float lambda, float mu, int32_t iters, cs_c64* x_out,
                   cs_state* state, float* J_trace, cs_stream stream) {
   if (!p || !y || !x_out) return set_error(CS_EINVAL, "plan, y and x_out must not be NULL");
-  if (!(lambda >= 0.f && std::isfinite(lambda))) return set_error(CS_EINVAL, "lambda must be finite and >= 0");
-  if (!(mu > 0.f && std::isfinite(mu))) return set_error(CS_EINVAL, "mu must be finite and > 0");
   if (iters < 0) return set_error(CS_EINVAL, "iters must be >= 0");
-  const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
-  const bool warm = state && state->iter > 0;
-  if (state && (!state->s0 || !state->s1 || !state->s2 || (tv && !state->s3)))
-    return set_error(CS_EINVAL, "state arrays must not be NULL");
-  if (state && state->iter < 0) return set_error(CS_EINVAL, "state->iter must be >= 0");
+  int st = solve_check(p, lambda, mu, state);
+  if (st != CS_OK) return st;
   CS_HIP(hipSetDevice(p->device));
   hipStream_t s = S(stream);
-  int st = CS_OK;
-  if (mu != p->mu) {
-    if (p->desc.flags & CS_FLAG_NO_REFACTOR)
-      return set_error(CS_EMU_MISMATCH, "mu differs from the plan's mu");
-    if ((st = build_factor(p, mu, s)) != CS_OK) return st;
+  const float2* wgiven = nullptr;
+  if ((st = solve_setup(p, y, mu, state, &wgiven, s)) != CS_OK) return st;
+  if ((st = run_iterations(p, iters, lambda, mu, J_trace, wgiven, s)) != CS_OK) return st;
+  return solve_finish(p, iters, x_out, state, s);
+}
+
+int cs_admm_solve_until(cs_plan* p, const cs_c64* y, float lambda, float mu, int32_t max_iters, float tol,
+                        int32_t check_every, cs_c64* x_out, cs_state* state, int32_t* iters_done, float* delta,
+                        cs_stream stream) {
+  if (!p || !y || !x_out || !iters_done) return set_error(CS_EINVAL, "plan, y, x_out and iters_done must not be NULL");
+  if (max_iters < 1) return set_error(CS_EINVAL, "max_iters must be >= 1");
+  if (check_every < 1) return set_error(CS_EINVAL, "check_every must be >= 1");
+  if (!std::isfinite(tol)) return set_error(CS_EINVAL, "tol must be finite");
+  int st = solve_check(p, lambda, mu, state);
+  if (st != CS_OK) return st;
+  CS_HIP(hipSetDevice(p->device));
+  hipStream_t s = S(stream);
+  if (!p->jhost) {
+    void* h = nullptr;
+    CS_HIP(hipHostMalloc(&h, 2 * sizeof(float), hipHostMallocDefault));
+    p->jhost = static_cast<float*>(h);
   }
-  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
-  const size_t nimg = (size_t)nv * nh * nt;
-  const float2 zero = make_float2(0.f, 0.f);
-  auto in_t = [&](const cs_c64* src, float2* dst, int frames) {
-    return launch_transpose(reinterpret_cast<const float2*>(src), dst, frames, nv, nh, s);
-  };
-  auto out_t = [&](const float2* src, cs_c64* dst, int frames) {
-    return launch_transpose(src, reinterpret_cast<float2*>(dst), frames, nh, nv, s);
-  };
-#define CK(expr)                      \
-  do {                                \
-    if ((st = (expr)) != CS_OK) return st; \
-  } while (0)
-  // setup: hybrid data F_h' y (kept for the objective) and H'y in solver layout
-  CK(launch_adjoint_rows(p, reinterpret_cast<const float2*>(y), s));
-  CK(launch_adjoint_image(p, p->hy, true, s));
-  if (tv) {
-    if (warm) {
-      CK(in_t(state->s0, p->s0, nt));
-      CK(in_t(state->s1, p->s1, nt - 1));
-      CK(in_t(state->s2, p->s2, nt));
-      CK(in_t(state->s3, p->s3, nt));
+  const float2* wgiven = nullptr;
+  if ((st = solve_setup(p, y, mu, state, &wgiven, s)) != CS_OK) return st;
+  // blocks of check_every iterations; the last two iterations of a block also
+  // evaluate J, and the solve stops after the first block whose Delta(k) (eq.
+  // r_ratio) falls below tol.  With check_every == 1 every iteration is
+  // checked against the previous one (J(0) is taken at the initial iterate).
+  int32_t k = 0;
+  double last_delta = std::numeric_limits<double>::quiet_NaN();
+  float jprev = 0.f;
+  bool stop = false;
+  while (k < max_iters && !stop && st == CS_OK) {
+    const int32_t n = std::min(check_every, max_iters - k);
+    const float2* wg = k == 0 ? wgiven : nullptr;
+    const bool cont = k > 0;
+    bool have_j0 = true;
+    if (n >= 2) {
+      st = run_phase_loop(p, n - 2, lambda, mu, nullptr, wg, s, cont);
+      if (st == CS_OK) st = run_phase_loop(p, 1, lambda, mu, p->jdev, n > 2 ? nullptr : wg, s, cont || n > 2);
+      if (st == CS_OK) st = run_phase_loop(p, 1, lambda, mu, p->jdev + 1, nullptr, s, true);
+    } else if (k == 0) {
+      st = launch_objective(p, p->s2, lambda, p->jdev, s);
+      if (st == CS_OK) st = run_phase_loop(p, 1, lambda, mu, p->jdev + 1, wg, s, false);
     } else {
-      CK(launch_copy(p->hy, p->s0, nimg, s));  // m = x
-      CK(launch_copy(p->hy, p->s2, nimg, s));  // x = H'y
-      CK(launch_fill(p->s1, nimg, zero, s));
-      CK(launch_fill(p->s3, nimg, zero, s));
+      st = run_phase_loop(p, 1, lambda, mu, p->jdev + 1, nullptr, s, true);
+      have_j0 = false;  // J(k - 1) is the previous block's J
     }
-  } else {
-    if (warm) {
-      CK(in_t(state->s0, p->img_tmp, nt));                 // w, used as is by the first pass
-      CK(launch_dft_apply(p, p->img_tmp, p->s2, nullptr, nullptr, 1, s));  // z = Psi' w (x_out if iters == 0)
-      CK(in_t(state->s1, p->s1, nt));                      // v
-      CK(in_t(state->s2, p->s0, nt));                      // d
-    } else {
-      CK(launch_copy(p->hy, p->s2, nimg, s));  // Psi' w_0 = H'y
-      CK(launch_fill(p->s0, nimg, zero, s));
-      CK(launch_fill(p->s1, nimg, zero, s));
+    if (st != CS_OK) break;
+    k += n;
+    hipError_t e = hipMemcpyAsync(p->jhost, p->jdev, 2 * sizeof(float), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "reading J back");
+      break;
     }
+    const double j0 = have_j0 ? p->jhost[0] : jprev, j1 = p->jhost[1];
+    jprev = p->jhost[1];
+    last_delta = (j0 - j1) / j1;
+    stop = last_delta < (double)tol;
   }
-  CK(run_iterations(p, iters, lambda, mu, J_trace, (!tv && warm) ? p->img_tmp : nullptr, s));
-  CK(out_t(p->s2, x_out, nt));
-  if (state) {
-    if (tv) {
-      CK(out_t(p->s0, state->s0, nt));
-      CK(out_t(p->s1, state->s1, nt - 1));
-      CK(out_t(p->s2, state->s2, nt));
-      CK(out_t(p->s3, state->s3, nt));
-    } else if (iters > 0 || !warm) {
-      // w = Psi z; after iterations this also completes the deferred dual
-      // update d <- d - (w - v) of the last one.  A warm start with no
-      // iteration leaves the caller's state untouched.
-      CK(launch_dft_apply(p, p->s2, p->img_tmp, iters > 0 ? p->s0 : nullptr, p->s1, 0, s));
-      CK(out_t(p->img_tmp, state->s0, nt));
-      CK(out_t(p->s1, state->s1, nt));
-      CK(out_t(p->s0, state->s2, nt));
-    }
-    state->iter += iters;
-  }
-#undef CK
-  return CS_OK;
+  if (st != CS_OK) return st;
+  *iters_done = k;
+  if (delta) *delta = (float)last_delta;
+  return solve_finish(p, k, x_out, state, s);
 }
 
 }  // extern "C"

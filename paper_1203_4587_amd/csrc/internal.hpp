@@ -177,6 +177,8 @@ struct cs_plan {
   float2* s3 = nullptr;         // TV: d2  DFT: u
   float2* img_tmp = nullptr;    // one image, layout conversions
   double* jpart = nullptr;      // objective partial sums
+  float* jdev = nullptr;        // [2] objective values read back by the Delta-driven solve
+  float* jhost = nullptr;       // [2] pinned host copy (hipHostMalloc, on first use)
   int jpart_len = 0;
 
   hipGraphExec_t graph = nullptr;  // cached iteration graph

@@ -160,3 +160,18 @@ def test_gradient_calls_reject_bad_arguments(lib):
     assert lib.cs_admm_forward_ckpt(None, FAKE, 0.01, 0.1, FAKE, None) == _lib.CS_EINVAL
     assert lib.cs_admm_backward(None, FAKE, FAKE, FAKE, None) == _lib.CS_EINVAL
     assert lib.cs_grad_destroy(None) == _lib.CS_OK
+
+
+def test_delta_solve_rejects_bad_arguments(lib):
+    n = ctypes.c_int32()
+    d = ctypes.c_float()
+    assert lib.cs_admm_solve_until(None, FAKE, 0.01, 0.1, 10, 1e-3, 5, FAKE, None, ctypes.byref(n),
+                                   ctypes.byref(d), None) == _lib.CS_EINVAL
+    assert lib.cs_admm_solve_until(FAKE, FAKE, 0.01, 0.1, 10, 1e-3, 5, FAKE, None, None, None,
+                                   None) == _lib.CS_EINVAL
+    assert lib.cs_admm_solve_until(FAKE, FAKE, 0.01, 0.1, 0, 1e-3, 5, FAKE, None, ctypes.byref(n), None,
+                                   None) == _lib.CS_EINVAL
+    assert lib.cs_admm_solve_until(FAKE, FAKE, 0.01, 0.1, 10, 1e-3, 0, FAKE, None, ctypes.byref(n), None,
+                                   None) == _lib.CS_EINVAL
+    assert lib.cs_admm_solve_until(FAKE, FAKE, 0.01, 0.1, 10, float("nan"), 5, FAKE, None, ctypes.byref(n), None,
+                                   None) == _lib.CS_EINVAL

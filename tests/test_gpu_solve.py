@@ -254,3 +254,70 @@ def test_column_form_is_deterministic(shape, prior):
     for _ in range(3):
         assert torch.equal(plan.solve(y, 0.02, 8), ref)
 
+
+
+def _oracle_stop(case, prior, lam, mu, rho, max_iters, check_every):
+    """The oracle's trajectory with J(k) at every iteration (J(0) at H'y), and
+    Delta(k) at the check points of the blocked stopping rule."""
+    Js = []
+    cb = lambda k, x: Js.append(O.objective_tv(x, case.y, case.coil, case.mask, lam) if prior == "tv"
+                                else O.objective_dft(x, case.y, case.coil, case.mask, lam))
+    Hy = O.adjoint(case.y, case.coil, case.mask)
+    J0 = O.objective_tv(Hy, case.y, case.coil, case.mask, lam) if prior == "tv" else \
+        O.objective_dft(Hy, case.y, case.coil, case.mask, lam)
+    ref = O.solve(case.y, case.coil, case.mask, prior, lam, mu, rho, max_iters)
+    fac = O.BlockFactor(case.coil, case.mask)
+    if prior == "tv":
+        O.admm_analysis(Hy, fac, lam, mu, rho, max_iters, callback=cb)
+    else:
+        O.admm_synthesis(Hy, fac, lam, mu, max_iters, callback=cb)
+    J = [J0] + Js
+    checks = []
+    k = 0
+    while k < max_iters:
+        k = min(k + check_every, max_iters)
+        checks.append((k, (J[k - 1] - J[k]) / J[k]))
+    return J, checks
+
+
+@pytest.mark.parametrize("prior,check_every", [("tv", 5), ("tv", 1), ("dft", 4), ("dft", 1)])
+def test_delta_driven_solve_stops_where_the_oracle_does(prior, check_every):
+    """cs_admm_solve_until: the iteration at which Delta(k) first falls below
+    tol matches the FP64 oracle's trajectory under the same blocked rule; the
+    image and state equal a fixed-count solve of that many iterations."""
+    from paper_1203_4587_amd.api import Plan
+    fam = "cardiac" if prior == "tv" else "periodic"
+    case = make_case(48, 24, 8, 3, accel=3, ncenter=2, prior=prior, family=fam, seed=61, sigma=0.01)
+    lam, mu, rho, max_iters = 0.02, 0.1, 0.5, 60
+    J, checks = _oracle_stop(case, prior, lam, mu, rho, max_iters, check_every)
+    deltas = [d for _, d in checks]
+    # a tolerance between two consecutive check values, far (>= 10%) from both
+    target = None
+    for a in range(3, len(checks) - 1):
+        lo = deltas[a]
+        if min(deltas[:a]) > 1.25 * lo and lo > 0:
+            target = (a, (min(deltas[:a]) * lo) ** 0.5)
+            break
+    assert target is not None, deltas
+    a, tol = target
+    k_ref = checks[a][0]
+    coil, mask, y = case.device()
+    plan = Plan(coil, mask, mu, prior=prior, mu_ratio=rho)
+    st = plan.new_state()
+    x, k, delta = plan.solve_until(y, lam, max_iters, tol=tol, check_every=check_every, state=st)
+    print(prior, check_every, "stop", k, "oracle", k_ref, "delta", delta, checks[a][1], "tol", tol)
+    assert k == k_ref
+    assert abs(delta - checks[a][1]) <= 0.05 * abs(checks[a][1])
+    ref_plain = Plan(coil, mask, mu, prior=prior, mu_ratio=rho)
+    st2 = ref_plain.new_state()
+    xp = ref_plain.solve(y, lam, k, state=st2)
+    assert torch.equal(x, xp)
+    for name in ("s0", "s1", "s2", "s3"):
+        if getattr(st, name) is not None:
+            assert torch.equal(getattr(st, name), getattr(st2, name)), name
+    assert st.iter == st2.iter == k
+    xo = O.solve(case.y, case.coil, case.mask, prior, lam, mu, rho, k)["x"]
+    assert rel_l2(x.cpu().numpy(), xo) < TOL
+    # tol below every Delta: runs to max_iters
+    x2, k2, _ = plan.solve_until(y, lam, 12, tol=-1e9, check_every=check_every)
+    assert k2 == 12 and torch.equal(x2, ref_plain.solve(y, lam, 12))
