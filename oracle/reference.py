@@ -188,6 +188,20 @@ def tdft_adj(w: np.ndarray) -> np.ndarray:
     return np.fft.ifft(w, axis=0, norm="ortho")
 
 
+def tframe(z: np.ndarray) -> np.ndarray:
+    """An overcomplete tight frame along frames (Sec. IV-A allows any Psi with
+    Psi'Psi = I): the union of the identity and the unitary temporal DFT,
+    scaled by 1/sqrt(2).  Coefficients stack the identity part (frames
+    0..nt-1) over the DFT part (frames nt..2nt-1)."""
+    return np.concatenate([z, tdft(z)], axis=0) / np.sqrt(2.0)
+
+
+def tframe_adj(w: np.ndarray) -> np.ndarray:
+    """Psi' of tframe: (w_identity + DFT'(w_dft)) / sqrt(2)."""
+    nt = w.shape[0] // 2
+    return (w[:nt] + tdft_adj(w[nt:])) / np.sqrt(2.0)
+
+
 # --------------------------------------------------------------------------
 # Algorithm 2: ADMM_Analysis with R = D_t (Sec. IV-B)
 # --------------------------------------------------------------------------
@@ -296,9 +310,10 @@ def delta(j_prev: float, j_cur: float) -> float:
 
 
 def solve(y, coil, mask, prior, lam, mu, rho, iters, cols=None, fac=None) -> dict:
-    """Run Algorithm 2 ("tv") or Algorithm 1 ("dft") on the given columns
-    (all by default).  Columns never interact under a temporal prior, so a
-    column subset gives exactly those columns of the full reconstruction."""
+    """Run Algorithm 2 ("tv"), Algorithm 1 with the temporal DFT ("dft"), or
+    Algorithm 1 with the overcomplete tight frame tframe ("frame") on the given
+    columns (all by default).  Columns never interact under a temporal prior,
+    so a column subset gives exactly those columns of the full reconstruction."""
     nh = coil.shape[2]
     cols = np.arange(nh) if cols is None else np.asarray(cols)
     if fac is None:
@@ -308,6 +323,8 @@ def solve(y, coil, mask, prior, lam, mu, rho, iters, cols=None, fac=None) -> dic
         return admm_analysis(Hy, fac, lam, mu, rho, iters)
     if prior == "dft":
         return admm_synthesis(Hy, fac, lam, mu, iters)
+    if prior == "frame":
+        return admm_synthesis(Hy, fac, lam, mu, iters, psi=tframe, psi_adj=tframe_adj)
     raise ValueError(prior)
 
 

@@ -257,6 +257,40 @@ def test_tight_frame_inverse_identity(rng):
     assert np.abs(lhs - printed).max() > 1e-2
 
 
+def test_union_frame_is_tight_and_overcomplete(rng):
+    """tframe = [I; F_t] / sqrt(2): Psi'Psi = I (tight), Psi Psi' != I but a
+    projection; its matrix equals the stacked identity and brute-force DFT."""
+    nt = 6
+    z = crandn(rng, nt, 3, 2)
+    np.testing.assert_allclose(O.tframe_adj(O.tframe(z)), z, atol=1e-14)
+    P = np.stack([O.tframe(np.eye(nt)[:, k][:, None, None])[:, 0, 0] for k in range(nt)], axis=1)
+    F = np.exp(-2j * np.pi * np.outer(np.arange(nt), np.arange(nt)) / nt) / np.sqrt(nt)
+    np.testing.assert_allclose(P, np.vstack([np.eye(nt), F]) / np.sqrt(2), atol=1e-14)
+    G = P @ P.conj().T
+    assert np.abs(G - np.eye(2 * nt)).max() > 0.1          # overcomplete
+    np.testing.assert_allclose(G @ G, G, atol=1e-14)        # orthogonal projection
+    w = crandn(rng, 2 * nt, 3, 2)
+    np.testing.assert_allclose(np.vdot(O.tframe(z), w), np.vdot(z, O.tframe_adj(w)), atol=1e-13)
+
+
+def test_synthesis_with_union_frame_reaches_kkt_point():
+    """Algorithm 1 with the overcomplete frame converges to a minimiser of
+    lambda ||w||_1 + ||y - H Psi' w||^2: with g = 2 Psi H'(H Psi' w - y),
+    g = -lambda w/|w| on the support and |g| <= lambda elsewhere."""
+    from tests.helpers import make_case
+    case = make_case(8, 4, 6, 2, accel=2, ncenter=2, prior="dft", family="periodic", seed=3, sigma=0.02)
+    lam, mu = 0.05, 0.5
+    fac = O.BlockFactor(case.coil, case.mask)
+    Hy = O.adjoint(case.y, case.coil, case.mask)
+    w = O.admm_synthesis(Hy, fac, lam, mu, 3000, psi=O.tframe, psi_adj=O.tframe_adj)["w"]
+    x = O.tframe_adj(w)
+    g = 2 * O.tframe(O.adjoint(O.forward(x, case.coil, case.mask), case.coil, case.mask) - Hy)
+    nz = np.abs(w) > 1e-9
+    assert 0.0 < nz.mean() < 0.5                      # a sparse, non-trivial solution
+    assert np.abs(g[nz] + lam * w[nz] / np.abs(w[nz])).max() < 1e-10
+    assert np.abs(g[~nz]).max() <= lam * (1 + 1e-9)
+
+
 def test_synthesis_with_overcomplete_frame_solves_w_subproblem(rng):
     """One Algorithm 1 w-step with an overcomplete tight frame equals the
     minimiser of ||y - H Psi' w||^2 + mu ||w - v - d||^2 (dense normal equations)."""
@@ -265,11 +299,7 @@ def test_synthesis_with_overcomplete_frame_solves_w_subproblem(rng):
     y = crandn(rng, nt, nc, nv, nh) * mask[:, None, :, None]
     fac = O.BlockFactor(coil, mask)
     # temporal frame: [Id; DFT] / sqrt(2) stacked along frames (6 rows, Psi'Psi = I)
-    def psi(z):
-        return np.concatenate([z, O.tdft(z)], axis=0) / np.sqrt(2)
-
-    def psi_adj(w):
-        return (w[:nt] + O.tdft_adj(w[nt:])) / np.sqrt(2)
+    psi, psi_adj = O.tframe, O.tframe_adj
     Hy = O.adjoint(y, coil, mask)
     lam, mu = 0.05, 0.4
     st = O.admm_synthesis(Hy, fac, lam, mu, 1, psi=psi, psi_adj=psi_adj)
