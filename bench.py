@@ -37,6 +37,7 @@ WORKLOADS = {
     "tv256": dict(name="tv-256x256x32-8c", prior="tv"),
     "dft192": dict(name="dft-192x192x40-12c", prior="dft"),
     "tv64": dict(name="tv-64x64x8-4c", prior="tv"),
+    "frame192": dict(name="frame-192x192x40-12c", prior="frame", config="dft192"),
 }
 
 
@@ -253,7 +254,7 @@ def main() -> int:
         return 1
     torch.cuda.set_device(0)
     wl = WORKLOADS[args.workload]
-    problem = S.CONFIGS[args.workload]()
+    problem = S.CONFIGS[wl.get("config", args.workload)]()
     nt, nv, nh = problem.x_true.shape
     nc = problem.coil.shape[0]
 
@@ -318,9 +319,13 @@ def main() -> int:
         x_bytes = factor_bytes + 5 * img_bytes          # reads H'y, m, d2; writes x, d2
         t_bytes = 6 * img_bytes - 2 * 8 * npix          # reads m, d1, x, d2; writes m, d1 (d1: nt-1 frames)
         tkind = "tv_step"
-    else:
+    elif wl["prior"] == "dft":
         x_bytes = factor_bytes + 3 * img_bytes          # reads H'y, u; writes z
         t_bytes = 6 * img_bytes                         # reads z, d, v; writes d, v, u
+        tkind = "dft_step"
+    else:
+        x_bytes = factor_bytes + 3 * img_bytes          # reads H'y, u; writes x~
+        t_bytes = 11 * img_bytes                        # reads x~, u, v, d (2 nt frames each); writes v, d, u
         tkind = "dft_step"
     if "column_solve" in ktimes:
         # one launch runs every iteration: temporal step + x-update per column

@@ -63,6 +63,11 @@ typedef enum {
 typedef enum {
   CS_PRIOR_TEMPORAL_TV = 0,   /* Algorithm 2 with R = D_t (eq. TV) */
   CS_PRIOR_TEMPORAL_DFT = 1,  /* Algorithm 1 with Psi = unitary DFT along frames */
+  CS_PRIOR_TEMPORAL_FRAME = 2, /* Algorithm 1 with the overcomplete tight frame Psi = [I; F] / sqrt(2)
+                                  (identity and unitary DFT along frames; Psi'Psi = I, Psi Psi' != I),
+                                  including the (1/mu)(I - Psi Psi') term of the w-update (Sec. IV-A).
+                                  Coefficients have 2 nt frames (identity part first).  No J_trace,
+                                  no Delta-driven solve, no column-resident form. */
 } cs_prior;
 
 enum {

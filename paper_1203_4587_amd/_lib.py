@@ -19,6 +19,7 @@ CS_EMU_MISMATCH = 5
 
 CS_PRIOR_TEMPORAL_TV = 0
 CS_PRIOR_TEMPORAL_DFT = 1
+CS_PRIOR_TEMPORAL_FRAME = 2
 
 CS_FLAG_NO_REFACTOR = 1 << 0
 CS_FLAG_GRAPH = 1 << 1

@@ -18,7 +18,8 @@ import torch
 from . import _lib
 from ._lib import CsAllocator, CsPlanDesc, CsState, check
 
-PRIORS = {"tv": _lib.CS_PRIOR_TEMPORAL_TV, "dft": _lib.CS_PRIOR_TEMPORAL_DFT}
+PRIORS = {"tv": _lib.CS_PRIOR_TEMPORAL_TV, "dft": _lib.CS_PRIOR_TEMPORAL_DFT,
+          "frame": _lib.CS_PRIOR_TEMPORAL_FRAME}
 
 
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
@@ -72,8 +73,9 @@ class _TorchAllocator:
 class State:
     """Solver state in image layout (see cs_state in include/csmri.h).
 
-    TV : s0 = m, s1 = d1 (nt-1 frames), s2 = x, s3 = d2
-    DFT: s0 = w, s1 = v, s2 = d, s3 unused
+    TV   : s0 = m, s1 = d1 (nt-1 frames), s2 = x, s3 = d2
+    DFT  : s0 = w, s1 = v, s2 = d, s3 unused
+    frame: s0 = w, s1 = v, s2 = d (2 nt coefficient frames each), s3 unused
     """
     s0: torch.Tensor
     s1: torch.Tensor
@@ -87,6 +89,8 @@ class State:
             return torch.zeros((frames, nv, nh), dtype=torch.complex64, device=device)
         if prior == "tv":
             return cls(img(nt), img(nt - 1), img(nt), img(nt), 0)
+        if prior == "frame":
+            return cls(img(2 * nt), img(2 * nt), img(2 * nt), None, 0)
         return cls(img(nt), img(nt), img(nt), None, 0)
 
 
@@ -261,14 +265,7 @@ class Plan:
         _need(y, "y", torch.complex64, self.kspace_shape)
         x = out if out is not None else torch.empty(self.image_shape, dtype=torch.complex64, device=y.device)
         _need(x, "out", torch.complex64, self.image_shape)
-        cstate = None
-        if state is not None:
-            fr = {"tv": (self.nt, self.nt - 1, self.nt, self.nt), "dft": (self.nt, self.nt, self.nt, None)}[self.prior]
-            for name, frames in zip(("s0", "s1", "s2", "s3"), fr):
-                if frames is not None:
-                    _need(getattr(state, name), f"state.{name}", torch.complex64, (frames, self.nv, self.nh))
-            cstate = CsState(state.s0.data_ptr(), state.s1.data_ptr(), state.s2.data_ptr(),
-                             state.s3.data_ptr() if state.s3 is not None else None, int(state.iter))
+        cstate = _state_struct(self, state)
         J = torch.empty(max(iters, 1), dtype=torch.float32, device=y.device) if trace else None
         st = _lib.load().cs_admm_solve(self.handle, _ptr(y), float(lam), float(self.mu if mu is None else mu),
                                        int(iters), _ptr(x), ctypes.byref(cstate) if cstate else None,
@@ -284,7 +281,8 @@ class Plan:
 def _state_struct(plan: "Plan", state: "State | None"):
     if state is None:
         return None
-    fr = {"tv": (plan.nt, plan.nt - 1, plan.nt, plan.nt), "dft": (plan.nt, plan.nt, plan.nt, None)}[plan.prior]
+    nt = plan.nt
+    fr = {"tv": (nt, nt - 1, nt, nt), "dft": (nt, nt, nt, None), "frame": (2 * nt, 2 * nt, 2 * nt, None)}[plan.prior]
     for name, frames in zip(("s0", "s1", "s2", "s3"), fr):
         if frames is not None:
             _need(getattr(state, name), f"state.{name}", torch.complex64, (frames, plan.nv, plan.nh))

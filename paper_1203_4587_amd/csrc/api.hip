@@ -83,7 +83,7 @@ static int validate_flags(uint32_t f) {
 static int validate_desc(const cs_plan_desc* d) {
   if (d->nv < 2 || d->nh < 2 || d->nt < 1 || d->nc < 1)
     return set_error(CS_EINVAL, "nv, nh must be >= 2 and nt, nc >= 1");
-  if (d->prior != CS_PRIOR_TEMPORAL_TV && d->prior != CS_PRIOR_TEMPORAL_DFT)
+  if (d->prior != CS_PRIOR_TEMPORAL_TV && d->prior != CS_PRIOR_TEMPORAL_DFT && d->prior != CS_PRIOR_TEMPORAL_FRAME)
     return set_error(CS_EINVAL, "unknown prior");
   if (d->prior == CS_PRIOR_TEMPORAL_TV && d->nt < 2)
     return set_error(CS_EINVAL, "the temporal TV prior needs nt >= 2");
@@ -195,6 +195,12 @@ static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, flo
       if (st == CS_OK)
         st = timed_launch(p, kKindX, s,
                           [&] { return launch_block_solve(p, kSolveTV, p->hy, p->s0, p->s3, p->s2, mu, s); });
+    } else if (p->desc.prior == CS_PRIOR_TEMPORAL_FRAME) {
+      // the first pass of a call starts from the w held in img_tmp
+      st = timed_launch(p, kKindDFT, s, [&] { return launch_frame_step(p, lambda, mu, k == 0 && !cont, s); });
+      if (st == CS_OK)
+        st = timed_launch(p, kKindX, s,
+                          [&] { return launch_block_solve(p, kSolveDFT, p->hy, p->s3, nullptr, p->s2, mu, s); });
     } else {
       st = timed_launch(p, kKindDFT, s, [&] {
         const bool first = k == 0 && !cont;
@@ -260,6 +266,18 @@ static int solve_setup(cs_plan* p, const cs_c64* y, float mu, const cs_state* st
       CK(launch_fill(p->s1, nimg, zero, s));
       CK(launch_fill(p->s3, nimg, zero, s));
     }
+  } else if (p->desc.prior == CS_PRIOR_TEMPORAL_FRAME) {
+    if (warm) {
+      CK(in_t(state->s0, p->img_tmp, 2 * nt));  // w, used as is by the first pass
+      CK(in_t(state->s1, p->s1, 2 * nt));       // v
+      CK(in_t(state->s2, p->s0, 2 * nt));       // d
+      CK(launch_frame_adjoint(p, p->img_tmp, p->s2, s));  // x = Psi' w (x_out if iters == 0)
+    } else {
+      CK(launch_copy(p->hy, p->s2, nimg, s));              // x = H'y
+      CK(launch_frame_forward(p, p->hy, p->img_tmp, s));   // w_0 = Psi H'y
+      CK(launch_fill(p->s0, 2 * nimg, zero, s));           // d_0 = 0
+      CK(launch_fill(p->s1, 2 * nimg, zero, s));           // v_0 = 0
+    }
   } else {
     if (warm) {
       CK(in_t(state->s0, p->img_tmp, nt));                 // w, used as is by the first pass
@@ -297,6 +315,15 @@ static int solve_finish(cs_plan* p, int32_t iters, cs_c64* x_out, cs_state* stat
       CK(out_t(p->s1, state->s1, nt - 1));
       CK(out_t(p->s2, state->s2, nt));
       CK(out_t(p->s3, state->s3, nt));
+    } else if (p->desc.prior == CS_PRIOR_TEMPORAL_FRAME) {
+      if (iters > 0 || !warm) {
+        // w and d of the last iteration (the pass that follows an iteration
+        // completes them); a fresh start with no iteration returns w_0 = Psi H'y
+        if (iters > 0) CK(launch_frame_finish(p, s));
+        CK(out_t(p->img_tmp, state->s0, 2 * nt));
+        CK(out_t(p->s1, state->s1, 2 * nt));
+        CK(out_t(p->s0, state->s2, 2 * nt));
+      }
     } else if (iters > 0 || !warm) {
       // w = Psi z; after iterations this also completes the deferred dual
       // update d <- d - (w - v) of the last one.  A warm start with no
@@ -351,6 +378,8 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
   const int nv = desc->nv, nh = desc->nh, nt = desc->nt, nc = desc->nc;
   const size_t npix = (size_t)nv * nh;
   const size_t nimg = npix * nt;
+  // coefficient arrays (d, v, w) of the overcomplete frame prior hold 2 nt frames
+  const size_t ncoef = desc->prior == CS_PRIOR_TEMPORAL_FRAME ? 2 * nimg : nimg;
   hipStream_t s = S(stream);
   auto fail = [&](int status) {
     plan_release(p);
@@ -461,11 +490,11 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
       (st = plan_alloc(p, &p->ktmp, ksz, "ktmp")) ||
       (st = plan_alloc(p, &p->ftmp, ksz, "ftmp")) ||
       (st = plan_alloc(p, &p->hy, nimg, "hy")) ||
-      (st = plan_alloc(p, &p->s0, nimg, "state")) ||
-      (st = plan_alloc(p, &p->s1, nimg, "state")) ||
+      (st = plan_alloc(p, &p->s0, ncoef, "state")) ||
+      (st = plan_alloc(p, &p->s1, ncoef, "state")) ||
       (st = plan_alloc(p, &p->s2, nimg, "state")) ||
       (st = plan_alloc(p, &p->s3, nimg, "state")) ||
-      (st = plan_alloc(p, &p->img_tmp, nimg, "image workspace")) ||
+      (st = plan_alloc(p, &p->img_tmp, ncoef, "image workspace")) ||
       (st = plan_alloc(p, &p->jpart, (size_t)objective_partial_count(), "objective partials")) ||
       (st = plan_alloc(p, &p->jdev, 2, "objective values")))
     return fail(st);
@@ -577,6 +606,8 @@ int cs_admm_solve(cs_plan* p, const cs_c64* y, float lambda, float mu, int32_t i
                   cs_state* state, float* J_trace, cs_stream stream) {
   if (!p || !y || !x_out) return set_error(CS_EINVAL, "plan, y and x_out must not be NULL");
   if (iters < 0) return set_error(CS_EINVAL, "iters must be >= 0");
+  if (J_trace && p->desc.prior == CS_PRIOR_TEMPORAL_FRAME)
+    return set_error(CS_EUNSUPPORTED, "no objective trace for the overcomplete frame prior");
   int st = solve_check(p, lambda, mu, state);
   if (st != CS_OK) return st;
   CS_HIP(hipSetDevice(p->device));
@@ -594,6 +625,8 @@ int cs_admm_solve_until(cs_plan* p, const cs_c64* y, float lambda, float mu, int
   if (max_iters < 1) return set_error(CS_EINVAL, "max_iters must be >= 1");
   if (check_every < 1) return set_error(CS_EINVAL, "check_every must be >= 1");
   if (!std::isfinite(tol)) return set_error(CS_EINVAL, "tol must be finite");
+  if (p->desc.prior == CS_PRIOR_TEMPORAL_FRAME)
+    return set_error(CS_EUNSUPPORTED, "no objective monitor for the overcomplete frame prior");
   int st = solve_check(p, lambda, mu, state);
   if (st != CS_OK) return st;
   CS_HIP(hipSetDevice(p->device));

@@ -223,6 +223,11 @@ int launch_dft_step(cs_plan* p, float lambda, float mu, int first, const float2*
 // also d <- d - (out - v)
 int launch_dft_apply(cs_plan* p, const float2* in, float2* out, float2* dual, const float2* v, int adjoint,
                      hipStream_t s);
+// overcomplete temporal frame prior (state: s0 = d, s1 = v, s2 = x~, s3 = u, img_tmp = w)
+int launch_frame_step(cs_plan* p, float lambda, float mu, int first, hipStream_t s);
+int launch_frame_finish(cs_plan* p, hipStream_t s);
+int launch_frame_forward(cs_plan* p, const float2* x, float2* w, hipStream_t s);
+int launch_frame_adjoint(cs_plan* p, const float2* w, float2* x, hipStream_t s);
 int launch_fill(float2* ptr, size_t n, float2 v, hipStream_t s);
 int launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s);
 // all iterations in one launch, one workgroup per readout column (even nv)

@@ -748,6 +748,233 @@ int launch_dft_apply(cs_plan* p, const float2* in, float2* out, float2* dual, co
   return dft_tiles_dispatch<kDftForward>(p, in, dual, const_cast<float2*>(v), out, nullptr, 0.f, 0, 0, nh, s);
 }
 
+// ---------------------------------------------------------------- overcomplete temporal frame
+//
+// Algorithm 1 with the tight frame Psi = [I; F] / sqrt(2) (identity and the
+// unitary temporal DFT F; Psi'Psi = I, Psi Psi' != I).  Coefficient arrays
+// hold 2 nt frames: the identity part (frames 0..nt-1) over the DFT part
+// (frames nt..2nt-1).  With u = Psi'(v + d) and x~ = (mu I + H'H)^{-1}(H'y +
+// mu u), the w-update of Algorithm 1 (including its (1/mu)(I - Psi Psi') term,
+// Sec. IV-A) is w = (v + d) + Psi (x~ - u), because Psi'q = H'y + mu u for
+// q = Psi H'y + mu (v + d); and Psi' w = x~.  So one iteration is one
+// per-pixel pass (finish the previous iteration's w and d, shrink, form u)
+// plus the x-update with right-hand side H'y + mu u.  Both transforms of a
+// pass run on the MFMA DFT tiles; the identity part needs no arithmetic.
+//   kFrameFirst:   v = soft(w - d, tau), u = Psi'(v + d) from the given w (d kept)
+//   kFrameStep:    w = v + d + Psi(x~ - u); d <- d - (w - v); v = soft(w - d, tau);
+//                  u = Psi'(v + d)
+//   kFrameFinish:  w = v + d + Psi(x~ - u); d <- d - (w - v); writes w, d
+//   kFrameForward: w = Psi x
+//   kFrameAdjoint: x = Psi' w
+enum FrameMode { kFrameFirst = 0, kFrameStep = 1, kFrameFinish = 2, kFrameForward = 3, kFrameAdjoint = 4 };
+constexpr float kInvSqrt2 = 0.70710678118654752440f;
+
+template <int KP, int MODE>
+__device__ __forceinline__ void frame_tile(const float* __restrict__ frag, float* tile, const float2* __restrict__ xt,
+                                           float2* __restrict__ u, float2* __restrict__ v, float2* __restrict__ d,
+                                           float2* __restrict__ w, int nt, size_t npix, size_t p0, int count,
+                                           float tau, int lane) {
+  constexpr int MT = DftTile<KP>::MT;
+  const int col = lane & 15, grp = lane >> 4;
+  const bool pv = col < count;
+  const size_t p = p0 + col;
+  mfma_v4 acc[MT];
+  if (MODE == kFrameForward) {
+    tile_stage<KP>(tile, xt, nt, npix, p0, count, lane);
+    tile_gemm<KP, false>(frag, tile, lane, acc);
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int f = 8 * m + 2 * grp + h;
+        if (f < nt && pv) {
+          const float2 xf = make_float2(tile[(2 * f) * 16 + col], tile[(2 * f + 1) * 16 + col]);
+          w[(size_t)f * npix + p] = cscale(xf, kInvSqrt2);
+          w[(size_t)(nt + f) * npix + p] = cscale(make_float2(acc[m][2 * h], acc[m][2 * h + 1]), kInvSqrt2);
+        }
+      }
+    __builtin_amdgcn_wave_barrier();
+    return;
+  }
+  float2 qI[MT][2];
+  if (MODE == kFrameAdjoint) {
+    // stage the DFT part of w, keep the identity part for the sum
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int f = 8 * m + 2 * grp + h;
+        const bool ok = f < nt && pv;
+        const float2 wf = ok ? w[(size_t)(nt + f) * npix + p] : make_float2(0.f, 0.f);
+        qI[m][h] = ok ? w[(size_t)f * npix + p] : make_float2(0.f, 0.f);
+        tile[(2 * f) * 16 + col] = wf.x;
+        tile[(2 * f + 1) * 16 + col] = wf.y;
+      }
+  } else {
+    // Psi (x~ - u): the DFT part from the MFMA tile, the identity part from the staged e
+    float2 peI[MT][2], peF[MT][2];
+    if (MODE != kFrameFirst) {
+      constexpr int NK = KP / 8;
+      float2 r[NK];
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int t = grp + 4 * k;
+        const bool ok = t < nt && pv;
+        const float2 a = ok ? xt[(size_t)t * npix + p] : make_float2(0.f, 0.f);
+        const float2 b = ok ? u[(size_t)t * npix + p] : make_float2(0.f, 0.f);
+        r[k] = csub(a, b);
+      }
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int t = grp + 4 * k;
+        tile[(2 * t) * 16 + col] = r[k].x;
+        tile[(2 * t + 1) * 16 + col] = r[k].y;
+      }
+      __builtin_amdgcn_wave_barrier();
+      tile_gemm<KP, false>(frag, tile, lane, acc);
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int f = 8 * m + 2 * grp + h;
+          peF[m][h] = cscale(make_float2(acc[m][2 * h], acc[m][2 * h + 1]), kInvSqrt2);
+          peI[m][h] = cscale(make_float2(tile[(2 * f) * 16 + col], tile[(2 * f + 1) * 16 + col]), kInvSqrt2);
+        }
+      __builtin_amdgcn_wave_barrier();
+    }
+    // coefficient updates, identity part (c = f) and DFT part (c = nt + f)
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int f = 8 * m + 2 * grp + h;
+        float2 qF = make_float2(0.f, 0.f);
+        qI[m][h] = make_float2(0.f, 0.f);
+        if (f < nt && pv) {
+#pragma unroll
+          for (int part = 0; part < 2; ++part) {
+            const size_t o = (size_t)(part ? nt + f : f) * npix + p;
+            float2 dv = d[o], q;
+            if (MODE == kFrameFirst) {
+              const float2 vn = soft_threshold(csub(w[o], dv), tau);
+              v[o] = vn;
+              q = cadd(vn, dv);
+            } else {
+              const float2 vv = v[o];
+              const float2 wv = cadd(cadd(vv, dv), part ? peF[m][h] : peI[m][h]);
+              dv = csub(dv, csub(wv, vv));
+              if (MODE == kFrameFinish) {
+                w[o] = wv;
+                d[o] = dv;
+                q = make_float2(0.f, 0.f);
+              } else {
+                const float2 vn = soft_threshold(csub(wv, dv), tau);
+                v[o] = vn;
+                d[o] = dv;
+                q = cadd(vn, dv);
+              }
+            }
+            if (part) qF = q;
+            else qI[m][h] = q;
+          }
+        }
+        if (MODE != kFrameFinish) {
+          tile[(2 * f) * 16 + col] = qF.x;
+          tile[(2 * f + 1) * 16 + col] = qF.y;
+        }
+      }
+    if (MODE == kFrameFinish) return;
+  }
+  // u = Psi' q = (q_identity + F' q_dft) / sqrt(2)  (x for kFrameAdjoint)
+  __builtin_amdgcn_wave_barrier();
+  tile_gemm<KP, true>(frag, tile, lane, acc);
+  float2* out = MODE == kFrameAdjoint ? const_cast<float2*>(xt) : u;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = 8 * m + 2 * grp + h;
+      if (t < nt && pv)
+        out[(size_t)t * npix + p] =
+            cscale(cadd(make_float2(acc[m][2 * h], acc[m][2 * h + 1]), qI[m][h]), kInvSqrt2);
+    }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int KP, int MODE>
+__global__ __launch_bounds__(256) void k_frame_tiles(const float* __restrict__ frags, const float2* xt,
+                                                     float2* __restrict__ u, float2* __restrict__ v,
+                                                     float2* __restrict__ d, float2* __restrict__ w, int nt,
+                                                     size_t npix, float tau) {
+  extern __shared__ float lds_f[];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float* tile = lds_f + DftTile<KP>::FRAG + wv * KP * 16;
+  load_frags<KP>(lds_f, frags);
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  const size_t ntiles = (npix + 15) / 16;
+  for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
+    const size_t p0 = tl * 16;
+    const int count = (int)std::min<size_t>(16, npix - p0);
+    frame_tile<KP, MODE>(lds_f, tile, xt, u, v, d, w, nt, npix, p0, count, tau, lane);
+  }
+}
+
+template <int KP, int MODE>
+static int frame_tiles_launch(cs_plan* p, const float2* xt, float2* u, float2* v, float2* d, float2* w, float tau,
+                              hipStream_t s) {
+  const size_t npix = (size_t)p->desc.nv * p->desc.nh;
+  const int waves = dft_waves(KP);
+  const size_t lds = dft_lds_bytes(KP, waves);
+  static bool attr = false;
+  if (lds > 65536 && !attr) {
+    CS_HIP(hipFuncSetAttribute((const void*)k_frame_tiles<KP, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    attr = true;
+  }
+  const size_t ntiles = (npix + 15) / 16;
+  const unsigned grid = (unsigned)std::min<size_t>((ntiles + waves - 1) / waves, 2048);
+  hipLaunchKernelGGL((k_frame_tiles<KP, MODE>), dim3(grid), dim3(64 * waves), lds, s, p->dft_frags, xt, u, v, d, w,
+                     p->desc.nt, npix, tau);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
+template <int MODE>
+static int frame_dispatch(cs_plan* p, const float2* xt, float2* u, float2* v, float2* d, float2* w, float tau,
+                          hipStream_t s) {
+  switch (dft_kp(p->desc.nt)) {
+    case 16: return frame_tiles_launch<16, MODE>(p, xt, u, v, d, w, tau, s);
+    case 32: return frame_tiles_launch<32, MODE>(p, xt, u, v, d, w, tau, s);
+    case 48: return frame_tiles_launch<48, MODE>(p, xt, u, v, d, w, tau, s);
+    case 64: return frame_tiles_launch<64, MODE>(p, xt, u, v, d, w, tau, s);
+    case 80: return frame_tiles_launch<80, MODE>(p, xt, u, v, d, w, tau, s);
+    case 96: return frame_tiles_launch<96, MODE>(p, xt, u, v, d, w, tau, s);
+    case 112: return frame_tiles_launch<112, MODE>(p, xt, u, v, d, w, tau, s);
+    default: return frame_tiles_launch<128, MODE>(p, xt, u, v, d, w, tau, s);
+  }
+}
+
+// plan state for the frame prior: s0 = d, s1 = v (2 nt frames each), s2 = x~,
+// s3 = u, img_tmp = w (2 nt frames)
+int launch_frame_step(cs_plan* p, float lambda, float mu, int first, hipStream_t s) {
+  const float tau = lambda / (2.0f * mu);
+  if (first) return frame_dispatch<kFrameFirst>(p, p->s2, p->s3, p->s1, p->s0, p->img_tmp, tau, s);
+  return frame_dispatch<kFrameStep>(p, p->s2, p->s3, p->s1, p->s0, p->img_tmp, tau, s);
+}
+
+int launch_frame_finish(cs_plan* p, hipStream_t s) {
+  return frame_dispatch<kFrameFinish>(p, p->s2, p->s3, p->s1, p->s0, p->img_tmp, 0.f, s);
+}
+
+int launch_frame_forward(cs_plan* p, const float2* x, float2* w, hipStream_t s) {
+  return frame_dispatch<kFrameForward>(p, x, nullptr, nullptr, nullptr, w, 0.f, s);
+}
+
+int launch_frame_adjoint(cs_plan* p, const float2* w, float2* x, hipStream_t s) {
+  return frame_dispatch<kFrameAdjoint>(p, x, nullptr, nullptr, nullptr, const_cast<float2*>(w), 0.f, s);
+}
+
 // Frame-count instantiations of the remaining per-pixel kernel (objective).
 #define CS_DISPATCH_NT(nt, FN, ...)            \
   do {                                         \
@@ -853,7 +1080,9 @@ static int column_launch(cs_plan* p, const ColumnSolveArgs& a, int threads, size
   return column_launch_rp<PRIOR, NT, 4>(p, a, threads, lds, s);
 }
 
-bool column_solve_supported(const cs_plan* p) { return (p->desc.nv & 1) == 0; }
+bool column_solve_supported(const cs_plan* p) {
+  return (p->desc.nv & 1) == 0 && p->desc.prior != CS_PRIOR_TEMPORAL_FRAME;
+}
 
 int launch_column_solve(cs_plan* p, int iters, float lambda, float mu, const float2* wgiven, hipStream_t s) {
   const int n = p->desc.nv, nt = p->desc.nt;

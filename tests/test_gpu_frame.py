@@ -1,0 +1,129 @@
+"""GPU parity of Algorithm 1 with the overcomplete tight temporal frame
+Psi = [I; F] / sqrt(2) (CS_PRIOR_TEMPORAL_FRAME) against the FP64 oracle:
+images and the coefficient state (w, v, d) within relative l2 1e-4 after a
+fixed iteration count, warm starts bit for bit, and the execution forms
+that apply (graph replay, batches)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1203_4587_amd import synthetic as S
+from tests.helpers import Case, make_case, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = 1e-4
+LAM, MU = 0.02, 0.1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _case(shape, seed):
+    nv, nh, nt, nc = shape
+    return make_case(nv, nh, nt, nc, accel=3, ncenter=2, prior="dft", family="periodic", seed=seed, sigma=0.01)
+
+
+def _oracle(case, iters, cols=None):
+    return O.solve(case.y, case.coil, case.mask, "frame", LAM, MU, 0.5, iters, cols=cols)
+
+
+@pytest.mark.parametrize("shape,iters", [
+    ((48, 32, 12, 3), 30),
+    ((36, 6, 8, 4), 25),        # 216 pixels: ragged last tile
+    ((27, 18, 5, 2), 20),       # odd nv (row x-update)
+    ((32, 8, 1, 2), 10),        # one frame: Psi = [1; 1] / sqrt(2)
+    ((96, 12, 40, 3), 15),      # 80-wide embedding
+    ((16, 8, 64, 2), 8),        # maximum frame count
+], ids=str)
+def test_frame_solves_match_oracle(shape, iters):
+    from paper_1203_4587_amd.api import Plan
+    case = _case(shape, seed=shape[0] + shape[2])
+    coil, mask, y = case.device()
+    plan = Plan(coil, mask, MU, prior="frame")
+    st = plan.new_state()
+    x = plan.solve(y, LAM, iters, state=st)
+    ref = _oracle(case, iters)
+    err = rel_l2(x.cpu().numpy(), ref["x"])
+    ew = rel_l2(st.s0.cpu().numpy(), ref["w"])
+    ev = rel_l2(st.s1.cpu().numpy(), ref["v"])
+    ed = rel_l2(st.s2.cpu().numpy(), ref["d"])
+    print(shape, iters, "x", err, "w", ew, "v", ev, "d", ed)
+    assert err < TOL and ew < TOL and ev < TOL and ed < TOL
+    assert st.iter == iters
+
+
+def test_frame_resume_zero_iterations_and_graph():
+    from paper_1203_4587_amd import _lib
+    from paper_1203_4587_amd.api import Plan
+    case = _case((48, 16, 10, 3), seed=5)
+    coil, mask, y = case.device()
+    plan = Plan(coil, mask, MU, prior="frame")
+    full = plan.new_state()
+    x20 = plan.solve(y, LAM, 20, state=full)
+    part = plan.new_state()
+    plan.solve(y, LAM, 12, state=part)
+    x20b = plan.solve(y, LAM, 8, state=part)
+    assert torch.equal(x20, x20b)
+    for n in ("s0", "s1", "s2"):
+        assert torch.equal(getattr(full, n), getattr(part, n)), n
+    # zero iterations: a fresh start returns H'y and (Psi H'y, 0, 0); a warm one x = Psi' w, state untouched
+    fresh = plan.new_state()
+    x0 = plan.solve(y, LAM, 0, state=fresh)
+    Hy = O.adjoint(case.y, case.coil, case.mask)
+    assert rel_l2(x0.cpu().numpy(), Hy) < 1e-5
+    assert rel_l2(fresh.s0.cpu().numpy(), O.tframe(Hy)) < 1e-5
+    assert not fresh.s1.any() and not fresh.s2.any()
+    keep = [getattr(part, n).clone() for n in ("s0", "s1", "s2")]
+    xw = plan.solve(y, LAM, 0, state=part)
+    for n, k in zip(("s0", "s1", "s2"), keep):
+        assert torch.equal(getattr(part, n), k)
+    assert rel_l2(xw.cpu().numpy(), O.tframe_adj(part.s0.cpu().numpy().astype(np.complex128))) < 1e-5
+    # graph replay and the column-resident flag (not available here: the phase form runs)
+    for flags in (_lib.CS_FLAG_GRAPH, _lib.CS_FLAG_COLUMN_RESIDENT, _lib.CS_FLAG_GRAPH | _lib.CS_FLAG_XU_WAVE):
+        g = Plan(coil, mask, MU, prior="frame", flags=flags)
+        for _ in range(2):
+            assert torch.equal(g.solve(y, LAM, 20), x20), flags
+
+
+def test_frame_unsupported_calls():
+    from paper_1203_4587_amd import _lib
+    from paper_1203_4587_amd.api import Plan
+    case = _case((32, 8, 6, 2), seed=9)
+    coil, mask, y = case.device()
+    plan = Plan(coil, mask, MU, prior="frame")
+    with pytest.raises(_lib.CsmriError, match="objective"):
+        plan.solve(y, LAM, 5, trace=True)
+    with pytest.raises(_lib.CsmriError, match="objective"):
+        plan.solve_until(y, LAM, 10)
+
+
+def test_frame_slice_in_a_batch():
+    from paper_1203_4587_amd.api import Batch, Plan, Slice
+    cases = [_case((48, 16, 8, 3), seed=21), make_case(32, 24, 6, 2, prior="tv", seed=22)]
+    priors = ["frame", "tv"]
+    dev = [c.device() for c in cases]
+    batch = Batch([Slice(c, m, p, MU, 0.5) for (c, m, _), p in zip(dev, priors)])
+    xs = batch.solve([y for _, _, y in dev], [LAM, LAM], 15)
+    for (c, m, y), p, x in zip(dev, priors, xs):
+        assert torch.equal(x, Plan(c, m, MU, prior=p, mu_ratio=0.5).solve(y, LAM, 15))
+
+
+def test_full_size_frame_192x192x40_12c_sampled_columns():
+    """The 192x192x40, 12-coil, R=10 periodic workload under the frame prior,
+    100 iterations at full size; five columns recomputed by the oracle."""
+    from paper_1203_4587_amd.api import Plan
+    case = Case(S.CONFIGS["dft192"]())
+    p = case.p
+    coil, mask, y = case.device()
+    x = Plan(coil, mask, p.mu, prior="frame").solve(y, p.lam, p.iters)
+    nh = p.x_true.shape[2]
+    cols = np.array(sorted({0, 1, nh // 3, nh // 2 + 1, nh - 1}))
+    ref = O.solve(case.y, case.coil, case.mask, "frame", p.lam, p.mu, p.rho, p.iters, cols=cols)
+    err = rel_l2(x.cpu().numpy()[:, :, cols], ref["x"])
+    print("frame 192 sampled rel_l2", err)
+    assert err < TOL
