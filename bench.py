@@ -46,8 +46,12 @@ def log(*a):
 
 
 def kernel_source_sha() -> str:
-    with open(os.path.join(ROOT, "paper_1203_4587_amd", "csrc", "iterate.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Fingerprint of the x-update kernels: iterate.hip up to its TV-step section
+    (the x-update kernels, their helpers and launchers)."""
+    with open(os.path.join(ROOT, "paper_1203_4587_amd", "csrc", "iterate.hip"), encoding="utf-8") as f:
+        text = f.read()
+    text = text[:text.index("// ---------------------------------------------------------------- TV step")]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def measured_traffic(kind: str, workload: str, steps: int):

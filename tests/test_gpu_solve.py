@@ -53,6 +53,9 @@ def test_tv_small_workload_matches_oracle():
     ((16, 8, 1, 2), "dft", 10),       # single frame: Psi is the identity
     ((64, 8, 64, 2), "tv", 10),       # maximum frame count
     ((64, 8, 64, 2), "dft", 10),
+    ((512, 4, 6, 2), "tv", 10),      # maximum nv: four row pairs per lane
+    ((384, 4, 5, 2), "dft", 10),     # three row pairs per lane (last group partly idle)
+    ((6, 512, 4, 2), "tv", 10),      # maximum nh
 ], ids=lambda v: str(v))
 def test_solves_match_oracle(shape, prior, iters):
     nv, nh, nt, nc = shape
@@ -181,7 +184,8 @@ def test_full_size_dft_192x192x40_12c_sampled_columns():
 FORM_CASES = [((64, 32, 10, 4), "tv"), ((64, 32, 10, 4), "dft"), ((96, 24, 40, 3), "dft"),
               ((96, 24, 40, 3), "tv"), ((192, 16, 32, 4), "dft"), ((192, 16, 24, 4), "tv"),
               ((144, 12, 20, 3), "dft"), ((144, 12, 20, 3), "tv"), ((128, 16, 48, 2), "tv"),
-              ((64, 8, 64, 2), "dft"), ((2, 8, 6, 2), "tv"), ((6, 12, 5, 2), "dft")]
+              ((64, 8, 64, 2), "dft"), ((2, 8, 6, 2), "tv"), ((6, 12, 5, 2), "dft"),
+              ((512, 4, 6, 2), "tv"), ((384, 4, 5, 2), "dft")]
 
 
 @pytest.mark.parametrize("shape,prior", FORM_CASES, ids=[f"{s}-{p}" for s, p in FORM_CASES])
