@@ -476,6 +476,39 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
     }
   }
 
+  // MFMA fragments of T^{-1}, T = rho I + D'D (FP64 Gauss-Jordan; T is symmetric
+  // positive definite), padded to KT = nt rounded up to 16, same lane layout
+  // as the DFT fragments
+  const int kt = (nt + 15) / 16 * 16;
+  std::vector<float> htfrag((size_t)(kt / 16) * (kt / 4) * 64, 0.f);
+  if (desc->prior == CS_PRIOR_TEMPORAL_TV) {
+    const double rho = desc->mu_ratio;
+    std::vector<double> A((size_t)nt * 2 * nt, 0.0);  // [T | I]
+    for (int t = 0; t < nt; ++t) {
+      A[(size_t)t * 2 * nt + t] = rho + ((t == 0 || t == nt - 1) ? 1.0 : 2.0);
+      if (t > 0) A[(size_t)t * 2 * nt + t - 1] = -1.0;
+      if (t < nt - 1) A[(size_t)t * 2 * nt + t + 1] = -1.0;
+      A[(size_t)t * 2 * nt + nt + t] = 1.0;
+    }
+    for (int c = 0; c < nt; ++c) {
+      const double piv = A[(size_t)c * 2 * nt + c];
+      for (int j = 0; j < 2 * nt; ++j) A[(size_t)c * 2 * nt + j] /= piv;
+      for (int r = 0; r < nt; ++r) {
+        if (r == c) continue;
+        const double f = A[(size_t)r * 2 * nt + c];
+        if (f != 0.0)
+          for (int j = 0; j < 2 * nt; ++j) A[(size_t)r * 2 * nt + j] -= f * A[(size_t)c * 2 * nt + j];
+      }
+    }
+    const int tks = kt / 4;
+    for (int mm = 0; mm < kt / 16; ++mm)
+      for (int kk = 0; kk < tks; ++kk)
+        for (int l = 0; l < 64; ++l) {
+          const int r = 16 * mm + l % 16, c = 4 * kk + l / 16;
+          if (r < nt && c < nt) htfrag[((size_t)mm * tks + kk) * 64 + l] = (float)A[(size_t)r * 2 * nt + nt + c];
+        }
+  }
+
   const size_t ksz = (size_t)nt * nc * mrow * nh;
   if ((st = plan_alloc(p, &p->rows, hrows.size(), "rows")) ||
       (st = plan_alloc(p, &p->mcnt, (size_t)nt, "mcnt")) ||
@@ -486,6 +519,7 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
       (st = plan_alloc(p, &p->psi_t, hpsi.size(), "psi")) ||
       (st = plan_alloc(p, &p->dft_frags, hfrag.size(), "psi fragments")) ||
       (st = plan_alloc(p, &p->tv_invden, (size_t)nt, "tv_invden")) ||
+      (st = plan_alloc(p, &p->tv_frags, htfrag.size(), "tv fragments")) ||
       (st = plan_alloc(p, &p->coil_cm, npix * nc, "coil")) ||
       (st = plan_alloc(p, &p->ktmp, ksz, "ktmp")) ||
       (st = plan_alloc(p, &p->ftmp, ksz, "ftmp")) ||
@@ -514,6 +548,7 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
   UP(p->psi_t, hpsi.data(), hpsi.size() * sizeof(float2));
   UP(p->dft_frags, hfrag.data(), hfrag.size() * sizeof(float));
   UP(p->tv_invden, hinv.data(), hinv.size() * sizeof(float));
+  UP(p->tv_frags, htfrag.data(), htfrag.size() * sizeof(float));
 #undef UP
   // coil maps [c][j][i] -> column-major [c][i][j]
   if ((st = launch_transpose(reinterpret_cast<const float2*>(coil), p->coil_cm, nc, nv, nh, s)) != CS_OK)

@@ -158,7 +158,8 @@ struct cs_plan {
   float2* tw_h = nullptr;
   float2* psi_t = nullptr;      // [nt][nt] unitary temporal DFT matrix (DFT prior)
   float* dft_frags = nullptr;   // MFMA A-operand fragments of the embedded Psi and Psi' (DFT prior)
-  float* tv_invden = nullptr;   // [nt] Thomas coefficients of (rho I + D'D)
+  float* tv_invden = nullptr;   // [nt] Thomas coefficients of (rho I + D'D) (gradient sweep)
+  float* tv_frags = nullptr;    // MFMA A-operand fragments of (rho I + D'D)^{-1}, padded to 16 (TV step)
 
   // coil maps in the solver's column-major layout [c][i][j]
   float2* coil_cm = nullptr;

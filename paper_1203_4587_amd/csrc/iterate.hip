@@ -349,125 +349,8 @@ int launch_block_solve(cs_plan* p, int mode, const float2* hy, const float2* m, 
 }
 
 // ---------------------------------------------------------------- TV step
-//
-// Algorithm 2, lines v, m and d1 with R = D_t, one pixel per thread over all
-// frames (D_t couples frames only):
-//   v   = soft(D m + d1, tau),  tau = lambda / (2 mu1)
-//   m   = (rho I + D'D)^{-1} [ D'(v - d1) + rho (x + d2) ],  rho = mu2 / mu1
-//   d1 <- d1 - (v - D m)
-// rho I + D'D is tridiagonal (diagonal rho+1, rho+2, ..., rho+2, rho+1; off-
-// diagonals -1) and is solved exactly by the Thomas recurrence with the
-// pivots' reciprocals invden[t] precomputed in FP64.  v never reaches memory:
-// e_t = d1_t - v_t is kept in registers for the dual update.
-// The time series of a pixel (4 arrays x nt frames) is loaded before any
-// arithmetic so that all its loads are in flight together: a 256x256 image
-// has only one wave per SIMD, so latency has to be hidden inside the wave.
-template <int NT>
-__device__ __forceinline__ void tv_pixel(float2* __restrict__ m, float2* __restrict__ d1, const float2* __restrict__ x,
-                                const float2* __restrict__ d2, const float* __restrict__ invden, int nt,
-                                size_t npix, size_t p, float tau, float rho) {
-  float2 M[NT], E[NT], R[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    M[t] = t < nt ? m[(size_t)t * npix + p] : make_float2(0.f, 0.f);
-    E[t] = t < nt - 1 ? d1[(size_t)t * npix + p] : make_float2(0.f, 0.f);
-    if (t < nt) {
-      const float2 xt = x[(size_t)t * npix + p], d2t = d2[(size_t)t * npix + p];
-      R[t] = make_float2(rho * (xt.x + d2t.x), rho * (xt.y + d2t.y));
-    } else {
-      R[t] = make_float2(0.f, 0.f);
-    }
-  }
-  // v_t = soft(m_{t+1} - m_t + d1_t); e_t = d1_t - v_t (kept in E);
-  // r_t = rho (x_t + d2_t) + e_t - e_{t-1}; forward Thomas sweep in place (R)
-  float2 eprev = make_float2(0.f, 0.f), dprev = make_float2(0.f, 0.f);
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    if (t < nt) {
-      float2 dtu = make_float2(0.f, 0.f);
-      if (t < nt - 1) {
-        const float2 a = make_float2(M[t + 1].x - M[t].x + E[t].x, M[t + 1].y - M[t].y + E[t].y);
-        const float2 v = soft_threshold(a, tau);
-        E[t] = csub(E[t], v);
-        dtu = E[t];
-      }
-      if (t > 0) dtu = csub(dtu, eprev);
-      if (t < nt - 1) eprev = E[t];
-      const float iv = invden[t];
-      dprev = make_float2((R[t].x + dtu.x + dprev.x) * iv, (R[t].y + dtu.y + dprev.y) * iv);
-      R[t] = dprev;
-    }
-  }
-  // back substitution m_t = r'_t + invden_t m_{t+1}; d1 <- e_t + m_{t+1} - m_t
-  float2 mnext = make_float2(0.f, 0.f);
-#pragma unroll
-  for (int t = NT - 1; t >= 0; --t) {
-    if (t < nt) {
-      float2 mt = R[t];
-      if (t < nt - 1) {
-        const float iv = invden[t];
-        mt = make_float2(fmaf(iv, mnext.x, mt.x), fmaf(iv, mnext.y, mt.y));
-        d1[(size_t)t * npix + p] = make_float2(E[t].x + mnext.x - mt.x, E[t].y + mnext.y - mt.y);
-      }
-      m[(size_t)t * npix + p] = mt;
-      mnext = mt;
-    }
-  }
-}
+// (defined after the MFMA tile helpers of the temporal DFT, which it shares)
 
-template <int NT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_tv_step(
-    float2* __restrict__ m, float2* __restrict__ d1, const float2* __restrict__ x, const float2* __restrict__ d2,
-    const float* __restrict__ invden, int nt, size_t npix, size_t pix0, size_t pix1, float tau, float rho) {
-  const size_t p = pix0 + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < pix1) tv_pixel<NT>(m, d1, x, d2, invden, nt, npix, p, tau, rho);
-}
-
-// pixels of columns [i0, i1): the solver layout puts column i's rows at i*nv .. i*nv + nv - 1
-template <int NT>
-static void tv_launch(cs_plan* p, float tau, float rho, int i0, int i1, hipStream_t s) {
-  const size_t npix = (size_t)p->desc.nv * p->desc.nh;
-  const size_t pix0 = (size_t)i0 * p->desc.nv, pix1 = (size_t)i1 * p->desc.nv;
-  hipLaunchKernelGGL(k_tv_step<NT>, dim3((unsigned)((pix1 - pix0 + 63) / 64)), dim3(64), 0, s, p->s0, p->s1, p->s2,
-                     p->s3, p->tv_invden, p->desc.nt, npix, pix0, pix1, tau, rho);
-}
-
-int launch_tv_step_cols(cs_plan* p, float lambda, float mu, int i0, int i1, hipStream_t s) {
-  if (i1 <= i0) return CS_OK;
-  const float rho = p->desc.mu_ratio;
-  const float tau = lambda * rho / (2.0f * mu);  // lambda / (2 mu1), mu1 = mu / rho
-  const int nt = p->desc.nt;
-  if (nt <= 8) tv_launch<8>(p, tau, rho, i0, i1, s);
-  else if (nt <= 16) tv_launch<16>(p, tau, rho, i0, i1, s);
-  else if (nt <= 24) tv_launch<24>(p, tau, rho, i0, i1, s);
-  else if (nt <= 32) tv_launch<32>(p, tau, rho, i0, i1, s);
-  else if (nt <= 40) tv_launch<40>(p, tau, rho, i0, i1, s);
-  else if (nt <= 48) tv_launch<48>(p, tau, rho, i0, i1, s);
-  else tv_launch<64>(p, tau, rho, i0, i1, s);
-  CS_HIP(hipGetLastError());
-  return CS_OK;
-}
-
-int launch_tv_step(cs_plan* p, float lambda, float mu, hipStream_t s) {
-  return launch_tv_step_cols(p, lambda, mu, 0, p->desc.nh, s);
-}
-
-// ---------------------------------------------------------------- DFT step
-//
-// Algorithm 1 with Psi = unitary DFT along frames, one pixel per thread.
-// The iteration is split around the x-update so that each half is one pass:
-//   this kernel:  w = Psi z  (z = the last x-update output)
-//                 d <- d - (w - v)       (dual update of the previous
-//                                          iteration; skipped on the first)
-//                 v <- soft(w - d, tau),  tau = lambda / (2 mu)
-//                 u <- Psi'(v + d)
-//   x-update:     z <- (mu I + H'H)^{-1} (H'y + mu u)
-// which is the algorithm's order (v, w, d) with the d-update deferred to the
-// start of the next pass.  For an orthonormal Psi the frame term
-// (1/mu)(I - Psi Psi')[.] of the w-update vanishes.
-// On a warm start the saved w is passed as `wgiven` and used as is on the
-// first pass (it is the value an uninterrupted run computes there), so a
-// resumed solve reproduces the uninterrupted one bit for bit.
 // ---------------------------------------------------------------- temporal DFT on MFMA
 //
 // The temporal DFT of 16 pixels at a time is a dense real contraction: with a
@@ -748,6 +631,182 @@ int launch_dft_apply(cs_plan* p, const float2* in, float2* out, float2* dual, co
   return dft_tiles_dispatch<kDftForward>(p, in, dual, const_cast<float2*>(v), out, nullptr, 0.f, 0, 0, nh, s);
 }
 
+// ---------------------------------------------------------------- TV step on MFMA
+//
+// Algorithm 2, lines v, m and d1 with R = D_t (D_t couples frames only):
+//   v   = soft(D m + d1, tau),  tau = lambda / (2 mu1)
+//   m   = (rho I + D'D)^{-1} [ D'(v - d1) + rho (x + d2) ],  rho = mu2 / mu1
+//   d1 <- d1 - (v - D m)
+// T = rho I + D'D is the same for every pixel, so the m-solve of 16 pixels
+// is one real contraction m = T^{-1} r of the padded KT x KT inverse (built in
+// FP64 on the host) with the KT x 16 real and imaginary parts of r, on
+// v_mfma_f32_16x16x4f32 (fragment layout as for the temporal DFT).  The
+// pointwise lines run with lane l on pixel l % 16 and frames t = l / 16 + 4 k;
+// values a lane needs from a neighbouring frame pass through the wave's LDS.
+// One wave per 16 pixels gives four times the waves of a pixel-per-lane
+// recurrence, which is what hides the latency of the streams.
+template <int KT>
+__device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* buf0, float2* buf1,
+                                        float2* __restrict__ m, float2* __restrict__ d1,
+                                        const float2* __restrict__ x, const float2* __restrict__ d2, int nt,
+                                        size_t npix, size_t p0, int count, float tau, float rho, int lane) {
+  constexpr int MT = DftTile<KT>::MT, NK = KT / 4;
+  const int col = lane & 15, grp = lane >> 4;
+  const bool pv = col < count;
+  const size_t p = p0 + col;
+  // m -> buf0, d1 -> buf1 (rows t, 16 pixels)
+  {
+    float2 mv[NK], dv[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = grp + 4 * k;
+      const bool ok = t < nt && pv;
+      const size_t o = (size_t)t * npix + p;
+      mv[k] = ok ? m[o] : make_float2(0.f, 0.f);
+      dv[k] = (ok && t < nt - 1) ? d1[o] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = grp + 4 * k;
+      buf0[t * 16 + col] = mv[k];
+      buf1[t * 16 + col] = dv[k];
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  // v_t = soft(m_{t+1} - m_t + d1_t, tau); e_t = d1_t - v_t (t < nt - 1), into buf1
+  {
+    float2 ev[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = grp + 4 * k;
+      ev[k] = make_float2(0.f, 0.f);
+      if (t + 1 < KT && t < nt - 1) {
+        const float2 m0 = buf0[t * 16 + col], m1 = buf0[(t + 1) * 16 + col], dt = buf1[t * 16 + col];
+        const float2 a = make_float2(m1.x - m0.x + dt.x, m1.y - m0.y + dt.y);
+        ev[k] = csub(dt, soft_threshold(a, tau));
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < NK; ++k) buf1[(grp + 4 * k) * 16 + col] = ev[k];
+  }
+  __builtin_amdgcn_wave_barrier();
+  // r_t = rho (x_t + d2_t) + e_t - e_{t-1}, split into real and imaginary
+  // operand rows (buf0, whose m is no longer needed, as two KT x 16 float tiles)
+  float* bre = reinterpret_cast<float*>(buf0);
+  float* bim = bre + KT * 16;
+  {
+    float2 xv[NK], zv[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = grp + 4 * k;
+      const bool ok = t < nt && pv;
+      const size_t o = (size_t)t * npix + p;
+      xv[k] = ok ? x[o] : make_float2(0.f, 0.f);
+      zv[k] = ok ? d2[o] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = grp + 4 * k;
+      float2 r = make_float2(0.f, 0.f);
+      if (t < nt) {
+        const float2 e0 = buf1[t * 16 + col];
+        const float2 em1 = t > 0 ? buf1[(t - 1) * 16 + col] : make_float2(0.f, 0.f);
+        r = make_float2(rho * (xv[k].x + zv[k].x) + e0.x - em1.x, rho * (xv[k].y + zv[k].y) + e0.y - em1.y);
+      }
+      bre[t * 16 + col] = r.x;
+      bim[t * 16 + col] = r.y;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  mfma_v4 are[MT], aim[MT];
+  tile_gemm<KT, false>(frag, bre, lane, are);
+  tile_gemm<KT, false>(frag, bim, lane, aim);
+  __builtin_amdgcn_wave_barrier();
+  // new m: accumulator lane l holds frames 16 mm + 4 (l / 16) + j of pixel l % 16
+#pragma unroll
+  for (int mm = 0; mm < MT; ++mm)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int t = 16 * mm + 4 * grp + j;
+      const float2 mv = make_float2(are[mm][j], aim[mm][j]);
+      buf0[t * 16 + col] = mv;
+      if (t < nt && pv) m[(size_t)t * npix + p] = mv;
+    }
+  __builtin_amdgcn_wave_barrier();
+  // d1_t <- e_t + m_{t+1} - m_t
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int t = grp + 4 * k;
+    if (t + 1 < KT && t < nt - 1 && pv) {
+      const float2 e0 = buf1[t * 16 + col], m0 = buf0[t * 16 + col], m1 = buf0[(t + 1) * 16 + col];
+      d1[(size_t)t * npix + p] = make_float2(e0.x + m1.x - m0.x, e0.y + m1.y - m0.y);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// LDS floats of one wave's two KT x 16 complex buffers
+constexpr int tv_wave_floats(int kt) { return 4 * kt * 16; }
+inline int tv_kt(int nt) { return (nt + 15) / 16 * 16; }
+
+template <int KT>
+__global__ __launch_bounds__(256) void k_tv_tiles(
+    const float* __restrict__ frags, float2* __restrict__ m,
+                                                  float2* __restrict__ d1, const float2* __restrict__ x,
+                                                  const float2* __restrict__ d2, int nt, size_t npix, size_t pix0,
+                                                  size_t pix1, float tau, float rho) {
+  extern __shared__ float lds_f[];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float2* buf0 = reinterpret_cast<float2*>(lds_f + DftTile<KT>::FRAG + wv * tv_wave_floats(KT));
+  float2* buf1 = buf0 + KT * 16;
+  load_frags<KT>(lds_f, frags);
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  const size_t ntiles = (pix1 - pix0 + 15) / 16;
+  for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
+    const size_t p0 = pix0 + tl * 16;
+    const int count = (int)std::min<size_t>(16, pix1 - p0);
+    tv_tile<KT>(lds_f, buf0, buf1, m, d1, x, d2, nt, npix, p0, count, tau, rho, lane);
+  }
+}
+
+template <int KT>
+static int tv_tiles_launch(cs_plan* p, float tau, float rho, int i0, int i1, hipStream_t s) {
+  const size_t npix = (size_t)p->desc.nv * p->desc.nh;
+  const size_t pix0 = (size_t)i0 * p->desc.nv, pix1 = (size_t)i1 * p->desc.nv;
+  constexpr int waves = 4;
+  const size_t lds = ((size_t)DftTile<KT>::FRAG + (size_t)waves * tv_wave_floats(KT)) * sizeof(float);
+  static bool attr = false;
+  if (lds > 65536 && !attr) {
+    CS_HIP(hipFuncSetAttribute((const void*)k_tv_tiles<KT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  const size_t ntiles = (pix1 - pix0 + 15) / 16;
+  const unsigned grid = (unsigned)std::min<size_t>((ntiles + waves - 1) / waves, 65535);
+  hipLaunchKernelGGL(k_tv_tiles<KT>, dim3(grid), dim3(64 * waves), lds, s, p->tv_frags, p->s0, p->s1, p->s2, p->s3,
+                     p->desc.nt, npix, pix0, pix1, tau, rho);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
+// pixels of columns [i0, i1): the solver layout puts column i's rows at i*nv .. i*nv + nv - 1
+int launch_tv_step_cols(cs_plan* p, float lambda, float mu, int i0, int i1, hipStream_t s) {
+  if (i1 <= i0) return CS_OK;
+  const float rho = p->desc.mu_ratio;
+  const float tau = lambda * rho / (2.0f * mu);  // lambda / (2 mu1), mu1 = mu / rho
+  switch (tv_kt(p->desc.nt)) {
+    case 16: return tv_tiles_launch<16>(p, tau, rho, i0, i1, s);
+    case 32: return tv_tiles_launch<32>(p, tau, rho, i0, i1, s);
+    case 48: return tv_tiles_launch<48>(p, tau, rho, i0, i1, s);
+    default: return tv_tiles_launch<64>(p, tau, rho, i0, i1, s);
+  }
+}
+
+int launch_tv_step(cs_plan* p, float lambda, float mu, hipStream_t s) {
+  return launch_tv_step_cols(p, lambda, mu, 0, p->desc.nh, s);
+}
+
 // ---------------------------------------------------------------- overcomplete temporal frame
 //
 // Algorithm 1 with the tight frame Psi = [I; F] / sqrt(2) (identity and the
@@ -1006,21 +1065,18 @@ struct ColumnSolveArgs {
   FactorLayout L;
   const float2* hy;
   float2 *s0, *s1, *s2, *s3;
-  const float* invden;
-  const float* dft_frags;
+  const float* frags;    // MFMA fragments: T^{-1} (TV prior) or the embedded temporal DFT (DFT prior)
   const float2* wgiven;  // DFT warm start: w for the first pass, or null
   int nh, nt, iters;
   int wave_floats;       // LDS floats per wave
   float mu, tau, rho;
 };
 
-// MAXT: 512 threads (two waves per SIMD) while the temporal step fits in
-// 256 VGPRs (up to 40 frames), 256 threads beyond
-// NT: TV frame-count bound; for the DFT prior the padded embedding size KP.
-// Per-wave LDS: `wave_floats` floats (x-update staging, reused as the DFT
-// tile), then the DFT fragment matrix.
-template <int PRIOR, int NT, int RP, int MAXT = (PRIOR == CS_PRIOR_TEMPORAL_TV && NT > 40 ? 256 : 512)>
-__global__ __launch_bounds__(MAXT) void k_column_solve(ColumnSolveArgs a) {
+// NT: the padded MFMA size, KT of the TV step (TV prior) or KP of the
+// embedded DFT (DFT prior).  Per-wave LDS: `wave_floats` floats (x-update
+// staging, reused as the temporal step's tiles), then the fragment matrix.
+template <int PRIOR, int NT, int RP>
+__global__ __launch_bounds__(512) void k_column_solve(ColumnSolveArgs a) {
   extern __shared__ float2 lds[];
   const int n = a.L.n;
   const int nwaves = blockDim.x >> 6;
@@ -1028,16 +1084,15 @@ __global__ __launch_bounds__(MAXT) void k_column_solve(ColumnSolveArgs a) {
   float2* bsh = lds + (size_t)w * (a.wave_floats / 2);
   float2* dsh = bsh + n;
   float* frags = reinterpret_cast<float*>(lds + (size_t)nwaves * (a.wave_floats / 2));
-  if constexpr (PRIOR == CS_PRIOR_TEMPORAL_DFT) {
-    load_frags<NT>(frags, a.dft_frags);
-    __syncthreads();
-  }
+  load_frags<NT>(frags, a.frags);
+  __syncthreads();
   const int i = blockIdx.x;
   const size_t npix = (size_t)n * a.nh;
   for (int k = 0; k < a.iters; ++k) {
     if constexpr (PRIOR == CS_PRIOR_TEMPORAL_TV) {
-      for (int j = threadIdx.x; j < n; j += blockDim.x)
-        tv_pixel<NT>(a.s0, a.s1, a.s2, a.s3, a.invden, a.nt, npix, (size_t)i * n + j, a.tau, a.rho);
+      for (int tl = w; tl * 16 < n; tl += nwaves)
+        tv_tile<NT>(frags, bsh, bsh + NT * 16, a.s0, a.s1, a.s2, a.s3, a.nt, npix, (size_t)i * n + 16 * tl,
+                    std::min(16, n - 16 * tl), a.tau, a.rho, lane);
     } else {
       for (int tl = w; tl * 16 < n; tl += nwaves)
         dft_tile<NT, kDftStep>(frags, reinterpret_cast<float*>(bsh), a.s2, a.s0, a.s1,
@@ -1096,8 +1151,7 @@ int launch_column_solve(cs_plan* p, int iters, float lambda, float mu, const flo
   a.s1 = p->s1;
   a.s2 = p->s2;
   a.s3 = p->s3;
-  a.invden = p->tv_invden;
-  a.dft_frags = p->dft_frags;
+  a.frags = tv ? p->tv_frags : p->dft_frags;
   a.wgiven = wgiven;
   a.nh = p->desc.nh;
   a.nt = nt;
@@ -1105,11 +1159,10 @@ int launch_column_solve(cs_plan* p, int iters, float lambda, float mu, const flo
   a.mu = mu;
   a.rho = p->desc.mu_ratio;
   a.tau = tv ? lambda * a.rho / (2.0f * mu) : lambda / (2.0f * mu);
-  // two waves per SIMD fit the temporal step's registers up to 40 frames
-  const int max_threads = nt <= 40 ? 512 : 256;  // matches MAXT of k_column_solve
-  const int kp = dft_kp(nt);
-  const size_t frag_bytes = tv ? 0 : (size_t)(kp / 16) * (kp / 4) * 64 * sizeof(float);
-  a.wave_floats = std::max(2 * (1 + kXUnrollCol) * n, tv ? 0 : kp * 16);
+  const int max_threads = 512;  // the launch bound of k_column_solve
+  const int kp = tv ? tv_kt(nt) : dft_kp(nt);
+  const size_t frag_bytes = (size_t)(kp / 16) * (kp / 4) * 64 * sizeof(float);
+  a.wave_floats = std::max(2 * (1 + kXUnrollCol) * n, tv ? tv_wave_floats(kp) : kp * 16);
   a.wave_floats = (a.wave_floats + 3) / 4 * 4;  // keep every wave's region 16-byte aligned
   const size_t per_wave = (size_t)a.wave_floats * sizeof(float);
   const size_t lds_budget = 160 * 1024;
@@ -1117,13 +1170,12 @@ int launch_column_solve(cs_plan* p, int iters, float lambda, float mu, const flo
   const int threads = nwaves * 64;
   const size_t lds = nwaves * per_wave + frag_bytes;
   if (tv) {
-    if (nt <= 8) return column_launch<CS_PRIOR_TEMPORAL_TV, 8>(p, a, threads, lds, s);
-    if (nt <= 16) return column_launch<CS_PRIOR_TEMPORAL_TV, 16>(p, a, threads, lds, s);
-    if (nt <= 24) return column_launch<CS_PRIOR_TEMPORAL_TV, 24>(p, a, threads, lds, s);
-    if (nt <= 32) return column_launch<CS_PRIOR_TEMPORAL_TV, 32>(p, a, threads, lds, s);
-    if (nt <= 40) return column_launch<CS_PRIOR_TEMPORAL_TV, 40>(p, a, threads, lds, s);
-    if (nt <= 48) return column_launch<CS_PRIOR_TEMPORAL_TV, 48>(p, a, threads, lds, s);
-    return column_launch<CS_PRIOR_TEMPORAL_TV, 64>(p, a, threads, lds, s);
+    switch (kp) {
+      case 16: return column_launch<CS_PRIOR_TEMPORAL_TV, 16>(p, a, threads, lds, s);
+      case 32: return column_launch<CS_PRIOR_TEMPORAL_TV, 32>(p, a, threads, lds, s);
+      case 48: return column_launch<CS_PRIOR_TEMPORAL_TV, 48>(p, a, threads, lds, s);
+      default: return column_launch<CS_PRIOR_TEMPORAL_TV, 64>(p, a, threads, lds, s);
+    }
   }
   switch (kp) {
     case 16: return column_launch<CS_PRIOR_TEMPORAL_DFT, 16>(p, a, threads, lds, s);
