@@ -45,6 +45,8 @@ EXPORTED = (
     "cs_plan_flags",
     "cs_plan_set_flags",
     "cs_plan_tune",
+    "cs_plan_fft_tiles",
+    "cs_plan_set_fft_tiles",
     "cs_batch_create",
     "cs_batch_destroy",
     "cs_batch_size",
@@ -134,6 +136,8 @@ def load() -> ctypes.CDLL:
     lib.cs_plan_flags.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
     lib.cs_plan_set_flags.argtypes = [vp, ctypes.c_uint32]
     lib.cs_plan_tune.argtypes = [vp, vp, f32, i32, ctypes.POINTER(CsTuneEntry), i32, ctypes.POINTER(i32), vp]
+    lib.cs_plan_fft_tiles.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.cs_plan_set_fft_tiles.argtypes = [vp, i32, i32]
     lib.cs_batch_create.argtypes = [ctypes.POINTER(CsSliceDesc), i32, ctypes.POINTER(CsAllocator), vp,
                                     ctypes.POINTER(vp)]
     lib.cs_batch_destroy.argtypes = [vp]

@@ -205,6 +205,18 @@ class Plan:
     def flags(self, value: int) -> None:
         check(_lib.load().cs_plan_set_flags(self.handle, int(value)), "cs_plan_set_flags")
 
+    @property
+    def fft_tiles(self):
+        """(columns per workgroup of the vertical FFT passes, sampled rows per
+        workgroup of the horizontal ones) in use."""
+        c, r = ctypes.c_int32(), ctypes.c_int32()
+        check(_lib.load().cs_plan_fft_tiles(self.handle, ctypes.byref(c), ctypes.byref(r)), "cs_plan_fft_tiles")
+        return int(c.value), int(r.value)
+
+    @fft_tiles.setter
+    def fft_tiles(self, value) -> None:
+        check(_lib.load().cs_plan_set_fft_tiles(self.handle, int(value[0]), int(value[1])), "cs_plan_set_fft_tiles")
+
     def tune(self, y: torch.Tensor, lam: float, iters: int = 10, cache: str | None = None,
              stream=None) -> dict:
         """cs_plan_tune: time every execution form on y, keep the fastest.
@@ -221,15 +233,19 @@ class Plan:
             if entry is not None:
                 keep = self.flags & _lib.CS_FLAG_NO_REFACTOR
                 self.flags = keep | (int(entry["flags"]) & ~_lib.CS_FLAG_NO_REFACTOR)
-                return {"flags": self.flags, "candidates": [tuple(c) for c in entry["candidates"]], "cached": True}
+                if "fft_tiles" in entry:
+                    self.fft_tiles = entry["fft_tiles"]
+                return {"flags": self.flags, "candidates": [tuple(c) for c in entry["candidates"]],
+                        "fft_tiles": self.fft_tiles, "cached": True}
         recs = (_lib.CsTuneEntry * 8)()
         n = ctypes.c_int32()
         check(_lib.load().cs_plan_tune(self.handle, _ptr(y), float(lam), int(iters), recs, 8, ctypes.byref(n),
                                        _stream(stream)), "cs_plan_tune")
         cands = [(int(recs[i].flags), float(recs[i].ms_per_iter)) for i in range(min(n.value, 8))]
-        result = {"flags": self.flags, "candidates": cands, "cached": False}
+        result = {"flags": self.flags, "candidates": cands, "fft_tiles": self.fft_tiles, "cached": False}
         if cache is not None:
-            _tune_cache_write(cache, key, {"flags": result["flags"], "candidates": cands})
+            _tune_cache_write(cache, key, {"flags": result["flags"], "candidates": cands,
+                                           "fft_tiles": list(result["fft_tiles"])})
         return result
 
     def solve_until(self, y: torch.Tensor, lam: float, max_iters: int, tol: float = 1e-3,

@@ -747,6 +747,72 @@ int cs_plan_set_flags(cs_plan* p, uint32_t flags) {
   return CS_OK;
 }
 
+int cs_plan_fft_tiles(const cs_plan* p, int32_t* cols, int32_t* rows) {
+  if (!p || !cols || !rows) return set_error(CS_EINVAL, "plan, cols and rows must not be NULL");
+  *cols = fft_cols_per_group(p);
+  *rows = fft_rows_per_group(p);
+  return CS_OK;
+}
+
+int cs_plan_set_fft_tiles(cs_plan* p, int32_t cols, int32_t rows) {
+  if (!p) return set_error(CS_EINVAL, "plan is NULL");
+  if (cols < 0 || rows < 0) return set_error(CS_EINVAL, "tile sizes must be >= 0 (0 selects the largest)");
+  p->fft_cw = cols;
+  p->fft_rb = rows;
+  return CS_OK;
+}
+
+// FFT tiles of the SENSE passes: every (columns, rows) pair from the largest
+// tile down to 1/16 (columns) and 1/4 (rows) of it is timed on H'y of y (the
+// adjoint passes) followed by the vertical forward pass, which the objective
+// uses; the fastest is kept in the plan.
+static int tune_fft_tiles(cs_plan* p, const cs_c64* y, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const int save_cw = p->fft_cw, save_rb = p->fft_rb;
+  p->fft_cw = 0;
+  p->fft_rb = 0;
+  const int cw_full = fft_cols_per_group(p), rb_full = fft_rows_per_group(p);
+  std::vector<int> cws, rbs;
+  for (int d = 1; d <= 16; d *= 2)
+    if (cw_full / d >= 1 && (cws.empty() || cws.back() != cw_full / d)) cws.push_back(cw_full / d);
+  for (int d = 1; d <= 4; d *= 2)
+    if (rb_full / d >= 1 && (rbs.empty() || rbs.back() != rb_full / d)) rbs.push_back(rb_full / d);
+  float best = -1.f;
+  int bcw = cw_full, brb = rb_full, st = CS_OK;
+  for (int cw : cws)
+    for (int rb : rbs) {
+      p->fft_cw = cw;
+      p->fft_rb = rb;
+      auto run = [&]() {
+        int r = launch_adjoint_rows(p, reinterpret_cast<const float2*>(y), s);
+        if (r == CS_OK) r = launch_adjoint_image(p, p->img_tmp, true, s);
+        if (r == CS_OK) r = launch_forward(p, p->img_tmp, true, nullptr, s);
+        return r;
+      };
+      if ((st = run()) != CS_OK) break;  // warm-up
+      hipError_t e = hipEventRecord(e0, s);
+      for (int rep = 0; rep < 3 && e == hipSuccess && st == CS_OK; ++rep) st = run();
+      if (e == hipSuccess && st == CS_OK) e = hipEventRecord(e1, s);
+      if (e == hipSuccess && st == CS_OK) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess && st == CS_OK) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) st = hip_fail(e, "timing an FFT tile candidate");
+      if (st != CS_OK) break;
+      if (best < 0.f || ms < best) {
+        best = ms;
+        bcw = cw;
+        brb = rb;
+      }
+    }
+  if (st != CS_OK) {
+    p->fft_cw = save_cw;
+    p->fft_rb = save_rb;
+    return st;
+  }
+  p->fft_cw = bcw == cw_full ? 0 : bcw;
+  p->fft_rb = brb == rb_full ? 0 : brb;
+  return CS_OK;
+}
+
 int cs_plan_tune(cs_plan* p, const cs_c64* y, float lambda, int32_t iters, cs_tune_entry* entries, int32_t cap,
                  int32_t* count, cs_stream stream) {
   if (!p || !y) return set_error(CS_EINVAL, "plan and y must not be NULL");
@@ -767,14 +833,20 @@ int cs_plan_tune(cs_plan* p, const cs_c64* y, float lambda, int32_t iters, cs_tu
     cand.push_back(CS_FLAG_GRAPH);
   }
   if (column_solve_supported(p)) cand.push_back(CS_FLAG_COLUMN_RESIDENT);
-  // a fresh start on y: state in the plan's workspaces, x written to img_tmp
-  int st = cs_admm_solve(p, y, lambda, p->mu, 0, reinterpret_cast<cs_c64*>(p->img_tmp), nullptr, nullptr, stream);
-  if (st != CS_OK) return st;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CS_HIP(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return set_error(CS_EDEVICE, "hipEventCreate failed");
+  }
+  int st = tune_fft_tiles(p, y, s, e0, e1);
+  // a fresh start on y: state in the plan's workspaces, x written to img_tmp
+  if (st == CS_OK)
+    st = cs_admm_solve(p, y, lambda, p->mu, 0, reinterpret_cast<cs_c64*>(p->img_tmp), nullptr, nullptr, stream);
+  if (st != CS_OK) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
   }
   uint32_t best = original;
   float best_ms = 0.f;

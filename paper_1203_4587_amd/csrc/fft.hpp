@@ -65,6 +65,24 @@ __device__ __forceinline__ void fft_butterfly(const float2* s, int nr, int r, in
   }
 }
 
+// q = a / b and a - q b for 0 <= a < 16384, 1 <= b <= 4096 (checked
+// exhaustively): a float estimate of the quotient, off by at most one, then
+// corrected.  A general integer division costs tens of instructions; every
+// index split of the FFT kernels (a < 2 kFftElems, b <= 512) uses this.
+__device__ __forceinline__ int fast_div(int a, int b, float inv_b, int& rem) {
+  int q = (int)((float)a * inv_b);
+  int r = a - q * b;
+  if (r < 0) {
+    --q;
+    r += b;
+  } else if (r >= b) {
+    ++q;
+    r -= b;
+  }
+  rem = r;
+  return q;
+}
+
 // In-place transform of nbatch sequences; all threads of the (1-D, kFftThreads
 // wide) workgroup must call it.  Ends with a barrier.
 template <int SIGN>
@@ -77,14 +95,21 @@ __device__ void fft_lds(float2* buf, const FftDesc& d, const float2* tw, int nba
     const int nr = n / r;
     const int tstep = n / (p * r);
     const int total = nbatch * nr;
+    const float inv_nr = 1.0f / (float)nr, inv_p = 1.0f / (float)p;
+    // butterfly g of the pass: sequence bt = g / nr, index k = g mod nr, i = k mod p
+    int bt_q[kFftMaxBfly], k_q[kFftMaxBfly], i_q[kFftMaxBfly];
     float2 v[kFftMaxBfly][4];
 #pragma unroll
     for (int q = 0; q < kFftMaxBfly; ++q) {
       const int g = tid + q * kFftThreads;
+      bt_q[q] = k_q[q] = i_q[q] = 0;
       if (g < total) {
-        const int bt = g / nr;
-        const int k = g - bt * nr;
-        const int i = k % p;
+        int k, i;
+        const int bt = fast_div(g, nr, inv_nr, k);
+        (void)fast_div(k, p, inv_p, i);
+        bt_q[q] = bt;
+        k_q[q] = k;
+        i_q[q] = i;
         fft_butterfly<SIGN>(buf + bt * stride + k, nr, r, i * tstep, tw, v[q]);
       }
     }
@@ -93,9 +118,7 @@ __device__ void fft_lds(float2* buf, const FftDesc& d, const float2* tw, int nba
     for (int q = 0; q < kFftMaxBfly; ++q) {
       const int g = tid + q * kFftThreads;
       if (g < total) {
-        const int bt = g / nr;
-        const int k = g - bt * nr;
-        const int i = k % p;
+        const int bt = bt_q[q], k = k_q[q], i = i_q[q];
         float2* o = buf + bt * stride + (k - i) * r + i;
         o[0] = v[q][0];
         o[p] = v[q][1];

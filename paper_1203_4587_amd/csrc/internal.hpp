@@ -144,6 +144,10 @@ struct cs_plan {
   std::vector<void*> owned;
   size_t bytes = 0;
 
+  // FFT tiles of the SENSE passes (0: the largest that fit; cs_plan_tune may pick smaller)
+  int fft_cw = 0;  // columns per workgroup, vertical passes
+  int fft_rb = 0;  // sampled rows per workgroup, horizontal passes
+
   // sampling pattern
   int m_max = 0;
   std::vector<int32_t> h_mcnt;  // sampled rows per frame
@@ -204,6 +208,8 @@ int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipS
 int launch_adjoint_rows(cs_plan* p, const float2* y, hipStream_t s);  // y -> p->ktmp
 int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s);  // p->ktmp -> x
 int launch_transpose(const float2* in, float2* out, int frames, int rows, int cols, hipStream_t s);
+int fft_cols_per_group(const cs_plan* p);
+int fft_rows_per_group(const cs_plan* p);
 
 // factor.hip
 int build_factor(cs_plan* p, float mu, hipStream_t s);

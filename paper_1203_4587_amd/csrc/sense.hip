@@ -42,16 +42,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_vertical(
   const int ncol = min(cw, nh - i0);
   for (int q = threadIdx.x; q < nv; q += kFftThreads) tw[q] = twv[q];
   const int tot = ncol * nv;
+  const float inv_nv = 1.0f / (float)nv, inv_ncol = 1.0f / (float)ncol;
   for (int e = threadIdx.x; e < tot; e += kFftThreads) {
     int j, col;
     float2 xv;
     if (COLMAJOR) {
-      col = e / nv;
-      j = e - col * nv;
+      col = fast_div(e, nv, inv_nv, j);
       xv = x[((size_t)t * nh + i0 + col) * nv + j];
     } else {
-      j = e / ncol;
-      col = e - j * ncol;
+      j = fast_div(e, ncol, inv_ncol, col);
       xv = x[((size_t)t * nv + j) * nh + i0 + col];
     }
     const float2 sv = coil_cm[((size_t)c * nh + i0 + col) * nv + j];
@@ -63,7 +62,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_vertical(
   const int32_t* rw = rows + (size_t)t * m_max;
   float2* out = ktmp + ((size_t)(t * nc + c) * m_max) * nh + i0;
   for (int e = threadIdx.x; e < m * ncol; e += kFftThreads) {
-    const int r = e / ncol, col = e - r * ncol;
+    int col;
+    const int r = fast_div(e, ncol, inv_ncol, col);
     out[(size_t)r * nh + col] = cscale(buf[col * stride + rw[r]], scale);
   }
 }
@@ -80,17 +80,20 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_horizontal(
   const int r0 = blockIdx.x * rb, t = blockIdx.y, c = blockIdx.z;
   const int nrow = min(rb, mcnt[t] - r0);
   if (nrow <= 0) return;  // uniform over the workgroup
+  const float inv_nh = 1.0f / (float)nh;
   for (int q = threadIdx.x; q < nh; q += kFftThreads) tw[q] = twh[q];
   const float2* src = ktmp + ((size_t)(t * nc + c) * m_max + r0) * nh;
   for (int e = threadIdx.x; e < nrow * nh; e += kFftThreads) {
-    const int rr = e / nh, i = e - rr * nh;
+    int i;
+    const int rr = fast_div(e, nh, inv_nh, i);
     buf[rr * stride + i] = src[(size_t)rr * nh + i];
   }
   __syncthreads();
   fft_lds<-1>(buf, fh, tw, nrow, stride);
   const int32_t* rw = rows + (size_t)t * m_max + r0;
   for (int e = threadIdx.x; e < nrow * nh; e += kFftThreads) {
-    const int rr = e / nh, i = e - rr * nh;
+    int i;
+    const int rr = fast_div(e, nh, inv_nh, i);
     y[((size_t)(t * nc + c) * nv + rw[rr]) * nh + i] = cscale(buf[rr * stride + i], scale);
   }
 }
@@ -116,17 +119,20 @@ __global__ __launch_bounds__(kFftThreads) void k_adj_horizontal(
   const int r0 = blockIdx.x * rb, t = blockIdx.y, c = blockIdx.z;
   const int nrow = min(rb, mcnt[t] - r0);
   if (nrow <= 0) return;
+  const float inv_nh = 1.0f / (float)nh;
   for (int q = threadIdx.x; q < nh; q += kFftThreads) tw[q] = twh[q];
   const int32_t* rw = rows + (size_t)t * m_max + r0;
   for (int e = threadIdx.x; e < nrow * nh; e += kFftThreads) {
-    const int rr = e / nh, i = e - rr * nh;
+    int i;
+    const int rr = fast_div(e, nh, inv_nh, i);
     buf[rr * stride + i] = y[((size_t)(t * nc + c) * nv + rw[rr]) * nh + i];
   }
   __syncthreads();
   fft_lds<+1>(buf, fh, tw, nrow, stride);
   float2* dst = ktmp + ((size_t)(t * nc + c) * m_max + r0) * nh;
   for (int e = threadIdx.x; e < nrow * nh; e += kFftThreads) {
-    const int rr = e / nh, i = e - rr * nh;
+    int i;
+    const int rr = fast_div(e, nh, inv_nh, i);
     dst[(size_t)rr * nh + i] = cscale(buf[rr * stride + i], scale);
   }
 }
@@ -146,6 +152,15 @@ __global__ __launch_bounds__(kFftThreads) void k_adj_vertical(
   const int ncol = min(cw, nh - i0);
   const int tot = ncol * nv;
   const int m = mcnt[t];
+  const float inv_nv = 1.0f / (float)nv, inv_ncol = 1.0f / (float)ncol;
+  // this thread's (column, row) pairs of the accumulation, fixed over the coils
+  int jq[kEPT], colq[kEPT];
+#pragma unroll
+  for (int q = 0; q < kEPT; ++q) {
+    const int e = threadIdx.x + q * kFftThreads;
+    if (COLMAJOR) colq[q] = fast_div(e, nv, inv_nv, jq[q]);
+    else jq[q] = fast_div(e, ncol, inv_ncol, colq[q]);
+  }
   const int32_t* rw = rows + (size_t)t * m_max;
   for (int q = threadIdx.x; q < nv; q += kFftThreads) tw[q] = twv[q];
   float2 acc[kEPT];
@@ -156,7 +171,8 @@ __global__ __launch_bounds__(kFftThreads) void k_adj_vertical(
     __syncthreads();
     const float2* src = ktmp + ((size_t)(t * nc + c) * m_max) * nh + i0;
     for (int e = threadIdx.x; e < m * ncol; e += kFftThreads) {
-      const int r = e / ncol, col = e - r * ncol;
+      int col;
+      const int r = fast_div(e, ncol, inv_ncol, col);
       buf[col * stride + rw[r]] = src[(size_t)r * nh + col];
     }
     __syncthreads();
@@ -165,14 +181,7 @@ __global__ __launch_bounds__(kFftThreads) void k_adj_vertical(
     for (int q = 0; q < kEPT; ++q) {
       const int e = threadIdx.x + q * kFftThreads;
       if (e < tot) {
-        int j, col;
-        if (COLMAJOR) {
-          col = e / nv;
-          j = e - col * nv;
-        } else {
-          j = e / ncol;
-          col = e - j * ncol;
-        }
+        const int j = jq[q], col = colq[q];
         const float2 sv = coil_cm[((size_t)c * nh + i0 + col) * nv + j];
         acc[q] = cfmac(sv, buf[col * stride + j], acc[q]);
       }
@@ -183,13 +192,9 @@ __global__ __launch_bounds__(kFftThreads) void k_adj_vertical(
   for (int q = 0; q < kEPT; ++q) {
     const int e = threadIdx.x + q * kFftThreads;
     if (e < tot) {
-      if (COLMAJOR) {
-        const int col = e / nv, j = e - col * nv;
-        x[((size_t)t * nh + i0 + col) * nv + j] = cscale(acc[q], scale);
-      } else {
-        const int j = e / ncol, col = e - j * ncol;
-        x[((size_t)t * nv + j) * nh + i0 + col] = cscale(acc[q], scale);
-      }
+      const int j = jq[q], col = colq[q];
+      if (COLMAJOR) x[((size_t)t * nh + i0 + col) * nv + j] = cscale(acc[q], scale);
+      else x[((size_t)t * nv + j) * nh + i0 + col] = cscale(acc[q], scale);
     }
   }
 }
@@ -216,6 +221,18 @@ __global__ void k_transpose(const float2* __restrict__ in, float2* __restrict__ 
 
 static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// columns per workgroup of the vertical passes and sampled rows per workgroup
+// of the horizontal passes: the largest that fit kFftElems values, or the
+// plan's tuned (smaller) choice
+int fft_cols_per_group(const cs_plan* p) {
+  const int full = std::min(p->desc.nh, kFftElems / p->desc.nv);
+  return p->fft_cw > 0 ? std::min(p->fft_cw, full) : full;
+}
+int fft_rows_per_group(const cs_plan* p) {
+  const int full = std::max(1, std::min(p->m_max, kFftElems / p->desc.nh));
+  return p->fft_rb > 0 ? std::min(p->fft_rb, full) : full;
+}
+
 int launch_transpose(const float2* in, float2* out, int frames, int rows, int cols, hipStream_t s) {
   if (frames <= 0) return CS_OK;
   dim3 grid(ceil_div(cols, 32), ceil_div(rows, 32), frames);
@@ -227,7 +244,7 @@ int launch_transpose(const float2* in, float2* out, int frames, int rows, int co
 int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipStream_t s) {
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
   if (p->m_max > 0) {
-    const int cw = std::min(nh, kFftElems / nv);
+    const int cw = fft_cols_per_group(p);
     const size_t lds1 = (size_t)(nv + cw * (nv + 1)) * sizeof(float2);
     dim3 g1(ceil_div(nh, cw), nt, nc);
     const float sv = 1.0f / std::sqrt((float)nv), sh = 1.0f / std::sqrt((float)nh);
@@ -239,7 +256,7 @@ int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipS
                          p->rows, p->mcnt, p->fft_v, p->tw_v, nv, nh, nc, p->m_max, cw, sv);
     CS_HIP(hipGetLastError());
     if (y) {
-      const int rb = std::max(1, std::min(p->m_max, kFftElems / nh));
+      const int rb = fft_rows_per_group(p);
       const size_t lds2 = (size_t)(nh + rb * (nh + 1)) * sizeof(float2);
       dim3 g2(ceil_div(p->m_max, rb), nt, nc);
       hipLaunchKernelGGL(k_fwd_horizontal, g2, dim3(kFftThreads), lds2, s, p->ftmp, y, p->rows, p->mcnt,
@@ -257,7 +274,7 @@ int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipS
 int launch_adjoint_rows(cs_plan* p, const float2* y, hipStream_t s) {
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
   if (p->m_max == 0) return CS_OK;
-  const int rb = std::max(1, std::min(p->m_max, kFftElems / nh));
+  const int rb = fft_rows_per_group(p);
   const size_t lds = (size_t)(nh + rb * (nh + 1)) * sizeof(float2);
   dim3 g(ceil_div(p->m_max, rb), nt, nc);
   hipLaunchKernelGGL(k_adj_horizontal, g, dim3(kFftThreads), lds, s, y, p->ktmp, p->rows, p->mcnt,
@@ -268,7 +285,7 @@ int launch_adjoint_rows(cs_plan* p, const float2* y, hipStream_t s) {
 
 int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s) {
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
-  const int cw = std::min(nh, kFftElems / nv);
+  const int cw = fft_cols_per_group(p);
   const size_t lds = (size_t)(nv + cw * (nv + 1)) * sizeof(float2);
   dim3 g(ceil_div(nh, cw), nt);
   const float sv = 1.0f / std::sqrt((float)nv);

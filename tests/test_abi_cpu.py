@@ -175,3 +175,9 @@ def test_delta_solve_rejects_bad_arguments(lib):
                                    None) == _lib.CS_EINVAL
     assert lib.cs_admm_solve_until(FAKE, FAKE, 0.01, 0.1, 10, float("nan"), 5, FAKE, None, ctypes.byref(n), None,
                                    None) == _lib.CS_EINVAL
+
+
+def test_fft_tile_calls_reject_bad_arguments(lib):
+    c, r = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.cs_plan_fft_tiles(None, ctypes.byref(c), ctypes.byref(r)) == _lib.CS_EINVAL
+    assert lib.cs_plan_set_fft_tiles(None, 4, 4) == _lib.CS_EINVAL
