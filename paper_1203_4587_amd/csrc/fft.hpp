@@ -16,8 +16,6 @@ namespace csmri {
 
 constexpr int kFftThreads = 256;      // workgroup size of every FFT kernel
 constexpr int kFftElems = 4096;       // nbatch * n handled by one workgroup
-constexpr int kFftMaxBfly = 8;        // kFftElems / 2 / kFftThreads: butterflies per thread in
-                                      // a radix-2 pass, the most of any radix
 
 template <int SIGN>
 __device__ __forceinline__ float2 twiddle(float2 u, float2 w) {
@@ -25,11 +23,10 @@ __device__ __forceinline__ float2 twiddle(float2 u, float2 w) {
   return SIGN < 0 ? cmul(u, w) : cmulc(w, u);
 }
 
-// Loads one butterfly's inputs, applies twiddles and the r-point DFT.
-template <int SIGN>
-__device__ __forceinline__ void fft_butterfly(const float2* s, int nr, int r, int tq, const float2* tw,
-                                     float2* v) {
-  if (r == 4) {
+// Loads one butterfly's inputs, applies twiddles and the R-point DFT.
+template <int SIGN, int R>
+__device__ __forceinline__ void fft_butterfly(const float2* s, int nr, int tq, const float2* tw, float2 (&v)[R]) {
+  if constexpr (R == 4) {
     float2 u0 = s[0], u1 = s[nr], u2 = s[2 * nr], u3 = s[3 * nr];
     if (tq) {
       u1 = twiddle<SIGN>(u1, tw[tq]);
@@ -43,7 +40,7 @@ __device__ __forceinline__ void fft_butterfly(const float2* s, int nr, int r, in
     v[1] = cadd(t1, wt3);
     v[2] = csub(t0, t2);
     v[3] = csub(t1, wt3);
-  } else if (r == 3) {
+  } else if constexpr (R == 3) {
     float2 u0 = s[0], u1 = s[nr], u2 = s[2 * nr];
     if (tq) {
       u1 = twiddle<SIGN>(u1, tw[tq]);
@@ -57,7 +54,8 @@ __device__ __forceinline__ void fft_butterfly(const float2* s, int nr, int r, in
     v[0] = cadd(u0, sm);
     v[1] = cadd(base, rot);
     v[2] = csub(base, rot);
-  } else {  // r == 2
+  } else {
+    static_assert(R == 2, "radix 2, 3 or 4");
     float2 u0 = s[0], u1 = s[nr];
     if (tq) u1 = twiddle<SIGN>(u1, tw[tq]);
     v[0] = cadd(u0, u1);
@@ -83,50 +81,58 @@ __device__ __forceinline__ int fast_div(int a, int b, float inv_b, int& rem) {
   return q;
 }
 
-// In-place transform of nbatch sequences; all threads of the (1-D, kFftThreads
-// wide) workgroup must call it.  Ends with a barrier.
+// One radix-R pass after a span p of earlier radices, in place: every thread
+// first computes its butterflies into registers, then all store after a
+// barrier.  R is a template argument so that the staging arrays are indexed
+// with constants only and stay in registers (a radix chosen at run time made
+// them a private-memory array).
+template <int SIGN, int R>
+__device__ __forceinline__ void fft_pass(float2* buf, const float2* tw, int n, int p, int nbatch, int stride) {
+  constexpr int kB = (kFftElems / R + kFftThreads - 1) / kFftThreads;  // butterflies per thread
+  const int tid = threadIdx.x;
+  const int nr = n / R;
+  const int tstep = n / (p * R);
+  const int total = nbatch * nr;
+  const float inv_nr = 1.0f / (float)nr, inv_p = 1.0f / (float)p;
+  float2 v[kB][R];
+  int dst[kB];
+#pragma unroll
+  for (int q = 0; q < kB; ++q) {
+    // butterfly g: sequence bt = g / nr, index k = g mod nr, i = k mod p
+    const int g = tid + q * kFftThreads;
+    dst[q] = -1;
+    if (g < total) {
+      int k, i;
+      const int bt = fast_div(g, nr, inv_nr, k);
+      (void)fast_div(k, p, inv_p, i);
+      fft_butterfly<SIGN, R>(buf + bt * stride + k, nr, i * tstep, tw, v[q]);
+      dst[q] = bt * stride + (k - i) * R + i;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kB; ++q) {
+    if (dst[q] >= 0) {
+      float2* o = buf + dst[q];
+#pragma unroll
+      for (int m = 0; m < R; ++m) o[m * p] = v[q][m];
+    }
+  }
+  __syncthreads();
+}
+
+// In-place transform of nbatch sequences (nbatch * n <= kFftElems); all
+// threads of the (1-D, kFftThreads wide) workgroup must call it.  Ends with a
+// barrier.
 template <int SIGN>
 __device__ void fft_lds(float2* buf, const FftDesc& d, const float2* tw, int nbatch, int stride) {
-  const int tid = threadIdx.x;
   const int n = d.n;
   int p = 1;
   for (int ps = 0; ps < d.npass; ++ps) {
     const int r = d.radix[ps];
-    const int nr = n / r;
-    const int tstep = n / (p * r);
-    const int total = nbatch * nr;
-    const float inv_nr = 1.0f / (float)nr, inv_p = 1.0f / (float)p;
-    // butterfly g of the pass: sequence bt = g / nr, index k = g mod nr, i = k mod p
-    int bt_q[kFftMaxBfly], k_q[kFftMaxBfly], i_q[kFftMaxBfly];
-    float2 v[kFftMaxBfly][4];
-#pragma unroll
-    for (int q = 0; q < kFftMaxBfly; ++q) {
-      const int g = tid + q * kFftThreads;
-      bt_q[q] = k_q[q] = i_q[q] = 0;
-      if (g < total) {
-        int k, i;
-        const int bt = fast_div(g, nr, inv_nr, k);
-        (void)fast_div(k, p, inv_p, i);
-        bt_q[q] = bt;
-        k_q[q] = k;
-        i_q[q] = i;
-        fft_butterfly<SIGN>(buf + bt * stride + k, nr, r, i * tstep, tw, v[q]);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kFftMaxBfly; ++q) {
-      const int g = tid + q * kFftThreads;
-      if (g < total) {
-        const int bt = bt_q[q], k = k_q[q], i = i_q[q];
-        float2* o = buf + bt * stride + (k - i) * r + i;
-        o[0] = v[q][0];
-        o[p] = v[q][1];
-        if (r > 2) o[2 * p] = v[q][2];
-        if (r > 3) o[3 * p] = v[q][3];
-      }
-    }
-    __syncthreads();
+    if (r == 4) fft_pass<SIGN, 4>(buf, tw, n, p, nbatch, stride);
+    else if (r == 3) fft_pass<SIGN, 3>(buf, tw, n, p, nbatch, stride);
+    else fft_pass<SIGN, 2>(buf, tw, n, p, nbatch, stride);
     p *= r;
   }
 }

@@ -138,8 +138,10 @@ __global__ __launch_bounds__(kFftThreads) void k_adj_horizontal(
 }
 
 // x_t[:, i] = (1/sqrt nv) sum_c conj(s_c[:, i]) . F_v' (zero-filled column of ktmp[t][c][:, i])
+// The coil sum lives in registers across the coil loop; two waves per SIMD
+// (instead of the one an unconstrained allocation leaves) measured 1.4x faster.
 template <bool COLMAJOR>
-__global__ __launch_bounds__(kFftThreads) void k_adj_vertical(
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_vertical(
     const float2* __restrict__ ktmp, const float2* __restrict__ coil_cm, float2* __restrict__ x,
     const int32_t* __restrict__ rows, const int32_t* __restrict__ mcnt, FftDesc fv,
     const float2* __restrict__ twv, int nv, int nh, int nc, int m_max, int cw, float scale) {
@@ -153,14 +155,13 @@ __global__ __launch_bounds__(kFftThreads) void k_adj_vertical(
   const int tot = ncol * nv;
   const int m = mcnt[t];
   const float inv_nv = 1.0f / (float)nv, inv_ncol = 1.0f / (float)ncol;
-  // this thread's (column, row) pairs of the accumulation, fixed over the coils
-  int jq[kEPT], colq[kEPT];
-#pragma unroll
-  for (int q = 0; q < kEPT; ++q) {
-    const int e = threadIdx.x + q * kFftThreads;
-    if (COLMAJOR) colq[q] = fast_div(e, nv, inv_nv, jq[q]);
-    else jq[q] = fast_div(e, ncol, inv_ncol, colq[q]);
-  }
+  // element e = threadIdx.x + q kFftThreads of the accumulation is the pair
+  // (column, row); the split is recomputed where it is used rather than held
+  // in registers across the coil loop
+  auto split = [&](int e, int& j, int& col) {
+    if (COLMAJOR) col = fast_div(e, nv, inv_nv, j);
+    else j = fast_div(e, ncol, inv_ncol, col);
+  };
   const int32_t* rw = rows + (size_t)t * m_max;
   for (int q = threadIdx.x; q < nv; q += kFftThreads) tw[q] = twv[q];
   float2 acc[kEPT];
@@ -181,7 +182,8 @@ __global__ __launch_bounds__(kFftThreads) void k_adj_vertical(
     for (int q = 0; q < kEPT; ++q) {
       const int e = threadIdx.x + q * kFftThreads;
       if (e < tot) {
-        const int j = jq[q], col = colq[q];
+        int j, col;
+        split(e, j, col);
         const float2 sv = coil_cm[((size_t)c * nh + i0 + col) * nv + j];
         acc[q] = cfmac(sv, buf[col * stride + j], acc[q]);
       }
@@ -192,7 +194,8 @@ __global__ __launch_bounds__(kFftThreads) void k_adj_vertical(
   for (int q = 0; q < kEPT; ++q) {
     const int e = threadIdx.x + q * kFftThreads;
     if (e < tot) {
-      const int j = jq[q], col = colq[q];
+      int j, col;
+      split(e, j, col);
       if (COLMAJOR) x[((size_t)t * nh + i0 + col) * nv + j] = cscale(acc[q], scale);
       else x[((size_t)t * nv + j) * nh + i0 + col] = cscale(acc[q], scale);
     }
