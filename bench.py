@@ -219,6 +219,61 @@ def unrolled_throughput(reps: int) -> dict:
     return res
 
 
+def step_rows(plan, problem, y, t_plan: float, prior: str) -> dict:
+    """Per-step figures beside the iteration: the SENSE forward and adjoint
+    passes (torch events on the stream they run on, mean of 20 calls), the
+    plan build (host clock), and one objective evaluation (HIP events the
+    library records around it during a traced solve)."""
+    import torch
+    nt, nv, nh = problem.x_true.shape
+    nc = problem.coil.shape[0]
+    m_rows = int(problem.mask.astype(bool).sum())           # sampled (frame, ky) rows
+    img, coil_b = 8 * nt * nv * nh, 8 * nc * nv * nh
+    sampled = 8 * m_rows * nc * nh                           # sampled rows of y, all coils
+
+    def event_us(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e3 / reps
+
+    def row(us, nbytes, what):
+        gbs = nbytes / (us * 1e-6) / 1e9
+        return {"us": round(us, 2), "algorithmic_bytes": nbytes, "bytes": what, "GBps": round(gbs, 1),
+                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+    x = plan.apply_AH(y)
+    yk = torch.empty_like(y)
+    xo = torch.empty_like(x)
+    a_us = event_us(lambda: plan.apply_A(x, out=yk))
+    ah_us = event_us(lambda: plan.apply_AH(y, out=xo))
+    rows = {
+        "apply_A": row(a_us, img + coil_b + 8 * nt * nc * nv * nh,
+                       "reads x and the coil maps, writes every k-space row (unsampled rows as zeros)"),
+        "apply_AH": row(ah_us, sampled + coil_b + img, "reads the sampled rows of y and the coil maps, writes x"),
+    }
+    gj_flops = 8.0 * nv ** 3 * nh * nt
+    rows["plan"] = {"s": round(t_plan, 4), "fp64_gauss_jordan_flops": gj_flops,
+                    "fp64_TFLOPs_over_plan": round(gj_flops / t_plan / 1e12, 2),
+                    "note": "whole plan build (Gram assembly, FP64 Gauss-Jordan inverse, packing) on the host clock"}
+    if prior != "frame":
+        plan.kernel_timing(True)
+        plan.solve(y, problem.lam, 20, trace=True)
+        torch.cuda.synchronize()
+        kt = plan.kernel_times()
+        plan.kernel_timing(False)
+        n, ms = kt.get("objective", (0, 0.0))
+        if n:
+            rows["objective"] = row(ms * 1e3 / n, img + coil_b + sampled,
+                                    "reads x, the coil maps and the hybrid-space data")
+    return rows
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +291,8 @@ def main() -> int:
     ap.add_argument("--no-unrolled", action="store_true", help="skip the differentiated-solve measurement")
     ap.add_argument("--unrolled-reps", type=int, default=10, help="timed forward+backward passes")
     ap.add_argument("--no-tune", action="store_true", help="time the default form instead of the tuned one")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the per-step figures (SENSE passes, plan, objective monitor)")
     ap.add_argument("--xu-form", choices=["wave", "group"], default=None,
                     help="force an x-update form (implies --no-tune; used for per-kernel counter passes)")
     ap.add_argument("--column-resident", action="store_true",
@@ -408,6 +465,8 @@ def main() -> int:
             "event_timed_iter_per_s": round(args.steps / elapsed_events, 2),
         },
     }
+    if not args.no_rows:
+        line["rows"] = step_rows(plan, problem, y, t_plan, wl["prior"])
     # the paper's stopping rule: iterate until Delta(k) < 1e-3 (checked every 5
     # iterations, J on the device), timed like the fixed-count solve
     if not args.no_delta:

@@ -167,16 +167,18 @@ int cs_admm_solve(cs_plan* plan, const cs_c64* y, float lambda, float mu, int32_
 int cs_plan_flags(const cs_plan* plan, uint32_t* flags);
 int cs_plan_set_flags(cs_plan* plan, uint32_t flags);
 
-/* FFT tiles of the SENSE passes: readout columns per workgroup of the vertical
+/* FFT tiles of the SENSE passes: readout columns per wave of the vertical
  * (phase-encode) FFTs and sampled rows per workgroup of the horizontal ones.
  * cs_plan_fft_tiles returns the values in use; cs_plan_set_fft_tiles sets
- * them (0 selects the largest tile that fits, larger values are clipped to
- * it).  Results do not depend on them. */
+ * them.  0 selects the default: as many columns as fit 256 values (one when
+ * nv > 256) and as many rows as fit 4096 values.  Larger values are clipped to
+ * 512 values per column group and 4096 per row group.  Results do not depend
+ * on them. */
 int cs_plan_fft_tiles(const cs_plan* plan, int32_t* cols, int32_t* rows);
 int cs_plan_set_fft_tiles(cs_plan* plan, int32_t cols, int32_t rows);
 
-/* Autotuner: first picks the FFT tiles (every pair from the largest tile down
- * to 1/16 of its columns and 1/4 of its rows, timed on H'y of y plus the
+/* Autotuner: first picks the FFT tiles (every pair from the largest tiles down
+ * to 1/16 of their columns and 1/4 of their rows, timed on H'y of y plus the
  * vertical forward pass), then times `iters` iterations (after as many untimed ones) of every
  * execution form the plan supports -- phase form with each x-update form
  * (graph-replayed), and the column-resident form -- on the data y, and keeps

@@ -762,15 +762,16 @@ int cs_plan_set_fft_tiles(cs_plan* p, int32_t cols, int32_t rows) {
   return CS_OK;
 }
 
-// FFT tiles of the SENSE passes: every (columns, rows) pair from the largest
-// tile down to 1/16 (columns) and 1/4 (rows) of it is timed on H'y of y (the
-// adjoint passes) followed by the vertical forward pass, which the objective
-// uses; the fastest is kept in the plan.
+// FFT tiles of the SENSE passes: every (columns per wave, rows per
+// workgroup) pair from the largest down to 1/16 (columns) and 1/4 (rows) of
+// it is timed on H'y of y (the adjoint passes) followed by the vertical
+// forward pass, which the objective uses; the fastest is kept in the plan.
 static int tune_fft_tiles(cs_plan* p, const cs_c64* y, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int save_cw = p->fft_cw, save_rb = p->fft_rb;
   p->fft_cw = 0;
   p->fft_rb = 0;
-  const int cw_full = fft_cols_per_group(p), rb_full = fft_rows_per_group(p);
+  const int cw_default = fft_cols_per_group(p);
+  const int cw_full = fft_cols_limit(p), rb_full = fft_rows_per_group(p);
   std::vector<int> cws, rbs;
   for (int d = 1; d <= 16; d *= 2)
     if (cw_full / d >= 1 && (cws.empty() || cws.back() != cw_full / d)) cws.push_back(cw_full / d);
@@ -808,7 +809,7 @@ static int tune_fft_tiles(cs_plan* p, const cs_c64* y, hipStream_t s, hipEvent_t
     p->fft_rb = save_rb;
     return st;
   }
-  p->fft_cw = bcw == cw_full ? 0 : bcw;
+  p->fft_cw = bcw == cw_default ? 0 : bcw;
   p->fft_rb = brb == rb_full ? 0 : brb;
   return CS_OK;
 }

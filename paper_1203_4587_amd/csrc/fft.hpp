@@ -1,7 +1,8 @@
 // LDS-resident mixed-radix (2, 3, 4) Stockham FFT used by the SENSE operator
-// kernels.  A workgroup transforms `nbatch` independent length-n sequences
-// stored at buf[b * stride + q]; the passes run in place with a register
-// stage between two barriers, so one LDS buffer suffices.
+// kernels.  A group of threads (a workgroup, or a single wave working in its
+// own LDS region) transforms `nbatch` independent length-n sequences stored
+// at buf[b * stride + q]; the passes run in place with a register stage
+// between two barriers, so one LDS buffer suffices.
 //
 // Pass with radix r after a span p of earlier radices: butterfly k in
 // [0, n/r) reads u_m = x[k + m n/r] (m < r), multiplies u_m by
@@ -14,8 +15,9 @@
 
 namespace csmri {
 
-constexpr int kFftThreads = 256;      // workgroup size of every FFT kernel
-constexpr int kFftElems = 4096;       // nbatch * n handled by one workgroup
+constexpr int kFftThreads = 256;      // workgroup size of the horizontal FFT kernels
+constexpr int kFftElems = 4096;       // nbatch * n handled by one such workgroup
+constexpr int kWaveElems = 512;       // nbatch * n handled by one wave (vertical passes)
 
 template <int SIGN>
 __device__ __forceinline__ float2 twiddle(float2 u, float2 w) {
@@ -81,15 +83,25 @@ __device__ __forceinline__ int fast_div(int a, int b, float inv_b, int& rem) {
   return q;
 }
 
-// One radix-R pass after a span p of earlier radices, in place: every thread
-// first computes its butterflies into registers, then all store after a
-// barrier.  R is a template argument so that the staging arrays are indexed
-// with constants only and stay in registers (a radix chosen at run time made
-// them a private-memory array).
-template <int SIGN, int R>
-__device__ __forceinline__ void fft_pass(float2* buf, const float2* tw, int n, int p, int nbatch, int stride) {
-  constexpr int kB = (kFftElems / R + kFftThreads - 1) / kFftThreads;  // butterflies per thread
-  const int tid = threadIdx.x;
+// Barrier between the read and write halves of a pass: the whole workgroup,
+// or only the wave when the buffer is private to it (a wave's LDS accesses
+// complete in issue order, so only code motion has to be fenced).
+template <bool WAVE>
+__device__ __forceinline__ void fft_sync() {
+  if constexpr (WAVE) __builtin_amdgcn_wave_barrier();
+  else __syncthreads();
+}
+
+// One radix-R pass after a span p of earlier radices, in place, by THREADS
+// threads (thread index tid) over at most ELEMS values: every thread first
+// computes its butterflies into registers, then all store after a barrier.
+// R is a template argument so that the staging arrays are indexed with
+// constants only and stay in registers (a radix chosen at run time made them
+// a private-memory array).
+template <int SIGN, int R, int THREADS, int ELEMS, bool WAVE>
+__device__ __forceinline__ void fft_pass(float2* buf, const float2* tw, int n, int p, int nbatch, int stride,
+                                         int tid) {
+  constexpr int kB = (ELEMS / R + THREADS - 1) / THREADS;  // butterflies per thread
   const int nr = n / R;
   const int tstep = n / (p * R);
   const int total = nbatch * nr;
@@ -99,7 +111,7 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* tw, int n, i
 #pragma unroll
   for (int q = 0; q < kB; ++q) {
     // butterfly g: sequence bt = g / nr, index k = g mod nr, i = k mod p
-    const int g = tid + q * kFftThreads;
+    const int g = tid + q * THREADS;
     dst[q] = -1;
     if (g < total) {
       int k, i;
@@ -109,7 +121,7 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* tw, int n, i
       dst[q] = bt * stride + (k - i) * R + i;
     }
   }
-  __syncthreads();
+  fft_sync<WAVE>();
 #pragma unroll
   for (int q = 0; q < kB; ++q) {
     if (dst[q] >= 0) {
@@ -118,23 +130,39 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* tw, int n, i
       for (int m = 0; m < R; ++m) o[m * p] = v[q][m];
     }
   }
-  __syncthreads();
+  fft_sync<WAVE>();
 }
 
-// In-place transform of nbatch sequences (nbatch * n <= kFftElems); all
-// threads of the (1-D, kFftThreads wide) workgroup must call it.  Ends with a
-// barrier.
-template <int SIGN>
-__device__ void fft_lds(float2* buf, const FftDesc& d, const float2* tw, int nbatch, int stride) {
+template <int SIGN, int THREADS, int ELEMS, bool WAVE>
+__device__ __forceinline__ void fft_passes(float2* buf, const FftDesc& d, const float2* tw, int nbatch, int stride,
+                                           int tid) {
   const int n = d.n;
   int p = 1;
   for (int ps = 0; ps < d.npass; ++ps) {
     const int r = d.radix[ps];
-    if (r == 4) fft_pass<SIGN, 4>(buf, tw, n, p, nbatch, stride);
-    else if (r == 3) fft_pass<SIGN, 3>(buf, tw, n, p, nbatch, stride);
-    else fft_pass<SIGN, 2>(buf, tw, n, p, nbatch, stride);
+    if (r == 4) fft_pass<SIGN, 4, THREADS, ELEMS, WAVE>(buf, tw, n, p, nbatch, stride, tid);
+    else if (r == 3) fft_pass<SIGN, 3, THREADS, ELEMS, WAVE>(buf, tw, n, p, nbatch, stride, tid);
+    else fft_pass<SIGN, 2, THREADS, ELEMS, WAVE>(buf, tw, n, p, nbatch, stride, tid);
     p *= r;
   }
+}
+
+// In-place transform of nbatch sequences (nbatch * n <= kFftElems) by the
+// whole (1-D, kFftThreads wide) workgroup; all threads must call it.  Ends
+// with a barrier.
+template <int SIGN>
+__device__ void fft_lds(float2* buf, const FftDesc& d, const float2* tw, int nbatch, int stride) {
+  fft_passes<SIGN, kFftThreads, kFftElems, false>(buf, d, tw, nbatch, stride, threadIdx.x);
+}
+
+// In-place transform of nbatch sequences (nbatch * n <= WE <= kWaveElems) in
+// a buffer private to the calling wave; all 64 lanes must call it.  Ends with
+// a wave barrier.
+template <int SIGN, int WE>
+__device__ __forceinline__ void fft_wave(float2* buf, const FftDesc& d, const float2* tw, int nbatch, int stride,
+                                         int lane) {
+  static_assert(WE <= kWaveElems, "wave transform larger than its buffer bound");
+  fft_passes<SIGN, 64, WE, true>(buf, d, tw, nbatch, stride, lane);
 }
 
 }  // namespace csmri

@@ -173,8 +173,8 @@ struct cs_plan {
   csmri::FactorLayout flayout{};
 
   // workspaces (solver layout [t][i][j], i.e. column-contiguous)
-  float2* ktmp = nullptr;       // [nt][nc][m_max][nh] hybrid-space rows of the data, F_h' y
-  float2* ftmp = nullptr;       // [nt][nc][m_max][nh] forward intermediate, M_t F_v (s_c . x)
+  float2* ktmp = nullptr;       // [nt][nc][nh][m_max] hybrid-space rows of the data, F_h' y
+  float2* ftmp = nullptr;       // [nt][nc][nh][m_max] forward intermediate, M_t F_v (s_c . x)
   float2* hy = nullptr;         // H'y
   float2* s0 = nullptr;         // TV: m   DFT: d
   float2* s1 = nullptr;         // TV: d1  DFT: v
@@ -206,9 +206,12 @@ namespace csmri {
 // sense.hip
 int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipStream_t s);
 int launch_adjoint_rows(cs_plan* p, const float2* y, hipStream_t s);  // y -> p->ktmp
+// sum |M_t F_v (s_c . x) - ktmp|^2, one FP64 partial per workgroup of an nblocks grid (x column-major)
+int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nblocks, hipStream_t s);
 int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s);  // p->ktmp -> x
 int launch_transpose(const float2* in, float2* out, int frames, int rows, int cols, hipStream_t s);
 int fft_cols_per_group(const cs_plan* p);
+int fft_cols_limit(const cs_plan* p);
 int fft_rows_per_group(const cs_plan* p);
 
 // factor.hip

@@ -1225,7 +1225,7 @@ int launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s) {
 // rows r.  l1 = sum |D_t x| (TV) or sum |Psi x| (DFT), moduli of complex
 // values.  Partial sums are FP64 and reduced in a fixed order, so the value
 // is bit-reproducible run to run.
-constexpr int kJBlocks = 512;
+constexpr int kJBlocks = 1024;
 constexpr int kJThreads = 256;
 
 __device__ __forceinline__ void block_reduce_store(double v, double* out) {
@@ -1237,25 +1237,6 @@ __device__ __forceinline__ void block_reduce_store(double v, double* out) {
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = red[0];
-}
-
-__global__ __launch_bounds__(kJThreads) void k_resid_partial(const float2* __restrict__ f,
-                                                             const float2* __restrict__ g,
-                                                             const int32_t* __restrict__ mcnt, int nc,
-                                                             int m_max, int nh, int nt, double* __restrict__ part) {
-  const size_t per_frame = (size_t)nc * m_max * nh;
-  const size_t total = per_frame * nt;
-  double acc = 0.0;
-  for (size_t q = (size_t)blockIdx.x * kJThreads + threadIdx.x; q < total; q += (size_t)kJBlocks * kJThreads) {
-    const int t = (int)(q / per_frame);
-    const int r = (int)((q / nh) % m_max);
-    if (r < mcnt[t]) {
-      const float2 a = f[q], b = g[q];
-      const double dx = (double)a.x - b.x, dy = (double)a.y - b.y;
-      acc += dx * dx + dy * dy;
-    }
-  }
-  block_reduce_store(acc, part + blockIdx.x);
 }
 
 __global__ __launch_bounds__(kJThreads) void k_l1_tv_partial(const float2* __restrict__ x, int nt, size_t npix,
@@ -1318,10 +1299,8 @@ static void l1_dft_launch(cs_plan* p, const float2* x, hipStream_t s) {
 int launch_objective(cs_plan* p, const float2* x, float lambda, float* out, hipStream_t s) {
   const int nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
   const size_t npix = (size_t)p->desc.nv * nh;
-  int st = launch_forward(p, x, true, nullptr, s);
+  int st = launch_forward_residual(p, x, p->jpart, kJBlocks, s);  // data term, fused with the vertical pass
   if (st != CS_OK) return st;
-  hipLaunchKernelGGL(k_resid_partial, dim3(kJBlocks), dim3(kJThreads), 0, s, p->ftmp, p->ktmp, p->mcnt, nc,
-                     p->m_max, nh, nt, p->jpart);
   if (p->desc.prior == CS_PRIOR_TEMPORAL_TV) {
     hipLaunchKernelGGL(k_l1_tv_partial, dim3(kJBlocks), dim3(kJThreads), 0, s, x, nt, npix,
                        p->jpart + kJBlocks);

@@ -1,12 +1,21 @@
 // Measurement operator H and its adjoint (Sec. II-A, eqs. mri_mcoil2,
 // mri_csmcoill2, H_2):   y_{t,c} = F_h M_t F_v (s_c . x_t).
 //
-// Forward: a vertical pass (coil multiply fused into the load, length-nv FFT
-// of every column, only the sampled ky rows kept) followed by a horizontal
-// pass over the sampled rows only, so the horizontal work is 1/R of a full
-// 2D FFT.  Rows ky that a frame does not sample are zero-filled by a third,
-// store-only kernel.  The adjoint runs the same passes in reverse order and
-// sums conj(s_c) . (.) over coils in registers before the single store.
+// Forward: a vertical pass (length-nv FFT of every column of s_c . x_t, only
+// the sampled ky rows kept) followed by a horizontal pass over the sampled
+// rows only, so the horizontal work is 1/R of a full 2D FFT.  Rows ky that a
+// frame does not sample are zero-filled by a third, store-only kernel.  The
+// adjoint runs the same passes in reverse order.
+//
+// The vertical passes work on the solver's column-major image layout
+// [t][i][j]: one wave owns a group of adjacent columns of one frame, keeps
+// them in registers, and runs every coil's transform in an LDS region of its
+// own, so no workgroup barrier is involved and each image value is read once
+// for all coils (the adjoint sums conj(s_c) . (.) over coils in registers
+// before its single store).  Between the two passes the sampled rows live in
+// hybrid (ky, i) space as [t][c][i][r] (r < m_max fastest), so the rows of one
+// column are contiguous for the vertical passes.  The row-major [t][j][i]
+// layout of the boundary goes through a tiled transpose.
 #include "fft.hpp"
 
 namespace csmri {
@@ -28,49 +37,109 @@ bool make_fft_desc(int n, FftDesc* d) {
 
 // ---------------------------------------------------------------- kernels
 
-// ktmp[t][c][r][i] = (1/sqrt nv) * (F_v (s_c . x_t))[rows[t][r], i]
-template <bool COLMAJOR>
-__global__ __launch_bounds__(kFftThreads) void k_fwd_vertical(
-    const float2* __restrict__ x, const float2* __restrict__ coil_cm, float2* __restrict__ ktmp,
-    const int32_t* __restrict__ rows, const int32_t* __restrict__ mcnt, FftDesc fv,
-    const float2* __restrict__ twv, int nv, int nh, int nc, int m_max, int cw, float scale) {
+constexpr int kVWaves = 4;  // waves per workgroup of the vertical passes
+// A column group holds at most WE = 256 or 512 values (WE / 64 per lane); the
+// kernels are compiled for both so that groups of up to 256 values carry half
+// the registers.
+
+// Per-lane part of a column group: element e = lane + 64 q of the group's
+// ncol * nv values, which sit contiguously in the column-major image.
+struct ColGroup {
+  int t, i0, ncol, tot;
+};
+
+__device__ __forceinline__ ColGroup col_group(int u, int ngrp, int cw, int nv, int nh) {
+  ColGroup g;
+  g.t = u / ngrp;
+  g.i0 = (u - g.t * ngrp) * cw;
+  g.ncol = min(cw, nh - g.i0);
+  g.tot = g.ncol * nv;
+  return g;
+}
+
+// MODE kFwdStore:    hyb[t][c][i][r] = (1/sqrt nv) (F_v (s_c . x_t))[rows[t][r], i]
+// MODE kFwdResidual: sum over (t, c, i, r < mcnt[t]) of |that value - ref[t][c][i][r]|^2,
+//                    one FP64 partial per workgroup (grid-stride over column
+//                    groups with a fixed grid, so the sum is reproducible)
+constexpr int kFwdStore = 0, kFwdResidual = 1;
+
+template <int MODE, int WE>
+__global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical(
+    const float2* __restrict__ x, const float2* __restrict__ coil_cm, float2* __restrict__ hyb,
+    const float2* __restrict__ ref, const int32_t* __restrict__ rows, const int32_t* __restrict__ mcnt,
+    FftDesc fv, const float2* __restrict__ twv, int nv, int nh, int nt, int nc, int m_max, int cw, float scale,
+    double* __restrict__ part) {
+  constexpr int kVE = WE / 64;  // image values per lane of one column group
   extern __shared__ float2 lds[];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float2* tw = lds;
-  float2* buf = lds + nv;
-  const int stride = nv + 1;
-  const int i0 = blockIdx.x * cw, t = blockIdx.y, c = blockIdx.z;
-  const int ncol = min(cw, nh - i0);
-  for (int q = threadIdx.x; q < nv; q += kFftThreads) tw[q] = twv[q];
-  const int tot = ncol * nv;
-  const float inv_nv = 1.0f / (float)nv, inv_ncol = 1.0f / (float)ncol;
-  for (int e = threadIdx.x; e < tot; e += kFftThreads) {
-    int j, col;
-    float2 xv;
-    if (COLMAJOR) {
-      col = fast_div(e, nv, inv_nv, j);
-      xv = x[((size_t)t * nh + i0 + col) * nv + j];
-    } else {
-      j = fast_div(e, ncol, inv_ncol, col);
-      xv = x[((size_t)t * nv + j) * nh + i0 + col];
-    }
-    const float2 sv = coil_cm[((size_t)c * nh + i0 + col) * nv + j];
-    buf[col * stride + j] = cmul(sv, xv);
-  }
+  float2* buf = lds + nv + (size_t)wv * cw * nv;
+  for (int q = threadIdx.x; q < nv; q += blockDim.x) tw[q] = twv[q];
   __syncthreads();
-  fft_lds<-1>(buf, fv, tw, ncol, stride);
-  const int m = mcnt[t];
-  const int32_t* rw = rows + (size_t)t * m_max;
-  float2* out = ktmp + ((size_t)(t * nc + c) * m_max) * nh + i0;
-  for (int e = threadIdx.x; e < m * ncol; e += kFftThreads) {
-    int col;
-    const int r = fast_div(e, ncol, inv_ncol, col);
-    out[(size_t)r * nh + col] = cscale(buf[col * stride + rw[r]], scale);
+  const int ngrp = (nh + cw - 1) / cw;
+  const int units = nt * ngrp;
+  double acc = 0.0;
+  for (int u = blockIdx.x * kVWaves + wv; u < units; u += gridDim.x * kVWaves) {
+    const ColGroup g = col_group(u, ngrp, cw, nv, nh);
+    const float2* xs = x + ((size_t)g.t * nh + g.i0) * nv;
+    float2 xv[kVE], cv[kVE];
+#pragma unroll
+    for (int q = 0; q < kVE; ++q) {
+      const int e = lane + 64 * q;
+      xv[q] = e < g.tot ? xs[e] : make_float2(0.f, 0.f);
+      cv[q] = e < g.tot ? coil_cm[(size_t)g.i0 * nv + e] : make_float2(0.f, 0.f);
+    }
+    const int m = mcnt[g.t];
+    const int32_t* rw = rows + (size_t)g.t * m_max;
+    const float inv_m = 1.0f / (float)max(m, 1);
+    for (int c = 0; c < nc; ++c) {
+#pragma unroll
+      for (int q = 0; q < kVE; ++q) {
+        const int e = lane + 64 * q;
+        if (e < g.tot) buf[e] = cmul(cv[q], xv[q]);
+      }
+      // the next coil's values are requested before this coil's transform
+      if (c + 1 < nc) {
+        const float2* cs = coil_cm + ((size_t)(c + 1) * nh + g.i0) * nv;
+#pragma unroll
+        for (int q = 0; q < kVE; ++q) {
+          const int e = lane + 64 * q;
+          if (e < g.tot) cv[q] = cs[e];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      fft_wave<-1, WE>(buf, fv, tw, g.ncol, nv, lane);
+      const size_t ob = (((size_t)g.t * nc + c) * nh + g.i0) * m_max;
+      for (int e = lane; e < g.ncol * m; e += 64) {
+        int r;
+        const int col = fast_div(e, m, inv_m, r);
+        const float2 v = cscale(buf[col * nv + rw[r]], scale);
+        if constexpr (MODE == kFwdStore) {
+          hyb[ob + (size_t)col * m_max + r] = v;
+        } else {
+          const float2 b = ref[ob + (size_t)col * m_max + r];
+          const double dx = (double)v.x - b.x, dy = (double)v.y - b.y;
+          acc += dx * dx + dy * dy;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();  // the next coil overwrites buf
+    }
+  }
+  if constexpr (MODE == kFwdResidual) {
+    __shared__ double red[64 * kVWaves];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 32 * kVWaves; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
   }
 }
 
-// y[t][c][rows[t][r]][:] = (1/sqrt nh) F_h ktmp[t][c][r][:]
+// y[t][c][rows[t][r]][:] = (1/sqrt nh) F_h hyb[t][c][:][r]
 __global__ __launch_bounds__(kFftThreads) void k_fwd_horizontal(
-    const float2* __restrict__ ktmp, float2* __restrict__ y, const int32_t* __restrict__ rows,
+    const float2* __restrict__ hyb, float2* __restrict__ y, const int32_t* __restrict__ rows,
     const int32_t* __restrict__ mcnt, FftDesc fh, const float2* __restrict__ twh, int nv, int nh,
     int nc, int m_max, int rb, float scale) {
   extern __shared__ float2 lds[];
@@ -80,13 +149,13 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_horizontal(
   const int r0 = blockIdx.x * rb, t = blockIdx.y, c = blockIdx.z;
   const int nrow = min(rb, mcnt[t] - r0);
   if (nrow <= 0) return;  // uniform over the workgroup
-  const float inv_nh = 1.0f / (float)nh;
+  const float inv_nh = 1.0f / (float)nh, inv_nrow = 1.0f / (float)nrow;
   for (int q = threadIdx.x; q < nh; q += kFftThreads) tw[q] = twh[q];
-  const float2* src = ktmp + ((size_t)(t * nc + c) * m_max + r0) * nh;
+  const float2* src = hyb + ((size_t)(t * nc + c) * nh) * m_max + r0;
   for (int e = threadIdx.x; e < nrow * nh; e += kFftThreads) {
-    int i;
-    const int rr = fast_div(e, nh, inv_nh, i);
-    buf[rr * stride + i] = src[(size_t)rr * nh + i];
+    int rr;
+    const int i = fast_div(e, nrow, inv_nrow, rr);
+    buf[rr * stride + i] = src[(size_t)i * m_max + rr];
   }
   __syncthreads();
   fft_lds<-1>(buf, fh, tw, nrow, stride);
@@ -107,9 +176,9 @@ __global__ void k_zero_unsampled(float2* __restrict__ y, const uint8_t* __restri
   for (int i = threadIdx.x; i < nh; i += blockDim.x) line[i] = make_float2(0.f, 0.f);
 }
 
-// ktmp[t][c][r][:] = (1/sqrt nh) F_h' y[t][c][rows[t][r]][:]   (hybrid space)
+// hyb[t][c][:][r] = (1/sqrt nh) F_h' y[t][c][rows[t][r]][:]   (hybrid space)
 __global__ __launch_bounds__(kFftThreads) void k_adj_horizontal(
-    const float2* __restrict__ y, float2* __restrict__ ktmp, const int32_t* __restrict__ rows,
+    const float2* __restrict__ y, float2* __restrict__ hyb, const int32_t* __restrict__ rows,
     const int32_t* __restrict__ mcnt, FftDesc fh, const float2* __restrict__ twh, int nv, int nh,
     int nc, int m_max, int rb, float scale) {
   extern __shared__ float2 lds[];
@@ -119,7 +188,7 @@ __global__ __launch_bounds__(kFftThreads) void k_adj_horizontal(
   const int r0 = blockIdx.x * rb, t = blockIdx.y, c = blockIdx.z;
   const int nrow = min(rb, mcnt[t] - r0);
   if (nrow <= 0) return;
-  const float inv_nh = 1.0f / (float)nh;
+  const float inv_nh = 1.0f / (float)nh, inv_nrow = 1.0f / (float)nrow;
   for (int q = threadIdx.x; q < nh; q += kFftThreads) tw[q] = twh[q];
   const int32_t* rw = rows + (size_t)t * m_max + r0;
   for (int e = threadIdx.x; e < nrow * nh; e += kFftThreads) {
@@ -129,75 +198,68 @@ __global__ __launch_bounds__(kFftThreads) void k_adj_horizontal(
   }
   __syncthreads();
   fft_lds<+1>(buf, fh, tw, nrow, stride);
-  float2* dst = ktmp + ((size_t)(t * nc + c) * m_max + r0) * nh;
+  float2* dst = hyb + ((size_t)(t * nc + c) * nh) * m_max + r0;
   for (int e = threadIdx.x; e < nrow * nh; e += kFftThreads) {
-    int i;
-    const int rr = fast_div(e, nh, inv_nh, i);
-    dst[(size_t)rr * nh + i] = cscale(buf[rr * stride + i], scale);
+    int rr;
+    const int i = fast_div(e, nrow, inv_nrow, rr);
+    dst[(size_t)i * m_max + rr] = cscale(buf[rr * stride + i], scale);
   }
 }
 
-// x_t[:, i] = (1/sqrt nv) sum_c conj(s_c[:, i]) . F_v' (zero-filled column of ktmp[t][c][:, i])
-// The coil sum lives in registers across the coil loop; two waves per SIMD
-// (instead of the one an unconstrained allocation leaves) measured 1.4x faster.
-template <bool COLMAJOR>
-__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_vertical(
-    const float2* __restrict__ ktmp, const float2* __restrict__ coil_cm, float2* __restrict__ x,
+// x_t[:, i] = (1/sqrt nv) sum_c conj(s_c[:, i]) . F_v' (column i of hyb[t][c],
+// zero-filled at the rows the frame does not sample); x column-major
+template <int WE>
+__global__ __launch_bounds__(64 * kVWaves) void k_adj_vertical(
+    const float2* __restrict__ hyb, const float2* __restrict__ coil_cm, float2* __restrict__ x,
     const int32_t* __restrict__ rows, const int32_t* __restrict__ mcnt, FftDesc fv,
-    const float2* __restrict__ twv, int nv, int nh, int nc, int m_max, int cw, float scale) {
-  constexpr int kEPT = kFftElems / kFftThreads;
+    const float2* __restrict__ twv, int nv, int nh, int nt, int nc, int m_max, int cw, float scale) {
+  constexpr int kVE = WE / 64;  // image values per lane of one column group
   extern __shared__ float2 lds[];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float2* tw = lds;
-  float2* buf = lds + nv;
-  const int stride = nv + 1;
-  const int i0 = blockIdx.x * cw, t = blockIdx.y;
-  const int ncol = min(cw, nh - i0);
-  const int tot = ncol * nv;
-  const int m = mcnt[t];
-  const float inv_nv = 1.0f / (float)nv, inv_ncol = 1.0f / (float)ncol;
-  // element e = threadIdx.x + q kFftThreads of the accumulation is the pair
-  // (column, row); the split is recomputed where it is used rather than held
-  // in registers across the coil loop
-  auto split = [&](int e, int& j, int& col) {
-    if (COLMAJOR) col = fast_div(e, nv, inv_nv, j);
-    else j = fast_div(e, ncol, inv_ncol, col);
-  };
-  const int32_t* rw = rows + (size_t)t * m_max;
-  for (int q = threadIdx.x; q < nv; q += kFftThreads) tw[q] = twv[q];
-  float2 acc[kEPT];
+  float2* buf = lds + nv + (size_t)wv * cw * nv;
+  for (int q = threadIdx.x; q < nv; q += blockDim.x) tw[q] = twv[q];
+  __syncthreads();
+  const int ngrp = (nh + cw - 1) / cw;
+  const int units = nt * ngrp;
+  for (int u = blockIdx.x * kVWaves + wv; u < units; u += gridDim.x * kVWaves) {
+    const ColGroup g = col_group(u, ngrp, cw, nv, nh);
+    const int m = mcnt[g.t];
+    const int32_t* rw = rows + (size_t)g.t * m_max;
+    const float inv_m = 1.0f / (float)max(m, 1);
+    float2 acc[kVE];
 #pragma unroll
-  for (int q = 0; q < kEPT; ++q) acc[q] = make_float2(0.f, 0.f);
-  for (int c = 0; c < nc; ++c) {
-    for (int e = threadIdx.x; e < ncol * stride; e += kFftThreads) buf[e] = make_float2(0.f, 0.f);
-    __syncthreads();
-    const float2* src = ktmp + ((size_t)(t * nc + c) * m_max) * nh + i0;
-    for (int e = threadIdx.x; e < m * ncol; e += kFftThreads) {
-      int col;
-      const int r = fast_div(e, ncol, inv_ncol, col);
-      buf[col * stride + rw[r]] = src[(size_t)r * nh + col];
-    }
-    __syncthreads();
-    fft_lds<+1>(buf, fv, tw, ncol, stride);
+    for (int q = 0; q < kVE; ++q) acc[q] = make_float2(0.f, 0.f);
+    for (int c = 0; c < nc; ++c) {
+      const float2* cs = coil_cm + ((size_t)c * nh + g.i0) * nv;
+      float2 cv[kVE];
 #pragma unroll
-    for (int q = 0; q < kEPT; ++q) {
-      const int e = threadIdx.x + q * kFftThreads;
-      if (e < tot) {
-        int j, col;
-        split(e, j, col);
-        const float2 sv = coil_cm[((size_t)c * nh + i0 + col) * nv + j];
-        acc[q] = cfmac(sv, buf[col * stride + j], acc[q]);
+      for (int q = 0; q < kVE; ++q) {
+        const int e = lane + 64 * q;
+        cv[q] = e < g.tot ? cs[e] : make_float2(0.f, 0.f);
+        if (e < g.tot) buf[e] = make_float2(0.f, 0.f);
       }
-    }
-    __syncthreads();
-  }
+      __builtin_amdgcn_wave_barrier();
+      const float2* src = hyb + (((size_t)g.t * nc + c) * nh + g.i0) * m_max;
+      for (int e = lane; e < g.ncol * m; e += 64) {
+        int r;
+        const int col = fast_div(e, m, inv_m, r);
+        buf[col * nv + rw[r]] = src[(size_t)col * m_max + r];
+      }
+      __builtin_amdgcn_wave_barrier();
+      fft_wave<+1, WE>(buf, fv, tw, g.ncol, nv, lane);
 #pragma unroll
-  for (int q = 0; q < kEPT; ++q) {
-    const int e = threadIdx.x + q * kFftThreads;
-    if (e < tot) {
-      int j, col;
-      split(e, j, col);
-      if (COLMAJOR) x[((size_t)t * nh + i0 + col) * nv + j] = cscale(acc[q], scale);
-      else x[((size_t)t * nv + j) * nh + i0 + col] = cscale(acc[q], scale);
+      for (int q = 0; q < kVE; ++q) {
+        const int e = lane + 64 * q;
+        if (e < g.tot) acc[q] = cfmac(cv[q], buf[e], acc[q]);
+      }
+      __builtin_amdgcn_wave_barrier();  // the next coil overwrites buf
+    }
+    float2* xs = x + ((size_t)g.t * nh + g.i0) * nv;
+#pragma unroll
+    for (int q = 0; q < kVE; ++q) {
+      const int e = lane + 64 * q;
+      if (e < g.tot) xs[e] = cscale(acc[q], scale);
     }
   }
 }
@@ -224,12 +286,14 @@ __global__ void k_transpose(const float2* __restrict__ in, float2* __restrict__ 
 
 static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// columns per workgroup of the vertical passes and sampled rows per workgroup
-// of the horizontal passes: the largest that fit kFftElems values, or the
-// plan's tuned (smaller) choice
+// columns per wave of the vertical passes: by default the most that fit 256
+// values (one column when nv > 256), or the plan's tuned choice of at most
+// fft_cols_limit; sampled rows per workgroup of the horizontal passes: the
+// most that fit kFftElems values, or the plan's tuned (smaller) choice
+int fft_cols_limit(const cs_plan* p) { return std::max(1, std::min(p->desc.nh, kWaveElems / p->desc.nv)); }
 int fft_cols_per_group(const cs_plan* p) {
-  const int full = std::min(p->desc.nh, kFftElems / p->desc.nv);
-  return p->fft_cw > 0 ? std::min(p->fft_cw, full) : full;
+  if (p->fft_cw > 0) return std::min(p->fft_cw, fft_cols_limit(p));
+  return std::max(1, std::min(p->desc.nh, 256 / p->desc.nv));
 }
 int fft_rows_per_group(const cs_plan* p) {
   const int full = std::max(1, std::min(p->m_max, kFftElems / p->desc.nh));
@@ -244,19 +308,30 @@ int launch_transpose(const float2* in, float2* out, int frames, int rows, int co
   return CS_OK;
 }
 
+static size_t vertical_lds(const cs_plan* p, int cw) {
+  return (size_t)(p->desc.nv + kVWaves * cw * p->desc.nv) * sizeof(float2);
+}
+
+// one wave per column group: enough workgroups for every group, at most 65535
+static unsigned vertical_grid(const cs_plan* p, int cw) {
+  const size_t units = (size_t)p->desc.nt * ceil_div(p->desc.nh, cw);
+  return (unsigned)std::min<size_t>((units + kVWaves - 1) / kVWaves, 65535);
+}
+
 int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipStream_t s) {
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
   if (p->m_max > 0) {
+    if (!x_colmajor) {
+      int st = launch_transpose(x, p->img_tmp, nt, nv, nh, s);
+      if (st != CS_OK) return st;
+      x = p->img_tmp;
+    }
     const int cw = fft_cols_per_group(p);
-    const size_t lds1 = (size_t)(nv + cw * (nv + 1)) * sizeof(float2);
-    dim3 g1(ceil_div(nh, cw), nt, nc);
     const float sv = 1.0f / std::sqrt((float)nv), sh = 1.0f / std::sqrt((float)nh);
-    if (x_colmajor)
-      hipLaunchKernelGGL(k_fwd_vertical<true>, g1, dim3(kFftThreads), lds1, s, x, p->coil_cm, p->ftmp,
-                         p->rows, p->mcnt, p->fft_v, p->tw_v, nv, nh, nc, p->m_max, cw, sv);
-    else
-      hipLaunchKernelGGL(k_fwd_vertical<false>, g1, dim3(kFftThreads), lds1, s, x, p->coil_cm, p->ftmp,
-                         p->rows, p->mcnt, p->fft_v, p->tw_v, nv, nh, nc, p->m_max, cw, sv);
+    auto k = cw * nv <= 256 ? k_fwd_vertical<kFwdStore, 256> : k_fwd_vertical<kFwdStore, 512>;
+    hipLaunchKernelGGL(k, dim3(vertical_grid(p, cw)), dim3(64 * kVWaves), vertical_lds(p, cw), s, x, p->coil_cm,
+                       p->ftmp, nullptr, p->rows, p->mcnt, p->fft_v, p->tw_v, nv, nh, nt, nc, p->m_max, cw, sv,
+                       nullptr);
     CS_HIP(hipGetLastError());
     if (y) {
       const int rb = fft_rows_per_group(p);
@@ -271,6 +346,17 @@ int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipS
     hipLaunchKernelGGL(k_zero_unsampled, dim3(nv, nt, nc), dim3(128), 0, s, y, p->mask, nv, nh, nc);
     CS_HIP(hipGetLastError());
   }
+  return CS_OK;
+}
+
+int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nblocks, hipStream_t s) {
+  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
+  const int cw = fft_cols_per_group(p);
+  auto k = cw * nv <= 256 ? k_fwd_vertical<kFwdResidual, 256> : k_fwd_vertical<kFwdResidual, 512>;
+  hipLaunchKernelGGL(k, dim3(nblocks), dim3(64 * kVWaves), vertical_lds(p, cw), s, x, p->coil_cm, nullptr,
+                     p->ktmp, p->rows, p->mcnt, p->fft_v, p->tw_v, nv, nh, nt, nc, p->m_max, cw,
+                     1.0f / std::sqrt((float)nv), part);
+  CS_HIP(hipGetLastError());
   return CS_OK;
 }
 
@@ -289,16 +375,13 @@ int launch_adjoint_rows(cs_plan* p, const float2* y, hipStream_t s) {
 int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s) {
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
   const int cw = fft_cols_per_group(p);
-  const size_t lds = (size_t)(nv + cw * (nv + 1)) * sizeof(float2);
-  dim3 g(ceil_div(nh, cw), nt);
-  const float sv = 1.0f / std::sqrt((float)nv);
-  if (x_colmajor)
-    hipLaunchKernelGGL(k_adj_vertical<true>, g, dim3(kFftThreads), lds, s, p->ktmp, p->coil_cm, x, p->rows,
-                       p->mcnt, p->fft_v, p->tw_v, nv, nh, nc, p->m_max, cw, sv);
-  else
-    hipLaunchKernelGGL(k_adj_vertical<false>, g, dim3(kFftThreads), lds, s, p->ktmp, p->coil_cm, x, p->rows,
-                       p->mcnt, p->fft_v, p->tw_v, nv, nh, nc, p->m_max, cw, sv);
+  float2* xo = x_colmajor ? x : p->img_tmp;
+  auto k = cw * nv <= 256 ? k_adj_vertical<256> : k_adj_vertical<512>;
+  hipLaunchKernelGGL(k, dim3(vertical_grid(p, cw)), dim3(64 * kVWaves), vertical_lds(p, cw), s, p->ktmp,
+                     p->coil_cm, xo, p->rows, p->mcnt, p->fft_v, p->tw_v, nv, nh, nt, nc, p->m_max, cw,
+                     1.0f / std::sqrt((float)nv));
   CS_HIP(hipGetLastError());
+  if (!x_colmajor) return launch_transpose(p->img_tmp, x, nt, nh, nv, s);
   return CS_OK;
 }
 

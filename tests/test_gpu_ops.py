@@ -105,9 +105,10 @@ def test_block_inverse_in_place_alias():
 
 @pytest.mark.parametrize("shape", [(256, 64, 6, 3), (192, 48, 5, 2), (27, 18, 4, 2), (96, 24, 3, 4)], ids=str)
 def test_fft_tiles_do_not_change_results(shape):
-    """Every FFT tile choice (columns per vertical workgroup, rows per
-    horizontal one) computes each column's and row's transform with the same
-    arithmetic: A, A' and a solve are bit-identical to the largest tiles."""
+    """Every FFT tile choice (columns per wave of the vertical passes, rows
+    per workgroup of the horizontal ones) computes each column's and row's
+    transform with the same arithmetic: A, A' and a solve are bit-identical to
+    the default tiles.  Column groups are clipped to 512 values."""
     from paper_1203_4587_amd.api import Plan
     nv, nh, nt, nc = shape
     case = make_case(nv, nh, nt, nc, accel=3, ncenter=2, prior="tv", seed=nv + nh)
@@ -116,10 +117,13 @@ def test_fft_tiles_do_not_change_results(shape):
     cw0, rb0 = base.fft_tiles
     x = torch.from_numpy(case.x_true.astype(np.complex64)).cuda()
     ya, xa, xs = base.apply_A(x), base.apply_AH(y), base.solve(y, 0.02, 6)
-    for cw, rb in [(1, 1), (max(1, cw0 // 2), rb0), (max(1, cw0 // 4), max(1, rb0 // 2)), (cw0 * 4, rb0 * 4)]:
+    assert cw0 == max(1, min(nh, 256 // nv))
+    climit = max(1, min(nh, 512 // nv))
+    for cw, rb in [(1, 1), (max(1, cw0 // 2), rb0), (max(1, cw0 // 4), max(1, rb0 // 2)), (climit, rb0),
+                   (cw0 * 4, rb0 * 4)]:
         p = Plan(coil, mask, 0.1, prior="tv")
         p.fft_tiles = (cw, rb)
-        assert p.fft_tiles == (min(cw, cw0), min(rb, rb0))
+        assert p.fft_tiles == (min(cw, climit), min(rb, rb0))
         assert torch.equal(p.apply_A(x), ya), (cw, rb)
         assert torch.equal(p.apply_AH(y), xa), (cw, rb)
         assert torch.equal(p.solve(y, 0.02, 6), xs), (cw, rb)
