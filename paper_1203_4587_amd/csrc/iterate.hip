@@ -1251,30 +1251,65 @@ __global__ __launch_bounds__(kJThreads) void k_l1_tv_partial(const float2* __res
   block_reduce_store(acc, part + blockIdx.x);
 }
 
-template <int NT>
-__global__ __launch_bounds__(kJThreads) void k_l1_dft_partial(const float2* __restrict__ x,
-                                                              const float2* __restrict__ psi, int nt, size_t npix,
-                                                              double* __restrict__ part) {
-  __shared__ float2 ps[NT * NT];
-  for (int q = threadIdx.x; q < nt * nt; q += blockDim.x) ps[q] = psi[q];
+// l1 of Psi x for the temporal-DFT prior: the same MFMA contraction as the
+// DFT step (16 pixels per wave), then sum |w| over this lane's frequencies in
+// FP64; a fixed grid with a grid-stride loop keeps the partials reproducible
+template <int KP>
+__global__ __launch_bounds__(256) void k_l1_dft_tiles(const float* __restrict__ frags, const float2* __restrict__ x,
+                                                      int nt, size_t npix, double* __restrict__ part) {
+  constexpr int MT = DftTile<KP>::MT;
+  extern __shared__ float lds_f[];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, grp = lane >> 4;
+  float* tile = lds_f + DftTile<KP>::FRAG + wv * KP * 16;
+  load_frags<KP>(lds_f, frags);
   __syncthreads();
+  const int nw = blockDim.x >> 6;
+  const size_t ntiles = (npix + 15) / 16;
   double acc = 0.0;
-  for (size_t p = (size_t)blockIdx.x * kJThreads + threadIdx.x; p < npix; p += (size_t)kJBlocks * kJThreads) {
-    float2 a[NT];
+  for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
+    const size_t p0 = tl * 16;
+    const int count = (int)std::min<size_t>(16, npix - p0);
+    mfma_v4 w[MT];
+    tile_stage<KP>(tile, x, nt, npix, p0, count, lane);
+    tile_gemm<KP, false>(lds_f, tile, lane, w);
+    __builtin_amdgcn_wave_barrier();  // the next tile overwrites this wave's staging rows
 #pragma unroll
-    for (int t = 0; t < NT; ++t) a[t] = t < nt ? x[(size_t)t * npix + p] : make_float2(0.f, 0.f);
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-    for (int f = 0; f < NT; ++f) {
-      if (f < nt) {
-        float2 w = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (t < nt) w = cfma(ps[f * nt + t], a[t], w);
-        acc += sqrt((double)w.x * w.x + (double)w.y * w.y);
+      for (int h = 0; h < 2; ++h) {
+        const int f = 8 * m + 2 * grp + h;
+        if (f < nt && col < count) {
+          const double a = w[m][2 * h], b = w[m][2 * h + 1];
+          acc += sqrt(a * a + b * b);
+        }
       }
-    }
   }
-  block_reduce_store(acc, part + blockIdx.x);
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int k = (int)blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+template <int KP>
+static int l1_dft_launch(cs_plan* p, const float2* x, double* part, hipStream_t s) {
+  const size_t npix = (size_t)p->desc.nv * p->desc.nh;
+  const int waves = dft_waves(KP);
+  const size_t lds = dft_lds_bytes(KP, waves);
+  static bool attr = false;
+  if (lds > 65536 && !attr) {
+    CS_HIP(hipFuncSetAttribute((const void*)k_l1_dft_tiles<KP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_l1_dft_tiles<KP>, dim3(kJBlocks), dim3(64 * waves), lds, s, p->dft_frags, x, p->desc.nt, npix,
+                     part);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
 }
 
 __global__ void k_j_final(const double* __restrict__ part, float lambda, float* __restrict__ out) {
@@ -1288,13 +1323,6 @@ __global__ void k_j_final(const double* __restrict__ part, float lambda, float* 
   if (threadIdx.x == 0) *out = (float)((double)lambda * r[1] + r[0]);
 }
 
-template <int NT>
-static void l1_dft_launch(cs_plan* p, const float2* x, hipStream_t s) {
-  const size_t npix = (size_t)p->desc.nv * p->desc.nh;
-  hipLaunchKernelGGL(k_l1_dft_partial<NT>, dim3(kJBlocks), dim3(kJThreads), 0, s, x, p->psi_t, p->desc.nt,
-                     npix, p->jpart + kJBlocks);
-}
-
 // x in solver layout; the plan's ktmp must hold F_h' y (set by the solve setup)
 int launch_objective(cs_plan* p, const float2* x, float lambda, float* out, hipStream_t s) {
   const int nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
@@ -1305,7 +1333,17 @@ int launch_objective(cs_plan* p, const float2* x, float lambda, float* out, hipS
     hipLaunchKernelGGL(k_l1_tv_partial, dim3(kJBlocks), dim3(kJThreads), 0, s, x, nt, npix,
                        p->jpart + kJBlocks);
   } else {
-    CS_DISPATCH_NT(nt, l1_dft_launch, p, x, s);
+    switch (dft_kp(nt)) {
+      case 16: st = l1_dft_launch<16>(p, x, p->jpart + kJBlocks, s); break;
+      case 32: st = l1_dft_launch<32>(p, x, p->jpart + kJBlocks, s); break;
+      case 48: st = l1_dft_launch<48>(p, x, p->jpart + kJBlocks, s); break;
+      case 64: st = l1_dft_launch<64>(p, x, p->jpart + kJBlocks, s); break;
+      case 80: st = l1_dft_launch<80>(p, x, p->jpart + kJBlocks, s); break;
+      case 96: st = l1_dft_launch<96>(p, x, p->jpart + kJBlocks, s); break;
+      case 112: st = l1_dft_launch<112>(p, x, p->jpart + kJBlocks, s); break;
+      default: st = l1_dft_launch<128>(p, x, p->jpart + kJBlocks, s); break;
+    }
+    if (st != CS_OK) return st;
   }
   hipLaunchKernelGGL(k_j_final, dim3(1), dim3(64), 0, s, p->jpart, lambda, out);
   CS_HIP(hipGetLastError());
