@@ -1312,15 +1312,30 @@ static int l1_dft_launch(cs_plan* p, const float2* x, double* part, hipStream_t 
   return CS_OK;
 }
 
-__global__ void k_j_final(const double* __restrict__ part, float lambda, float* __restrict__ out) {
-  __shared__ double r[2];
-  if (threadIdx.x < 2) {
-    double acc = 0.0;
-    for (int q = 0; q < kJBlocks; ++q) acc += part[threadIdx.x * kJBlocks + q];
-    r[threadIdx.x] = acc;
+// J = lambda * l1 + data from the two halves of the partials: each of the
+// kJThreads threads sums a fixed run of each half, then a fixed tree; the
+// order never changes, so J is reproducible
+__global__ __launch_bounds__(kJThreads) void k_j_final(const double* __restrict__ part, float lambda,
+                                                       float* __restrict__ out) {
+  constexpr int kRun = kJBlocks / kJThreads;
+  static_assert(kJBlocks % kJThreads == 0, "partials split evenly over the threads");
+  __shared__ double r0[kJThreads], r1[kJThreads];
+  double a = 0.0, b = 0.0;
+  for (int q = 0; q < kRun; ++q) {
+    a += part[threadIdx.x * kRun + q];
+    b += part[kJBlocks + threadIdx.x * kRun + q];
   }
+  r0[threadIdx.x] = a;
+  r1[threadIdx.x] = b;
   __syncthreads();
-  if (threadIdx.x == 0) *out = (float)((double)lambda * r[1] + r[0]);
+  for (int w = kJThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      r0[threadIdx.x] += r0[threadIdx.x + w];
+      r1[threadIdx.x] += r1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = (float)((double)lambda * r1[0] + r0[0]);
 }
 
 // x in solver layout; the plan's ktmp must hold F_h' y (set by the solve setup)
@@ -1345,7 +1360,7 @@ int launch_objective(cs_plan* p, const float2* x, float lambda, float* out, hipS
     }
     if (st != CS_OK) return st;
   }
-  hipLaunchKernelGGL(k_j_final, dim3(1), dim3(64), 0, s, p->jpart, lambda, out);
+  hipLaunchKernelGGL(k_j_final, dim3(1), dim3(kJThreads), 0, s, p->jpart, lambda, out);
   CS_HIP(hipGetLastError());
   return CS_OK;
 }

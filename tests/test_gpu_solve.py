@@ -103,10 +103,14 @@ def test_zero_iterations_return_initialisation(prior):
     assert rel_l2(x.cpu().numpy(), O.adjoint(case.y, case.coil, case.mask)) < 1e-5
 
 
-@pytest.mark.parametrize("prior", ["tv", "dft"])
-def test_objective_trace_matches_oracle(prior):
+@pytest.mark.parametrize("prior,shape", [("tv", (48, 32, 8, 3)), ("dft", (48, 32, 8, 3)),
+                                         ("dft", (27, 12, 40, 2)),   # 324 pixels: ragged last tile, KP = 80
+                                         ("dft", (16, 6, 64, 2)),    # maximum frame count, KP = 128
+                                         ("tv", (27, 12, 40, 2))], ids=str)
+def test_objective_trace_matches_oracle(prior, shape):
     fam = "cardiac" if prior == "tv" else "periodic"
-    case = make_case(48, 32, 8, 3, accel=3, ncenter=4, prior=prior, family=fam, seed=11)
+    nv, nh, nt, nc = shape
+    case = make_case(nv, nh, nt, nc, accel=3, ncenter=4, prior=prior, family=fam, seed=11)
     lam, mu, rho, iters = 0.02, 0.1, 0.5, 12
     _, _, (x, J) = _run(case, prior, lam, mu, rho, iters, trace=True)
     Jref = []
