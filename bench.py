@@ -219,6 +219,28 @@ def unrolled_throughput(reps: int) -> dict:
     return res
 
 
+def stream_context() -> dict:
+    """Rate of a plain torch device-to-device copy of 1 GiB (bytes read +
+    written), timed with torch events in the same run (mean of 5 after a
+    warm-up): context for the roofline fraction, which stays against the
+    published peak."""
+    import torch
+    a = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy = 2 * a.numel() * 4 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"device_copy_GBps": round(copy, 1)}
+
+
 def step_rows(plan, problem, y, t_plan: float, prior: str) -> dict:
     """Per-step figures beside the iteration: the SENSE forward and adjoint
     passes (torch events on the stream they run on, mean of 20 calls), the
@@ -465,6 +487,7 @@ def main() -> int:
             "event_timed_iter_per_s": round(args.steps / elapsed_events, 2),
         },
     }
+    line["roofline"].update(stream_context())
     if not args.no_rows:
         line["rows"] = step_rows(plan, problem, y, t_plan, wl["prior"])
     # the paper's stopping rule: iterate until Delta(k) < 1e-3 (checked every 5
