@@ -208,6 +208,19 @@ def unrolled_throughput(reps: int) -> dict:
             ts.append(time.perf_counter() - t)
         res[f"{name}_per_s"] = round(1.0 / _median(ts), 2)
         res[f"{name}_ms"] = round(1e3 * _median(ts), 3)
+    # the same K with one segment: the forward keeps the whole tape and the
+    # backward recomputes nothing (3 images per iteration of extra memory)
+    un.close()
+    un = Unrolled(plan, pr.iters, pr.iters)
+    fb()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        fb()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    res["forward_backward_full_tape_ms"] = round(1e3 * _median(ts), 3)
     nt, nv, nh = pr.x_true.shape
     res.update({
         "workload": "tv-192x192x24-12c R8, K=20 unrolled, checkpoint every 5",

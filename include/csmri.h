@@ -251,12 +251,15 @@ int cs_batch_solve(cs_batch* batch, const cs_c64* const* y, const float* lambda,
  * and dL/dmu (mu = mu_2; rho = mu_ratio is held fixed).  Complex gradients use
  * the convention g = dL/dRe z + i dL/dIm z (that of torch.autograd).
  *
- * The forward keeps the solver state every `ckpt_every` iterations; the
- * backward recomputes one segment at a time from its checkpoint and sweeps the
- * transposed Jacobian of each line of the algorithm in reverse (the x-update
- * kernel applies the Hermitian (mu I + H'H)^{-1}; one per-pixel kernel does
- * the transposed temporal step, soft threshold and dual updates).  Memory:
- * about 4 images per checkpoint plus 3 per iteration of a segment plus 7.
+ * The forward keeps the solver state every `ckpt_every` iterations, and the
+ * per-iteration values the adjoint needs (the tape) of its last segment; the
+ * backward sweeps the segments last first, recomputing each one's tape from
+ * its checkpoint except the one the forward kept (so ckpt_every >= iters
+ * recomputes nothing), and applies the transposed Jacobian of each line of the
+ * algorithm in reverse (the x-update kernel applies the Hermitian
+ * (mu I + H'H)^{-1}; one per-pixel kernel does the transposed temporal step,
+ * soft threshold and dual updates).  Memory: about 4 images per checkpoint
+ * plus 3 per iteration of a segment plus 7.
  * dL/dy = A(dL/dH'y) is zero on rows the mask does not sample.  Where some
  * |D m + d1| equals tau exactly the map is not differentiable; the derivative
  * of the inactive side is returned. */

@@ -185,6 +185,7 @@ struct cs_grad {
   float2* hy = nullptr;
   std::vector<float2*> ck;          // [nseg][4]: m, d1, x, d2 at the start of each segment
   std::vector<float2*> tm, td1, td2;  // [every + 1]: m_j, d1_j (before step j+1), d2_j
+  int taped_seg = -1;                 // segment whose tape the forward left in tm/td1/td2, or -1
   float2 *mb = nullptr, *d1b = nullptr, *d2b = nullptr, *e = nullptr, *bb = nullptr, *hyb = nullptr;
   double* partial = nullptr;
   int nslots = 0;
@@ -303,10 +304,24 @@ int cs_admm_forward_ckpt(cs_grad* g, const cs_c64* y, float lambda, float mu, cs
   CK(launch_fill(p->s1, n, zero, s));
   CK(launch_fill(p->s3, n, zero, s));
   float2* state[4] = {p->s0, p->s1, p->s2, p->s3};
+  g->taped_seg = -1;
   for (int seg = 0; seg < g->nseg && st == CS_OK; ++seg) {
     for (int a = 0; a < 4; ++a) CK(launch_copy(state[a], g->ck[(size_t)seg * 4 + a], n, s));
     const int L = std::min(g->every, g->iters - seg * g->every);
-    CK(run_iterations(p, L, lambda, mu, nullptr, nullptr, s));
+    if (seg + 1 < g->nseg) {
+      CK(run_iterations(p, L, lambda, mu, nullptr, nullptr, s));
+    } else {
+      // the last segment is the first one the backward sweeps: keep its tape
+      // now, so that the backward need not recompute it (with ckpt_every >= K
+      // nothing is recomputed at all)
+      for (int j = 0; j < L; ++j) {
+        CK(launch_copy(p->s0, g->tm[j], n, s));
+        CK(launch_copy(p->s1, g->td1[j], n, s));
+        CK(one_iteration(p, lambda, mu, s));
+        CK(launch_copy(p->s3, g->td2[j + 1], n, s));
+      }
+      if (st == CS_OK) g->taped_seg = seg;
+    }
   }
   CK(launch_transpose(p->s2, reinterpret_cast<float2*>(x_out), nt, nh, nv, s));
 #undef CK
@@ -345,13 +360,16 @@ int cs_admm_backward(cs_grad* g, const cs_c64* grad_x, cs_c64* grad_y, float* gr
   const unsigned blocks = (unsigned)g->nslots;
   for (int seg = g->nseg - 1; seg >= 0 && st == CS_OK; --seg) {
     const int L = std::min(g->every, g->iters - seg * g->every);
-    for (int a = 0; a < 4; ++a) CK(launch_copy(g->ck[(size_t)seg * 4 + a], state[a], n, s));
-    for (int j = 0; j < L; ++j) {  // recompute the segment, keeping what the adjoint needs
-      CK(launch_copy(p->s0, g->tm[j], n, s));
-      CK(launch_copy(p->s1, g->td1[j], n, s));
-      CK(one_iteration(p, lambda, mu, s));
-      CK(launch_copy(p->s3, g->td2[j + 1], n, s));
+    if (seg != g->taped_seg) {
+      for (int a = 0; a < 4; ++a) CK(launch_copy(g->ck[(size_t)seg * 4 + a], state[a], n, s));
+      for (int j = 0; j < L; ++j) {  // recompute the segment, keeping what the adjoint needs
+        CK(launch_copy(p->s0, g->tm[j], n, s));
+        CK(launch_copy(p->s1, g->td1[j], n, s));
+        CK(one_iteration(p, lambda, mu, s));
+        CK(launch_copy(p->s3, g->td2[j + 1], n, s));
+      }
     }
+    g->taped_seg = -1;  // the tape now holds (or will hold) another segment
     for (int j = L - 1; j >= 0 && st == CS_OK; --j) {
       CK(launch_block_solve(p, kSolvePlain, g->e, nullptr, nullptr, g->bb, mu, s));  // bb = W e
       if (st != CS_OK) break;

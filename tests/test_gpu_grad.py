@@ -75,6 +75,23 @@ def test_gradient_matches_oracle_reference(shape, iters, every):
     assert torch.equal(gy, gy2) and torch.equal(gs, gs2)
 
 
+def test_checkpoint_schedule_does_not_change_gradients():
+    """Every checkpoint interval runs the same kernels in the same order: the
+    gradients for ckpt_every = 1, 4 and K (the forward keeps the whole tape,
+    nothing is recomputed) are bit-identical."""
+    case = make_case(48, 32, 8, 3, accel=3, ncenter=2, prior="tv", seed=77, sigma=0.01)
+    rng = np.random.default_rng(5)
+    g = torch.from_numpy(_rand_c(rng, case.x_true.shape).astype(np.complex64)).cuda()
+    out = []
+    for every in (1, 4, 9):
+        plan, un, y = _setup(case, 9, every)
+        un.forward_raw(y, LAM, MU)
+        out.append(un.backward_raw(g))
+        un.close()
+    for gy, gs in out[1:]:
+        assert torch.equal(gy, out[0][0]) and torch.equal(gs, out[0][1])
+
+
 def test_gradient_matches_fp64_finite_differences():
     """The GPU gradient against central differences of the oracle's FP64
     forward map (y along a random sampled direction, lambda, mu)."""
