@@ -335,8 +335,9 @@ def main() -> int:
                          "launches per iteration")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs the reconstruction on one "
-              "GPU (columns are independent, see DESIGN.md for how the path would shard)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported; the benchmark runs the reconstruction on one "
+              "GPU (readout columns are independent ADMM problems, so more GPUs would each take a column range "
+              "or whole slices)", file=sys.stderr)
         return 2
 
     import numpy as np
