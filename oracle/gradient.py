@@ -1,4 +1,5 @@
-"""FP64 reference gradient of an unrolled Algorithm 2 (temporal TV).
+"""FP64 reference gradients of unrolled Algorithm 2 (temporal TV) and Algorithm 1
+(temporal DFT).
 
 TEST INFRASTRUCTURE ONLY, like ``reference.py``: imported only by the test
 suite, the smoke check and the benchmark's CPU-baseline leg, and sharing no
@@ -37,7 +38,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from .reference import BlockFactor, adjoint_columns, forward, soft, tdiff, tdiff_adj, tv_system_solve
+from .reference import (BlockFactor, adjoint_columns, forward, soft, tdft, tdft_adj, tdiff, tdiff_adj,
+                        tv_system_solve)
 
 
 def _rdot(u: np.ndarray, w: np.ndarray) -> float:
@@ -178,4 +180,116 @@ def unrolled_tv_loss(y, coil, mask, lam, mu, rho, iters, g, cols=None, fac=None)
         fac = BlockFactor(coil, mask, cols)
     Hy = adjoint_columns(y, coil, mask, cols)
     xK, _ = unrolled_tv_forward(Hy, fac, lam, mu, rho, iters)
+    return _rdot(g, xK)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1 (synthesis prior, Psi = unitary temporal DFT)
+# --------------------------------------------------------------------------
+#
+# K iterations of Algorithm 1 (Sec. IV-A) from its initialisation w = Psi H'y,
+# d = 0, with tau = lambda / (2 mu).  Psi is orthonormal, so the (1/mu)(I -
+# Psi Psi') term of the w-update vanishes and one iteration is
+#
+#     a  = w - d
+#     v  = soft(a, tau)
+#     u  = Psi'(v + d)
+#     b  = H'y + mu u
+#     z  = (mu I + H'H)^{-1} b
+#     w' = Psi z
+#     d' = d - (w' - v)
+#
+# with output x_K = Psi' w_K (= z_K for K > 0, H'y for K = 0).  The reverse
+# sweep follows the same conventions as the one above.
+
+
+def unrolled_dft_forward(Hy: np.ndarray, fac: BlockFactor, lam: float, mu: float, iters: int):
+    """Algorithm 1 for `iters` iterations, returning x_K and every iteration's
+    stored quantities (a, u, b, z)."""
+    tau = lam / (2.0 * mu)
+    w = tdft(Hy)
+    d = np.zeros_like(w)
+    tape = []
+    for _ in range(iters):
+        a = w - d
+        v = soft(a, tau)
+        u = tdft_adj(v + d)
+        b = Hy + mu * u
+        z = fac.solve(b, mu)
+        tape.append(dict(a=a, u=u, b=b, z=z))
+        wn = tdft(z)
+        d = d - (wn - v)
+        w = wn
+    return tdft_adj(w), tape
+
+
+def unrolled_dft_grad(Hy: np.ndarray, fac: BlockFactor, lam: float, mu: float, iters: int,
+                      gx: np.ndarray) -> dict:
+    """Reverse sweep of `iters` iterations of Algorithm 1 for gx = dL/dx_K.
+    Returns {"x": x_K, "Hy": dL/dH'y, "lam": dL/dlambda, "mu": dL/dmu}."""
+    tau = lam / (2.0 * mu)
+    xK, tape = unrolled_dft_forward(Hy, fac, lam, mu, iters)
+    # x_K = Psi' w_K: the adjoint of Psi' is Psi
+    gw = tdft(np.asarray(gx, dtype=np.complex128))
+    gd = np.zeros_like(gw)
+    gHy = np.zeros_like(Hy)
+    gtau = 0.0
+    gmu = 0.0
+    for st in reversed(tape):
+        # d' = d - w' + v
+        n_gd = gd.copy()
+        g_wn = gw - gd
+        g_v = gd.copy()
+        # w' = Psi z
+        g_z = tdft_adj(g_wn)
+        # z = (mu I + H'H)^{-1} b: the inverse is Hermitian; d/dmu = -(.)^{-2}
+        g_b = fac.solve(g_z, mu)
+        gmu += _rdot(g_z, -fac.solve(fac.solve(st["b"], mu), mu))
+        # b = H'y + mu u
+        gHy += g_b
+        g_u = mu * g_b
+        gmu += _rdot(g_b, st["u"])
+        # u = Psi'(v + d)
+        s = tdft(g_u)
+        g_v = g_v + s
+        n_gd = n_gd + s
+        # v = soft(a, tau)
+        g_a, gt = soft_vjp(st["a"], tau, g_v)
+        gtau += gt
+        # a = w - d
+        gw = g_a
+        gd = n_gd - g_a
+    # initialisation w_0 = Psi H'y (d_0 = 0 is a constant)
+    gHy += tdft_adj(gw)
+    # tau = lambda / (2 mu)
+    glam = gtau / (2.0 * mu)
+    gmu += gtau * (-lam / (2.0 * mu * mu))
+    return {"x": xK, "Hy": gHy, "lam": glam, "mu": gmu}
+
+
+def unrolled_dft_grad_y(y, coil, mask, lam, mu, iters, gx, cols=None, fac=None) -> dict:
+    """dL/dy, dL/dlambda, dL/dmu of L(x_K) for K = iters unrolled iterations of
+    Algorithm 1 on data y, given gx = dL/dx_K (column restriction as for
+    unrolled_tv_grad_y)."""
+    nt, nv = mask.shape
+    nh = coil.shape[2]
+    cols = np.arange(nh) if cols is None else np.asarray(cols)
+    if fac is None:
+        fac = BlockFactor(coil, mask, cols)
+    Hy = adjoint_columns(y, coil, mask, cols)
+    res = unrolled_dft_grad(Hy, fac, lam, mu, iters, gx)
+    gHy = np.zeros((nt, nv, nh), dtype=np.complex128)
+    gHy[:, :, cols] = res["Hy"]
+    return {"x": res["x"], "y": forward(gHy, coil, mask), "lam": res["lam"], "mu": res["mu"],
+            "Hy": res["Hy"]}
+
+
+def unrolled_dft_loss(y, coil, mask, lam, mu, iters, g, cols=None, fac=None) -> float:
+    """L = Re <g, x_K> for the unrolled Algorithm 1 map (finite-difference pins)."""
+    nh = coil.shape[2]
+    cols = np.arange(nh) if cols is None else np.asarray(cols)
+    if fac is None:
+        fac = BlockFactor(coil, mask, cols)
+    Hy = adjoint_columns(y, coil, mask, cols)
+    xK, _ = unrolled_dft_forward(Hy, fac, lam, mu, iters)
     return _rdot(g, xK)
