@@ -246,10 +246,11 @@ int cs_batch_solve(cs_batch* batch, const cs_c64* const* y, const float* lambda,
 
 /* ---------------------------------------------------------------- gradients
  * Reverse-mode derivative of K unrolled iterations of Algorithm 2 (temporal TV
- * prior, Sec. IV-B) from its initialisation, for training or tuning through
- * the reconstruction: given dL/dx_K of a real loss L, returns dL/dy, dL/dlambda
- * and dL/dmu (mu = mu_2; rho = mu_ratio is held fixed).  Complex gradients use
- * the convention g = dL/dRe z + i dL/dIm z (that of torch.autograd).
+ * prior, Sec. IV-B) or Algorithm 1 (temporal DFT prior, Sec. IV-A) from its
+ * initialisation, for training or tuning through the reconstruction: given
+ * dL/dx_K of a real loss L, returns dL/dy, dL/dlambda and dL/dmu (for TV
+ * mu = mu_2 and rho = mu_ratio is held fixed).  Complex gradients use the
+ * convention g = dL/dRe z + i dL/dIm z (that of torch.autograd).
  *
  * The forward keeps the solver state every `ckpt_every` iterations, and the
  * per-iteration values the adjoint needs (the tape) of its last segment; the
@@ -257,17 +258,18 @@ int cs_batch_solve(cs_batch* batch, const cs_c64* const* y, const float* lambda,
  * its checkpoint except the one the forward kept (so ckpt_every >= iters
  * recomputes nothing), and applies the transposed Jacobian of each line of the
  * algorithm in reverse (the x-update kernel applies the Hermitian
- * (mu I + H'H)^{-1}; one per-pixel kernel does the transposed temporal step,
- * soft threshold and dual updates).  Memory: about 4 images per checkpoint
- * plus 3 per iteration of a segment plus 7.
+ * (mu I + H'H)^{-1}; one per-pixel kernel does the transposed temporal step
+ * (for the DFT prior three contractions on the matrix cores), soft threshold
+ * and dual updates).  Memory: about 4 images per checkpoint plus 3 per
+ * iteration of a segment plus 7.
  * dL/dy = A(dL/dH'y) is zero on rows the mask does not sample.  Where some
  * |D m + d1| equals tau exactly the map is not differentiable; the derivative
  * of the inactive side is returned. */
 typedef struct cs_grad cs_grad;
 
-/* Workspace for `iters` unrolled iterations on `plan` (TV prior only, else
- * CS_EUNSUPPORTED), allocated through the plan's allocator; it must be
- * destroyed before the plan.  ckpt_every >= 1. */
+/* Workspace for `iters` unrolled iterations on `plan` (TV or DFT prior; the
+ * overcomplete frame prior returns CS_EUNSUPPORTED), allocated through the
+ * plan's allocator; it must be destroyed before the plan.  ckpt_every >= 1. */
 int cs_grad_create(cs_plan* plan, int32_t iters, int32_t ckpt_every, cs_grad** out);
 int cs_grad_destroy(cs_grad* grad);
 

@@ -6,7 +6,8 @@
     loss(x).backward()                # fills y.grad, lam.grad, mu.grad
 
 Forward and backward both run in libcsmri (cs_admm_forward_ckpt /
-cs_admm_backward): K iterations of Algorithm 2 with checkpoints every
+cs_admm_backward): K iterations of Algorithm 2 (plan prior "tv") or
+Algorithm 1 (prior "dft") with checkpoints every
 `ckpt_every` iterations, then the reverse sweep.  Complex gradients follow
 torch's convention (dL/dRe + i dL/dIm).  One Unrolled object holds the
 checkpoints of its latest forward: a backward must follow its own forward
@@ -24,11 +25,11 @@ from .api import Plan, _need, _ptr, _stream
 
 
 class Unrolled:
-    """Differentiable K-iteration temporal-TV reconstruction on a plan."""
+    """Differentiable K-iteration reconstruction (temporal TV or temporal DFT) on a plan."""
 
     def __init__(self, plan: Plan, iters: int, ckpt_every: int = 5):
-        if plan.prior != "tv":
-            raise ValueError("the unrolled derivative is implemented for the temporal TV prior")
+        if plan.prior not in ("tv", "dft"):
+            raise ValueError("the unrolled derivative is implemented for the temporal TV and DFT priors")
         self.plan = plan
         self.iters = int(iters)
         self.ckpt_every = int(ckpt_every)

@@ -217,6 +217,10 @@ static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, flo
 }
 
 
+int run_iterations_cont(cs_plan* p, int32_t iters, float lambda, float mu, bool cont, hipStream_t s) {
+  return run_phase_loop(p, iters, lambda, mu, nullptr, nullptr, s, cont);
+}
+
 // ---------------------------------------------------------------- solve pieces
 
 static int solve_check(cs_plan* p, float lambda, float mu, const cs_state* state) {

@@ -1,6 +1,8 @@
-// Reverse-mode differentiation of unrolled Algorithm 2 (temporal TV): the
-// checkpointed forward and the adjoint sweep behind cs_admm_forward_ckpt /
-// cs_admm_backward.
+// Reverse-mode differentiation of unrolled Algorithm 2 (temporal TV) and
+// Algorithm 1 (temporal DFT): the checkpointed forward and the adjoint sweep
+// behind cs_admm_forward_ckpt / cs_admm_backward.  The Algorithm 1 reverse
+// step is the x-update kernel applying W followed by k_dft_adjoint
+// (iterate.hip), which carries its derivation; what follows is Algorithm 2's.
 //
 // One iteration of Algorithm 2 (Sec. IV-B), with D = D_t (eq. TV),
 // T = rho I + D'D, W = (mu I + H'H)^{-1} (eq. eigen_mu), tau = lambda/(2 mu1):
@@ -184,7 +186,10 @@ struct cs_grad {
   std::vector<void*> owned;
   float2* hy = nullptr;
   std::vector<float2*> ck;          // [nseg][4]: m, d1, x, d2 at the start of each segment
-  std::vector<float2*> tm, td1, td2;  // [every + 1]: m_j, d1_j (before step j+1), d2_j
+  bool dft = false;                   // Algorithm 1 (temporal DFT) instead of Algorithm 2
+  // the tape of one segment.  TV: m_j, d1_j (before step j+1), d2_j.  DFT
+  // (same arrays): z_j (tm, j <= L), d_j completed by step j+1 (td1), u_{j+1} (td2)
+  std::vector<float2*> tm, td1, td2;  // [every + 1]
   int taped_seg = -1;                 // segment whose tape the forward left in tm/td1/td2, or -1
   float2 *mb = nullptr, *d1b = nullptr, *d2b = nullptr, *e = nullptr, *bb = nullptr, *hyb = nullptr;
   double* partial = nullptr;
@@ -210,10 +215,76 @@ static int one_iteration(cs_plan* p, float lambda, float mu, hipStream_t s) {
   return run_iterations(p, 1, lambda, mu, nullptr, nullptr, s);
 }
 
+// L iterations of Algorithm 1 on the plan's state (z = s2, d = s0, v = s1),
+// one at a time, keeping z before each and the completed d and u after it;
+// cont: the first of them continues the solve (completes the deferred d)
+static int dft_segment_tape(cs_grad* g, int L, float lambda, float mu, bool cont, hipStream_t s) {
+  cs_plan* p = g->plan;
+  const size_t n = g->nimg;
+  int st = CS_OK;
+  for (int j = 0; j < L && st == CS_OK; ++j) {
+    st = launch_copy(p->s2, g->tm[j], n, s);
+    if (st == CS_OK) st = run_iterations_cont(p, 1, lambda, mu, cont || j > 0, s);
+    if (st == CS_OK) st = launch_copy(p->s0, g->td1[j], n, s);
+    if (st == CS_OK) st = launch_copy(p->s3, g->td2[j], n, s);
+  }
+  if (st == CS_OK) st = launch_copy(p->s2, g->tm[L], n, s);
+  return st;
+}
+
 static int ensure_mu(cs_plan* p, float mu, hipStream_t s) {
   if (mu == p->mu) return CS_OK;
   if (p->desc.flags & CS_FLAG_NO_REFACTOR) return set_error(CS_EMU_MISMATCH, "mu differs from the plan's mu");
   return build_factor(p, mu, s);
+}
+
+// Algorithm 1: with x_K = Psi' w_K, the adjoints after the last iteration are
+// wb_K = Psi g, db_K = 0, so the adjoint reaching z_K is Psi'(wb_K - db_K) = g
+static int dft_backward(cs_grad* g, const cs_c64* grad_x, cs_c64* grad_y, float* grad_lambda_mu, hipStream_t s) {
+  cs_plan* p = g->plan;
+  const float lambda = g->lambda, mu = g->mu;
+  const float tau = lambda / (2.0f * mu);  // as the forward step computes it
+  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
+  const size_t n = g->nimg;
+  const float2 zero = make_float2(0.f, 0.f);
+  int st = CS_OK;
+#define CK(expr)                              \
+  do {                                        \
+    if (st == CS_OK) st = (expr);             \
+  } while (0)
+  float2* zb = g->e;   // adjoint reaching z (image)
+  float2* db = g->d1b; // adjoint of d (frequency)
+  CK(launch_transpose(reinterpret_cast<const float2*>(grad_x), zb, nt, nv, nh, s));
+  CK(launch_fill(db, n, zero, s));
+  CK(launch_fill(g->hyb, n, zero, s));
+  CK(launch_fill(reinterpret_cast<float2*>(g->partial), (size_t)g->nslots * 2, zero, s));
+  CK(launch_copy(g->hy, p->hy, n, s));  // the plan may have solved something else since
+  for (int seg = g->nseg - 1; seg >= 0 && st == CS_OK; --seg) {
+    const int L = std::min(g->every, g->iters - seg * g->every);
+    if (seg != g->taped_seg) {
+      CK(launch_copy(g->ck[(size_t)seg * 4 + 0], p->s2, n, s));
+      CK(launch_copy(g->ck[(size_t)seg * 4 + 1], p->s0, n, s));
+      CK(launch_copy(g->ck[(size_t)seg * 4 + 2], p->s1, n, s));
+      CK(dft_segment_tape(g, L, lambda, mu, seg > 0, s));
+    }
+    g->taped_seg = -1;  // the tape now holds (or will hold) another segment
+    for (int j = L - 1; j >= 0 && st == CS_OK; --j) {
+      CK(launch_block_solve(p, kSolvePlain, zb, nullptr, nullptr, g->bb, mu, s));  // bb = W zb
+      const int last = (seg == 0 && j == 0) ? 1 : 0;
+      CK(launch_dft_adjoint(p, (unsigned)g->nslots, g->bb, db, zb, g->hyb, g->tm[j], g->td1[j], g->td2[j],
+                            g->tm[j + 1], g->partial, tau, mu, last, s));
+    }
+  }
+  if (g->iters == 0) CK(launch_copy(zb, g->hyb, n, s));  // x_K = x_0 = H'y
+  if (st == CS_OK) {
+    hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(256), 0, s, g->partial, g->nslots, grad_lambda_mu,
+                       (double)lambda, (double)mu, 1.0);  // tau = lambda / (2 mu)
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) st = hip_fail(e, "k_grad_finish");
+  }
+  CK(launch_forward(p, g->hyb, true, reinterpret_cast<float2*>(grad_y), s));  // dL/dy = A(dL/dH'y)
+#undef CK
+  return st;
 }
 
 extern "C" {
@@ -222,13 +293,14 @@ int cs_grad_create(cs_plan* p, int32_t iters, int32_t every, cs_grad** out) {
   if (!out) return set_error(CS_EINVAL, "out is NULL");
   *out = nullptr;
   if (!p) return set_error(CS_EINVAL, "plan is NULL");
-  if (p->desc.prior != CS_PRIOR_TEMPORAL_TV)
-    return set_error(CS_EUNSUPPORTED, "differentiation is implemented for the temporal TV prior");
+  if (p->desc.prior == CS_PRIOR_TEMPORAL_FRAME)
+    return set_error(CS_EUNSUPPORTED, "differentiation is implemented for the temporal TV and DFT priors");
   if (iters < 0) return set_error(CS_EINVAL, "iters must be >= 0");
   if (every < 1) return set_error(CS_EINVAL, "ckpt_every must be >= 1");
   cs_grad* g = new (std::nothrow) cs_grad();
   if (!g) return set_error(CS_ENOMEM, "host allocation failed");
   g->plan = p;
+  g->dft = p->desc.prior == CS_PRIOR_TEMPORAL_DFT;
   g->iters = iters;
   g->every = std::min(every, std::max(iters, 1));
   g->nseg = (iters + g->every - 1) / g->every;
@@ -247,11 +319,9 @@ int cs_grad_create(cs_plan* p, int32_t iters, int32_t every, cs_grad** out) {
   g->td1.assign(g->every + 1, nullptr);
   g->td2.assign(g->every + 1, nullptr);
   for (int j = 0; j <= g->every; ++j) {
-    if (j < g->every) {
-      A(&g->tm[j]);
-      A(&g->td1[j]);
-    }
-    if (j > 0) A(&g->td2[j]);
+    if (j < g->every || g->dft) A(&g->tm[j]);
+    if (j < g->every) A(&g->td1[j]);
+    if (j > 0 || g->dft) A(&g->td2[j]);
   }
   A(&g->mb);
   A(&g->d1b);
@@ -299,6 +369,31 @@ int cs_admm_forward_ckpt(cs_grad* g, const cs_c64* y, float lambda, float mu, cs
   CK(launch_adjoint_rows(p, reinterpret_cast<const float2*>(y), s));
   CK(launch_adjoint_image(p, p->hy, true, s));
   CK(launch_copy(p->hy, g->hy, n, s));
+  if (g->dft) {
+    // Algorithm 1's initial state as cs_admm_solve sets it: z = Psi' w_0 = H'y, d = v = 0
+    CK(launch_copy(p->hy, p->s2, n, s));
+    CK(launch_fill(p->s0, n, zero, s));
+    CK(launch_fill(p->s1, n, zero, s));
+    g->taped_seg = -1;
+    for (int seg = 0; seg < g->nseg && st == CS_OK; ++seg) {
+      CK(launch_copy(p->s2, g->ck[(size_t)seg * 4 + 0], n, s));
+      CK(launch_copy(p->s0, g->ck[(size_t)seg * 4 + 1], n, s));
+      CK(launch_copy(p->s1, g->ck[(size_t)seg * 4 + 2], n, s));
+      const int L = std::min(g->every, g->iters - seg * g->every);
+      if (seg + 1 < g->nseg) {
+        CK(run_iterations_cont(p, L, lambda, mu, seg > 0, s));
+      } else {
+        CK(dft_segment_tape(g, L, lambda, mu, seg > 0, s));
+        if (st == CS_OK) g->taped_seg = seg;
+      }
+    }
+    CK(launch_transpose(p->s2, reinterpret_cast<float2*>(x_out), nt, nh, nv, s));
+    if (st != CS_OK) return st;
+    g->lambda = lambda;
+    g->mu = mu;
+    g->ready = true;
+    return CS_OK;
+  }
   CK(launch_copy(p->hy, p->s0, n, s));  // m = x
   CK(launch_copy(p->hy, p->s2, n, s));  // x = H'y
   CK(launch_fill(p->s1, n, zero, s));
@@ -342,6 +437,8 @@ int cs_admm_backward(cs_grad* g, const cs_c64* grad_x, cs_c64* grad_y, float* gr
   const float lambda = g->lambda, mu = g->mu, rho = p->desc.mu_ratio;
   const float tau = lambda * rho / (2.0f * mu);  // as the forward step computes it
   int st = ensure_mu(p, mu, s);
+  if (st != CS_OK) return st;
+  if (g->dft) return dft_backward(g, grad_x, grad_y, grad_lambda_mu, s);
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
   const size_t n = g->nimg;
   const float2 zero = make_float2(0.f, 0.f);

@@ -205,6 +205,13 @@ namespace csmri {
 
 // sense.hip
 int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipStream_t s);
+// reverse step of one Algorithm 1 iteration (temporal DFT prior): see iterate.hip
+int launch_dft_adjoint(cs_plan* p, unsigned nblocks, const float2* bb, float2* db, float2* zb, float2* hyb,
+                       const float2* zprev, const float2* dprev, const float2* u, const float2* z, double* partial,
+                       float tau, float mu, int last, hipStream_t s);
+// `iters` phase-form iterations without objective; cont: they continue a loop of
+// the same solve (the temporal DFT step completes the previous deferred update)
+int run_iterations_cont(cs_plan* p, int32_t iters, float lambda, float mu, bool cont, hipStream_t s);
 int launch_adjoint_rows(cs_plan* p, const float2* y, hipStream_t s);  // y -> p->ktmp
 // sum |M_t F_v (s_c . x) - ktmp|^2, one FP64 partial per workgroup of an nblocks grid (x column-major)
 int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nblocks, hipStream_t s);

@@ -1217,6 +1217,173 @@ int launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s) {
   return CS_OK;
 }
 
+// ---------------------------------------------------------------- Algorithm 1 reverse step
+//
+// Transposed Jacobian of one iteration of Algorithm 1 with Psi the unitary
+// temporal DFT (a = w - d, v = soft(a, tau), u = Psi'(v + d),
+// z = W (H'y + mu u), w' = Psi z, d' = d - (w' - v)), given
+//   bb = W zb   (zb = Psi'(wb' - db'), the adjoint reaching z; W Hermitian)
+// and the adjoint db' of d':
+//   s   = Psi (mu bb)                        adjoint of u, taken to (v, d)
+//   vb  = db' + s
+//   ab  = (dsoft/da)^T vb                    real 2x2 Jacobian on |a| > tau
+//   wb  = ab;  db = db' + s - ab
+//   zb  <- Psi'(wb - db)                     the next (earlier) step's zb
+//   dL/dH'y += bb;  dL/dtau += -sum Re(conj(a/|a|) vb);  dL/dmu += Re<bb, u - z>
+// For the first iteration (last = 1) the state before it is w_0 = Psi H'y,
+// d_0 = 0, so Psi' wb is added to dL/dH'y instead of forming zb.  a is formed
+// again from the stored z_{k-1} and d_{k-1} with the forward step's own
+// contraction and subtraction, so every |a| > tau decision is the forward's.
+// One wave per 16 pixels, three contractions on the fragments of Psihat; a
+// fixed grid with a grid-stride loop and one FP64 slot pair per workgroup.
+template <int KP>
+__global__ __launch_bounds__(256) void k_dft_adjoint(const float* __restrict__ frags, const float2* __restrict__ bb,
+                                                     float2* __restrict__ db, float2* __restrict__ zb,
+                                                     float2* __restrict__ hyb, const float2* __restrict__ zprev,
+                                                     const float2* __restrict__ dprev,
+                                                     const float2* __restrict__ u, const float2* __restrict__ z,
+                                                     double* __restrict__ partial, int nt, size_t npix, float tau,
+                                                     float mu, int last) {
+  constexpr int MT = DftTile<KP>::MT, NK = KP / 8;
+  extern __shared__ float lds_f[];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, grp = lane >> 4;
+  float* tile = lds_f + DftTile<KP>::FRAG + wv * KP * 16;
+  load_frags<KP>(lds_f, frags);
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  const size_t ntiles = (npix + 15) / 16;
+  double tsum = 0.0, msum = 0.0;
+  for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
+    const size_t p0 = tl * 16;
+    const int count = (int)std::min<size_t>(16, npix - p0);
+    const bool pv = col < count;
+    const size_t p = p0 + col;
+    // s = Psi (mu bb)
+    {
+      float2 r[NK];
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int t = grp + 4 * k;
+        r[k] = (t < nt && pv) ? cscale(bb[(size_t)t * npix + p], mu) : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int t = grp + 4 * k;
+        tile[(2 * t) * 16 + col] = r[k].x;
+        tile[(2 * t + 1) * 16 + col] = r[k].y;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    mfma_v4 S[MT], A[MT];
+    tile_gemm<KP, false>(lds_f, tile, lane, S);
+    __builtin_amdgcn_wave_barrier();
+    // w_{k-1} = Psi z_{k-1}, as the forward step formed it
+    tile_stage<KP>(tile, zprev, nt, npix, p0, count, lane);
+    tile_gemm<KP, false>(lds_f, tile, lane, A);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int f = 8 * m + 2 * grp + h;
+        const int row = 16 * m + 4 * grp + 2 * h;
+        float2 q = make_float2(0.f, 0.f);
+        if (f < nt && pv) {
+          const size_t o = (size_t)f * npix + p;
+          const float2 dk = db[o];
+          const float2 a = csub(make_float2(A[m][2 * h], A[m][2 * h + 1]), dprev[o]);
+          const float2 sv = make_float2(S[m][2 * h], S[m][2 * h + 1]);
+          const float2 vb = cadd(dk, sv);
+          float2 ab = make_float2(0.f, 0.f);
+          const float mag = sqrtf(fmaf(a.x, a.x, a.y * a.y));
+          if (mag > tau) {
+            const float sdot = fmaf(a.x, vb.x, a.y * vb.y) / mag;  // Re(conj(a/|a|) vb)
+            const float kk = tau / mag;
+            const float ks = kk * sdot / mag;
+            ab = make_float2(fmaf(1.f - kk, vb.x, ks * a.x), fmaf(1.f - kk, vb.y, ks * a.y));
+            tsum -= (double)sdot;
+          }
+          const float2 dn = csub(vb, ab);
+          db[o] = dn;
+          q = last ? ab : csub(ab, dn);
+        }
+        tile[row * 16 + col] = q.x;
+        tile[(row + 1) * 16 + col] = q.y;
+      }
+    __builtin_amdgcn_wave_barrier();
+    tile_gemm<KP, true>(lds_f, tile, lane, A);  // Psi'(wb - db), or Psi' wb for the first iteration
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = 8 * m + 2 * grp + h;
+        if (t < nt && pv) {
+          const size_t o = (size_t)t * npix + p;
+          const float2 r = make_float2(A[m][2 * h], A[m][2 * h + 1]);
+          const float2 b = bb[o], uu = u[o], zz = z[o];
+          msum += (double)b.x * ((double)uu.x - zz.x) + (double)b.y * ((double)uu.y - zz.y);
+          float2 hv = cadd(hyb[o], b);
+          if (last) hv = cadd(hv, r);
+          else zb[o] = r;
+          hyb[o] = hv;
+        }
+      }
+  }
+  __shared__ double red[2][256];
+  red[0][threadIdx.x] = tsum;
+  red[1][threadIdx.x] = msum;
+  __syncthreads();
+  for (int k = (int)blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + k];
+      red[1][threadIdx.x] += red[1][threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] += red[0][0];
+    partial[2 * blockIdx.x + 1] += red[1][0];
+  }
+}
+
+template <int KP>
+static int dft_adjoint_launch(cs_plan* p, unsigned nblocks, const float2* bb, float2* db, float2* zb, float2* hyb,
+                              const float2* zprev, const float2* dprev, const float2* u, const float2* z,
+                              double* partial, float tau, float mu, int last, hipStream_t s) {
+  const size_t npix = (size_t)p->desc.nv * p->desc.nh;
+  const int waves = dft_waves(KP);
+  const size_t lds = dft_lds_bytes(KP, waves);
+  static bool attr = false;
+  if (lds > 65536 && !attr) {
+    CS_HIP(hipFuncSetAttribute((const void*)k_dft_adjoint<KP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_dft_adjoint<KP>, dim3(nblocks), dim3(64 * waves), lds, s, p->dft_frags, bb, db, zb, hyb,
+                     zprev, dprev, u, z, partial, p->desc.nt, npix, tau, mu, last);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
+int launch_dft_adjoint(cs_plan* p, unsigned nblocks, const float2* bb, float2* db, float2* zb, float2* hyb,
+                       const float2* zprev, const float2* dprev, const float2* u, const float2* z, double* partial,
+                       float tau, float mu, int last, hipStream_t s) {
+  switch (dft_kp(p->desc.nt)) {
+    case 16: return dft_adjoint_launch<16>(p, nblocks, bb, db, zb, hyb, zprev, dprev, u, z, partial, tau, mu, last, s);
+    case 32: return dft_adjoint_launch<32>(p, nblocks, bb, db, zb, hyb, zprev, dprev, u, z, partial, tau, mu, last, s);
+    case 48: return dft_adjoint_launch<48>(p, nblocks, bb, db, zb, hyb, zprev, dprev, u, z, partial, tau, mu, last, s);
+    case 64: return dft_adjoint_launch<64>(p, nblocks, bb, db, zb, hyb, zprev, dprev, u, z, partial, tau, mu, last, s);
+    case 80: return dft_adjoint_launch<80>(p, nblocks, bb, db, zb, hyb, zprev, dprev, u, z, partial, tau, mu, last, s);
+    case 96: return dft_adjoint_launch<96>(p, nblocks, bb, db, zb, hyb, zprev, dprev, u, z, partial, tau, mu, last, s);
+    case 112:
+      return dft_adjoint_launch<112>(p, nblocks, bb, db, zb, hyb, zprev, dprev, u, z, partial, tau, mu, last, s);
+    default:
+      return dft_adjoint_launch<128>(p, nblocks, bb, db, zb, hyb, zprev, dprev, u, z, partial, tau, mu, last, s);
+  }
+}
+
 // ---------------------------------------------------------------- objective
 //
 // J = lambda * l1 + ||y - H x||^2 (eqs. L1an_pri / L1unconst), evaluated in

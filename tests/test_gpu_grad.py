@@ -166,9 +166,9 @@ def test_zero_iterations_and_errors():
     with pytest.raises(_lib.CsmriError, match="preceding"):
         fresh.backward_raw(g)
     coil, mask, _ = case.device()
-    dft = Plan(coil, mask, MU, prior="dft")
+    frame = Plan(coil, mask, MU, prior="frame")
     h = __import__("ctypes").c_void_p()
-    assert _lib.load().cs_grad_create(dft.handle, 4, 2, __import__("ctypes").byref(h)) == _lib.CS_EUNSUPPORTED
+    assert _lib.load().cs_grad_create(frame.handle, 4, 2, __import__("ctypes").byref(h)) == _lib.CS_EUNSUPPORTED
 
 
 def test_full_size_192x192x24_12c_k20_ckpt5_sampled_columns():

@@ -1,0 +1,165 @@
+"""GPU parity of the unrolled-ADMM derivative for Algorithm 1 (temporal DFT
+prior) through the C ABI and the torch.autograd binding, against the FP64
+reverse sweep of the oracle and FP64 central differences of the oracle's
+forward map.  Tolerance 1e-3 (relative l2 for dL/dy, relative for the
+scalars), as for Algorithm 2."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import gradient as OG
+from paper_1203_4587_amd import synthetic as S
+from tests.helpers import Case, make_case, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GTOL = 1e-3
+LAM, MU = 0.02, 0.1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _rand_c(rng, shape):
+    """complex64 draws (what the GPU receives); the oracle takes them upcast"""
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+
+
+def _case(nv, nh, nt, nc, seed):
+    return make_case(nv, nh, nt, nc, accel=3, ncenter=2, prior="dft", family="periodic", seed=seed, sigma=0.01)
+
+
+def _setup(case, iters, every, flags=0):
+    from paper_1203_4587_amd.api import Plan
+    from paper_1203_4587_amd.autograd import Unrolled
+    coil, mask, y = case.device()
+    plan = Plan(coil, mask, MU, prior="dft", flags=flags)
+    return plan, Unrolled(plan, iters, every), y
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-30)
+
+
+@pytest.mark.parametrize("every", [1, 3, 7, 50])
+def test_forward_ckpt_equals_plain_solve(every):
+    from paper_1203_4587_amd import _lib
+    case = _case(48, 32, 8, 3, seed=41)
+    for flags in (0, _lib.CS_FLAG_COLUMN_RESIDENT, _lib.CS_FLAG_GRAPH):
+        plan, un, y = _setup(case, 12, every, flags)
+        x = un.forward_raw(y, LAM, MU)
+        assert torch.equal(x, plan.solve(y, LAM, 12)), flags
+        un.close()
+
+
+@pytest.mark.parametrize("shape,iters,every", [((48, 32, 8, 3), 10, 3), ((64, 16, 12, 4), 6, 6),
+                                               ((27, 12, 5, 2), 8, 5),     # odd nv: row x-update
+                                               ((32, 8, 1, 2), 5, 2),      # one frame: Psi = 1
+                                               ((96, 12, 40, 3), 4, 3),    # 80-wide embedding
+                                               ((16, 8, 64, 2), 3, 2)],    # maximum frame count
+                         ids=str)
+def test_gradient_matches_oracle_reference(shape, iters, every):
+    """dL/dy, dL/dlambda, dL/dmu of L = Re<g, x_K> against the FP64 reverse sweep."""
+    nv, nh, nt, nc = shape
+    case = _case(nv, nh, nt, nc, seed=nv * nt + iters)
+    rng = np.random.default_rng(nv + nt)
+    g = _rand_c(rng, case.x_true.shape)
+    plan, un, y = _setup(case, iters, every)
+    un.forward_raw(y, LAM, MU)
+    gy, gs = un.backward_raw(torch.from_numpy(g).cuda())
+    ref = OG.unrolled_dft_grad_y(case.y, case.coil, case.mask, LAM, MU, iters, g.astype(np.complex128))
+    ey = rel_l2(gy.cpu().numpy(), ref["y"])
+    el, em = _rel(float(gs[0]), ref["lam"]), _rel(float(gs[1]), ref["mu"])
+    print(shape, iters, every, "dy", ey, "dlam", el, "dmu", em)
+    assert ey < GTOL and el < GTOL and em < GTOL
+    # a second backward of the same forward (which recomputes every segment) is identical
+    gy2, gs2 = un.backward_raw(torch.from_numpy(g).cuda())
+    assert torch.equal(gy, gy2) and torch.equal(gs, gs2)
+
+
+def test_gradient_matches_fp64_finite_differences():
+    case = _case(32, 16, 6, 3, seed=8)
+    K = 8
+    rng = np.random.default_rng(9)
+    g = _rand_c(rng, case.x_true.shape)
+    plan, un, y = _setup(case, K, 3)
+    un.forward_raw(y, LAM, MU)
+    gy, gs = un.backward_raw(torch.from_numpy(g).cuda())
+    fac = O.BlockFactor(case.coil, case.mask)
+    g64 = g.astype(np.complex128)
+    L = lambda yy=case.y, lam=LAM, mu=MU: OG.unrolled_dft_loss(yy, case.coil, case.mask, lam, mu, K, g64, fac=fac)
+    h = 1e-6
+    dy = (rng.standard_normal(case.y.shape) + 1j * rng.standard_normal(case.y.shape)) * case.mask[:, None, :, None]
+    fd_y = (L(yy=case.y + h * dy) - L(yy=case.y - h * dy)) / (2 * h)
+    an_y = float(np.real(np.vdot(gy.cpu().numpy().astype(np.complex128), dy)))
+    fd_l = (L(lam=LAM + h) - L(lam=LAM - h)) / (2 * h)
+    fd_m = (L(mu=MU + h) - L(mu=MU - h)) / (2 * h)
+    print("fd y", fd_y, an_y, "lam", fd_l, float(gs[0]), "mu", fd_m, float(gs[1]))
+    assert _rel(an_y, fd_y) < GTOL
+    assert _rel(float(gs[0]), fd_l) < GTOL
+    assert _rel(float(gs[1]), fd_m) < GTOL
+
+
+def test_checkpoint_schedule_does_not_change_gradients():
+    case = _case(48, 32, 8, 3, seed=77)
+    rng = np.random.default_rng(5)
+    g = torch.from_numpy(_rand_c(rng, case.x_true.shape)).cuda()
+    out = []
+    for every in (1, 4, 9):
+        plan, un, y = _setup(case, 9, every)
+        un.forward_raw(y, LAM, MU)
+        out.append(un.backward_raw(g))
+        un.close()
+    for gy, gs in out[1:]:
+        assert torch.equal(gy, out[0][0]) and torch.equal(gs, out[0][1])
+
+
+def test_autograd_zero_iterations_and_errors():
+    from paper_1203_4587_amd import _lib
+    case = _case(48, 16, 8, 3, seed=13)
+    rng = np.random.default_rng(14)
+    g = torch.from_numpy(_rand_c(rng, case.x_true.shape)).cuda()
+    plan, un, y = _setup(case, 7, 3)
+    yv = y.clone().requires_grad_(True)
+    lam = torch.tensor(LAM, requires_grad=True)
+    mu = torch.tensor(MU, requires_grad=True)
+    x = un(yv, lam, mu)
+    torch.real(torch.sum(torch.conj(g) * x)).backward()
+    un.forward_raw(y, LAM, MU)
+    gy, gs = un.backward_raw(g)
+    assert torch.equal(yv.grad, gy)
+    assert lam.grad.item() == float(gs[0]) and mu.grad.item() == float(gs[1])
+    # K = 0: x = H'y, so dL/dy = A(g) and the scalars get nothing
+    plan0, un0, y0 = _setup(case, 0, 5)
+    assert torch.equal(un0.forward_raw(y0, LAM, MU), plan0.solve(y0, LAM, 0))
+    gy0, gs0 = un0.backward_raw(g)
+    assert torch.allclose(gy0, plan0.apply_A(g), rtol=1e-6, atol=1e-6)
+    assert float(gs0[0]) == 0.0 and float(gs0[1]) == 0.0
+
+
+def test_full_size_192x192x40_12c_k10_sampled_columns():
+    """The 192x192x40, 12-coil, R=10 periodic workload, K = 10 unrolled
+    iterations with a checkpoint every 5; the loss gradient lives on two
+    columns so the oracle's reverse sweep covers it exactly."""
+    pr = S.CONFIGS["dft192"]()
+    case = Case(pr)
+    nt, nv, nh = pr.x_true.shape
+    K = 10
+    cols = np.array([3, nh // 2 + 1])
+    rng = np.random.default_rng(19)
+    gs_cols = _rand_c(rng, (nt, nv, cols.size))
+    g = np.zeros((nt, nv, nh), dtype=np.complex64)
+    g[:, :, cols] = gs_cols
+    plan, un, y = _setup(case, K, 5)
+    un.forward_raw(y, pr.lam, pr.mu)
+    gy, gsc = un.backward_raw(torch.from_numpy(g).cuda())
+    ref = OG.unrolled_dft_grad_y(case.y, case.coil, case.mask, pr.lam, pr.mu, K, gs_cols.astype(np.complex128),
+                                 cols=cols)
+    ey = rel_l2(gy.cpu().numpy(), ref["y"])
+    el, em = _rel(float(gsc[0]), ref["lam"]), _rel(float(gsc[1]), ref["mu"])
+    print("dft192 K=10 dy", ey, "dlam", el, "dmu", em)
+    assert ey < GTOL and el < GTOL and em < GTOL
