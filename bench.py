@@ -229,6 +229,30 @@ def unrolled_throughput(reps: int) -> dict:
     })
     un.close()
     plan.close()
+    del y, g
+    torch.cuda.empty_cache()
+    # Algorithm 1 (temporal DFT) on the 192x192x40, 12-coil, R=10 workload
+    pr = S.CONFIGS["dft192"]()
+    plan = Plan(to_device(pr.coil), to_device(pr.mask, dtype=torch.uint8), pr.mu, prior="dft")
+    y = plan.apply_A(to_device(pr.x_true)) + to_device(pr.noise)
+    un = Unrolled(plan, 20, 5)
+    g = torch.randn(plan.image_shape, dtype=torch.complex64, device="cuda")
+    dres = {}
+    for name, fn in (("forward", lambda: un.forward_raw(y, pr.lam, pr.mu)),
+                     ("forward_backward", lambda: (un.forward_raw(y, pr.lam, pr.mu), un.backward_raw(g)))):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        dres[f"{name}_ms"] = round(1e3 * _median(ts), 3)
+    dres["workload"] = "dft-192x192x40-12c R10, K=20 unrolled, checkpoint every 5"
+    res["dft"] = dres
+    un.close()
+    plan.close()
     return res
 
 
