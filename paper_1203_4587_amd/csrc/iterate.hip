@@ -1400,7 +1400,7 @@ __device__ __forceinline__ void block_reduce_store(double v, double* out) {
   red[threadIdx.x] = v;
   __syncthreads();
   for (int w = kJThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = red[0];
@@ -1507,7 +1507,7 @@ __global__ __launch_bounds__(kJThreads) void k_j_final(const double* __restrict_
 
 // x in solver layout; the plan's ktmp must hold F_h' y (set by the solve setup)
 int launch_objective(cs_plan* p, const float2* x, float lambda, float* out, hipStream_t s) {
-  const int nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
+  const int nh = p->desc.nh, nt = p->desc.nt;
   const size_t npix = (size_t)p->desc.nv * nh;
   int st = launch_forward_residual(p, x, p->jpart, kJBlocks, s);  // data term, fused with the vertical pass
   if (st != CS_OK) return st;
