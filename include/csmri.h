@@ -179,11 +179,12 @@ int cs_plan_set_fft_tiles(cs_plan* plan, int32_t cols, int32_t rows);
 
 /* Autotuner: first picks the FFT tiles (every pair from the largest tiles down
  * to 1/16 of their columns and 1/4 of their rows, timed on H'y of y plus the
- * vertical forward pass), then times `iters` iterations (after as many untimed ones) of every
- * execution form the plan supports -- phase form with each x-update form
- * (graph-replayed), and the column-resident form -- on the data y, and keeps
- * the fastest in the plan's flags (CS_FLAG_NO_REFACTOR is preserved).
- * entries (host array of `cap`, may be NULL) receives the flags and measured
+ * vertical forward pass), then times `iters` iterations (after as many
+ * untimed ones) of every execution form the plan supports -- phase form with
+ * each x-update form (graph-replayed), and the column-resident form -- on the
+ * data y, in three interleaved rounds, and keeps the form with the fastest
+ * round in the plan's flags (CS_FLAG_NO_REFACTOR is preserved).  entries
+ * (host array of `cap`, may be NULL) receives the flags and fastest measured
  * ms per iteration of each candidate; *count (may be NULL) their number.
  * Synchronises `stream`.  The plan's solver workspaces are overwritten. */
 typedef struct {
