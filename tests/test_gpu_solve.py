@@ -106,7 +106,8 @@ def test_zero_iterations_return_initialisation(prior):
 @pytest.mark.parametrize("prior,shape", [("tv", (48, 32, 8, 3)), ("dft", (48, 32, 8, 3)),
                                          ("dft", (27, 12, 40, 2)),   # 324 pixels: ragged last tile, KP = 80
                                          ("dft", (16, 6, 64, 2)),    # maximum frame count, KP = 128
-                                         ("tv", (27, 12, 40, 2))], ids=str)
+                                         ("tv", (27, 12, 40, 2)),
+                                         ("tv", (384, 4, 5, 2))], ids=str)      # 512-value wave FFT groups
 def test_objective_trace_matches_oracle(prior, shape):
     fam = "cardiac" if prior == "tv" else "periodic"
     nv, nh, nt, nc = shape
