@@ -259,9 +259,8 @@ int cs_batch_solve(cs_batch* batch, const cs_c64* const* y, const float* lambda,
  * its checkpoint except the one the forward kept (so ckpt_every >= iters
  * recomputes nothing), and applies the transposed Jacobian of each line of the
  * algorithm in reverse (the x-update kernel applies the Hermitian
- * (mu I + H'H)^{-1}; one per-pixel kernel does the transposed temporal step
- * (for the DFT prior three contractions on the matrix cores), soft threshold
- * and dual updates).  Memory: about 4 images per checkpoint plus 3 per
+ * (mu I + H'H)^{-1}; one kernel over 16-pixel tiles does the transposed
+ * temporal step on the matrix cores, the soft threshold and the dual updates).  Memory: about 4 images per checkpoint plus 3 per
  * iteration of a segment plus 7.
  * dL/dy = A(dL/dH'y) is zero on rows the mask does not sample.  Where some
  * |D m + d1| equals tau exactly the map is not differentiable; the derivative

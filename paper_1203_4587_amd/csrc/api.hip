@@ -468,18 +468,6 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
           hfrag[((size_t)mm * kks + kk) * 64 + l] = (float)E[(size_t)r * kp + c];
         }
   }
-  // Thomas pivots of rho I + D'D: den_0 = b_0, den_t = b_t - 1/den_{t-1}
-  std::vector<float> hinv(nt, 0.f);
-  if (desc->prior == CS_PRIOR_TEMPORAL_TV) {
-    const double rho = desc->mu_ratio;
-    double den = 0;
-    for (int t = 0; t < nt; ++t) {
-      const double b = rho + ((t == 0 || t == nt - 1) ? 1.0 : 2.0);
-      den = t == 0 ? b : b - 1.0 / den;
-      hinv[t] = (float)(1.0 / den);
-    }
-  }
-
   // MFMA fragments of T^{-1}, T = rho I + D'D (FP64 Gauss-Jordan; T is symmetric
   // positive definite), padded to KT = nt rounded up to 16, same lane layout
   // as the DFT fragments
@@ -522,7 +510,6 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
       (st = plan_alloc(p, &p->tw_h, (size_t)nh, "tw_h")) ||
       (st = plan_alloc(p, &p->psi_t, hpsi.size(), "psi")) ||
       (st = plan_alloc(p, &p->dft_frags, hfrag.size(), "psi fragments")) ||
-      (st = plan_alloc(p, &p->tv_invden, (size_t)nt, "tv_invden")) ||
       (st = plan_alloc(p, &p->tv_frags, htfrag.size(), "tv fragments")) ||
       (st = plan_alloc(p, &p->coil_cm, npix * nc, "coil")) ||
       (st = plan_alloc(p, &p->ktmp, ksz, "ktmp")) ||
@@ -551,7 +538,6 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
   UP(p->tw_h, htwh.data(), htwh.size() * sizeof(float2));
   UP(p->psi_t, hpsi.data(), hpsi.size() * sizeof(float2));
   UP(p->dft_frags, hfrag.data(), hfrag.size() * sizeof(float));
-  UP(p->tv_invden, hinv.data(), hinv.size() * sizeof(float));
   UP(p->tv_frags, htfrag.data(), htfrag.size() * sizeof(float));
 #undef UP
   // coil maps [c][j][i] -> column-major [c][i][j]

@@ -21,11 +21,11 @@
 // and at the end x_0 = m_0 = H'y adds mb + xb to dL/dH'y, tau = lambda rho/(2 mu)
 // turns dL/dtau into dL/dlambda and dL/dmu, and dL/dy = A(dL/dH'y).
 //
-// Kernels: the x-update kernel applies W (bb = W e with e = xb' + d2b'); one
-// per-pixel kernel does everything else (three passes over the pixel's frames:
-// the Thomas sweep, the back substitution, then the elementwise tail), with
-// per-workgroup FP64 partial sums of dL/dtau and dL/dmu that each workgroup
-// accumulates in its own slot (no atomics; summed in a fixed order at the end).
+// Kernels: the x-update kernel applies W (bb = W e with e = xb' + d2b');
+// k_tv_adjoint_tiles (iterate.hip) does everything else, 16 pixels per wave,
+// with T^{-1} applied on the matrix cores, and accumulates per-workgroup FP64
+// partial sums of dL/dtau and dL/dmu in its own slot (no atomics; summed in a
+// fixed order at the end).
 #include <algorithm>
 #include <new>
 
@@ -36,106 +36,8 @@ namespace csmri {
 int run_iterations(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace, const float2* wgiven,
                    hipStream_t s);
 
-constexpr int kAdjThreads = 64;
-
-template <int NT>
-__global__ __launch_bounds__(kAdjThreads) void k_tv_adjoint(
-    float2* __restrict__ mb, float2* __restrict__ d1b, float2* __restrict__ d2b, float2* __restrict__ e,
-    const float2* __restrict__ bb, float2* __restrict__ hyb, const float2* __restrict__ m,
-    const float2* __restrict__ d1, const float2* __restrict__ d2n, const float* __restrict__ invden,
-    double* __restrict__ partial, int nt, size_t npix, float tau, float rho, float mu, int last) {
-  const size_t p = (size_t)blockIdx.x * kAdjThreads + threadIdx.x;
-  double tsum = 0.0, msum = 0.0;
-  if (p < npix) {
-    float2 C[NT];
-    // pass 1: q_t = mb'_t - d2b'_t + (D' d1b')_t + mu bb_t, forward Thomas sweep
-    float2 wprev = make_float2(0.f, 0.f), c = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (t < nt) {
-        const size_t o = (size_t)t * npix + p;
-        const float2 w = t < nt - 1 ? d1b[o] : make_float2(0.f, 0.f);
-        const float2 a = mb[o], z = d2b[o], b = bb[o];
-        const float2 q = make_float2(fmaf(mu, b.x, (a.x - z.x) + (wprev.x - w.x)),
-                                     fmaf(mu, b.y, (a.y - z.y) + (wprev.y - w.y)));
-        wprev = w;
-        const float iv = invden[t];
-        c = make_float2((q.x + c.x) * iv, (q.y + c.y) * iv);
-        C[t] = c;
-      }
-    }
-    // pass 2: back substitution rb_t = c_t + invden_t rb_{t+1}
-    float2 rnext = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int t = NT - 1; t >= 0; --t) {
-      if (t < nt) {
-        float2 r = C[t];
-        if (t < nt - 1) {
-          const float iv = invden[t];
-          r = make_float2(fmaf(iv, rnext.x, r.x), fmaf(iv, rnext.y, r.y));
-        }
-        C[t] = r;
-        rnext = r;
-      }
-    }
-    // pass 3: soft-threshold adjoint, new adjoint state, accumulators
-    float2 abprev = make_float2(0.f, 0.f);
-    float2 mcur = m[p];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (t < nt) {
-        const size_t o = (size_t)t * npix + p;
-        float2 ab = make_float2(0.f, 0.f);
-        if (t + 1 < NT && t < nt - 1) {
-          const float2 dr = csub(C[t + 1], C[t]);
-          const float2 w = d1b[o];
-          const float2 vb = csub(dr, w);
-          const float2 mnext = m[o + npix];
-          const float2 dd = d1[o];
-          // same arithmetic as the forward step, so the same |a| > tau decision
-          const float2 a = make_float2(mnext.x - mcur.x + dd.x, mnext.y - mcur.y + dd.y);
-          mcur = mnext;
-          const float mag = sqrtf(fmaf(a.x, a.x, a.y * a.y));
-          if (mag > tau) {
-            const float sdot = fmaf(a.x, vb.x, a.y * vb.y) / mag;  // Re(conj(a/|a|) vb)
-            const float k = tau / mag;
-            const float ks = k * sdot / mag;
-            ab = make_float2(fmaf(1.f - k, vb.x, ks * a.x), fmaf(1.f - k, vb.y, ks * a.y));
-            tsum -= (double)sdot;
-          }
-          d1b[o] = cadd(csub(w, dr), ab);
-        }
-        const float2 mnew = csub(abprev, ab);  // (D' ab)_t = ab_{t-1} - ab_t
-        abprev = ab;
-        const float2 b = bb[o], z = d2b[o], r = C[t], dn = d2n[o];
-        const float2 xb = make_float2(rho * r.x, rho * r.y);
-        const float2 z2 = make_float2(fmaf(-mu, b.x, z.x) + xb.x, fmaf(-mu, b.y, z.y) + xb.y);
-        d2b[o] = z2;
-        e[o] = cadd(xb, z2);
-        mb[o] = mnew;
-        float2 h = cadd(hyb[o], b);
-        if (last) h = cadd(h, cadd(mnew, xb));  // x_0 = m_0 = H'y
-        hyb[o] = h;
-        msum -= (double)fmaf(b.x, dn.x, b.y * dn.y);
-      }
-    }
-  }
-  __shared__ double red[2][kAdjThreads];
-  red[0][threadIdx.x] = tsum;
-  red[1][threadIdx.x] = msum;
-  __syncthreads();
-  for (int w = kAdjThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + w];
-      red[1][threadIdx.x] += red[1][threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] += red[0][0];
-    partial[2 * blockIdx.x + 1] += red[1][0];
-  }
-}
+// partial sums: one FP64 pair per 64 pixels (a workgroup of the reverse-step kernels)
+constexpr int kAdjPixels = 64;
 
 // dL/dlambda and dL/dmu from the accumulated dL/dtau and direct dL/dmu
 __global__ __launch_bounds__(256) void k_grad_finish(const double* __restrict__ partial, int nslots,
@@ -162,15 +64,6 @@ __global__ __launch_bounds__(256) void k_grad_finish(const double* __restrict__ 
     out[0] = (float)(gtau * rho / (2.0 * mu));
     out[1] = (float)(gmu - gtau * lambda * rho / (2.0 * mu * mu));
   }
-}
-
-template <int NT>
-static void adjoint_launch(unsigned blocks, hipStream_t s, float2* mb, float2* d1b, float2* d2b, float2* e,
-                           const float2* bb, float2* hyb, const float2* m, const float2* d1, const float2* d2n,
-                           const float* invden, double* partial, int nt, size_t npix, float tau, float rho,
-                           float mu, int last) {
-  hipLaunchKernelGGL(k_tv_adjoint<NT>, dim3(blocks), dim3(kAdjThreads), 0, s, mb, d1b, d2b, e, bb, hyb, m, d1,
-                     d2n, invden, partial, nt, npix, tau, rho, mu, last);
 }
 
 }  // namespace csmri
@@ -306,7 +199,7 @@ int cs_grad_create(cs_plan* p, int32_t iters, int32_t every, cs_grad** out) {
   g->nseg = (iters + g->every - 1) / g->every;
   g->npix = (size_t)p->desc.nv * p->desc.nh;
   g->nimg = g->npix * p->desc.nt;
-  g->nslots = (int)((g->npix + kAdjThreads - 1) / kAdjThreads);
+  g->nslots = (int)((g->npix + kAdjPixels - 1) / kAdjPixels);
   int st = CS_OK;
   auto A = [&](float2** q) {
     if (st == CS_OK) st = grad_alloc(g, q, g->nimg);
@@ -471,20 +364,8 @@ int cs_admm_backward(cs_grad* g, const cs_c64* grad_x, cs_c64* grad_y, float* gr
       CK(launch_block_solve(p, kSolvePlain, g->e, nullptr, nullptr, g->bb, mu, s));  // bb = W e
       if (st != CS_OK) break;
       const int last = (seg == 0 && j == 0) ? 1 : 0;
-      auto go = [&](auto tag) {
-        constexpr int NT = decltype(tag)::value;
-        adjoint_launch<NT>(blocks, s, g->mb, g->d1b, g->d2b, g->e, g->bb, g->hyb, g->tm[j], g->td1[j],
-                           g->td2[j + 1], p->tv_invden, g->partial, nt, g->npix, tau, rho, mu, last);
-      };
-      if (nt <= 8) go(std::integral_constant<int, 8>{});
-      else if (nt <= 16) go(std::integral_constant<int, 16>{});
-      else if (nt <= 24) go(std::integral_constant<int, 24>{});
-      else if (nt <= 32) go(std::integral_constant<int, 32>{});
-      else if (nt <= 40) go(std::integral_constant<int, 40>{});
-      else if (nt <= 48) go(std::integral_constant<int, 48>{});
-      else go(std::integral_constant<int, 64>{});
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) st = hip_fail(e, "k_tv_adjoint");
+      CK(launch_tv_adjoint(p, blocks, g->mb, g->d1b, g->d2b, g->e, g->bb, g->hyb, g->tm[j], g->td1[j],
+                           g->td2[j + 1], g->partial, tau, rho, mu, last, s));
     }
   }
   if (g->iters == 0) CK(launch_copy(g->e, g->hyb, n, s));  // x_K = x_0 = H'y

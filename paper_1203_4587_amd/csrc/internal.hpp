@@ -162,7 +162,6 @@ struct cs_plan {
   float2* tw_h = nullptr;
   float2* psi_t = nullptr;      // [nt][nt] unitary temporal DFT matrix (DFT prior)
   float* dft_frags = nullptr;   // MFMA A-operand fragments of the embedded Psi and Psi' (DFT prior)
-  float* tv_invden = nullptr;   // [nt] Thomas coefficients of (rho I + D'D) (gradient sweep)
   float* tv_frags = nullptr;    // MFMA A-operand fragments of (rho I + D'D)^{-1}, padded to 16 (TV step)
 
   // coil maps in the solver's column-major layout [c][i][j]
@@ -206,6 +205,10 @@ namespace csmri {
 // sense.hip
 int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipStream_t s);
 // reverse step of one Algorithm 1 iteration (temporal DFT prior): see iterate.hip
+// reverse step of one Algorithm 2 iteration (temporal TV prior), after bb = W e: see iterate.hip
+int launch_tv_adjoint(cs_plan* p, unsigned nblocks, float2* mb, float2* d1b, float2* d2b, float2* e,
+                      const float2* bb, float2* hyb, const float2* m, const float2* d1, const float2* d2n,
+                      double* partial, float tau, float rho, float mu, int last, hipStream_t s);
 int launch_dft_adjoint(cs_plan* p, unsigned nblocks, const float2* bb, float2* db, float2* zb, float2* hyb,
                        const float2* zprev, const float2* dprev, const float2* u, const float2* z, double* partial,
                        float tau, float mu, int last, hipStream_t s);

@@ -1217,6 +1217,183 @@ int launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s) {
   return CS_OK;
 }
 
+// ---------------------------------------------------------------- Algorithm 2 reverse step
+//
+// The per-pixel part of the transposed Jacobian of one Algorithm 2 iteration
+// (the x-update kernel applies W before it: bb = W e), given the adjoints
+// (mb', d1b', d2b') of the state after the iteration and the stored m, d1 of
+// its start and d2 after it (T = rho I + D'D, D = D_t):
+//   q   = mb' - d2b' + D' d1b' + mu bb;   rb = T^{-1} q
+//   vb  = D rb - d1b';   ab = (dsoft/da)^T vb  (real 2x2 Jacobian on |a| > tau)
+//   mb  = D' ab;   d1b = d1b' - D rb + ab;   xb = rho rb;   d2b = d2b' - mu bb + xb;   e = xb + d2b
+//   dL/dH'y += bb (+ mb + xb for the first iteration, x_0 = m_0 = H'y)
+//   dL/dtau += -sum_{|a| > tau} Re(conj(a/|a|) vb);   dL/dmu += -Re<bb, d2'>
+// As in the forward TV step, 16 pixels per wave: lane l holds pixel l % 16
+// and frames l / 16 + 4 k, neighbouring frames pass through the wave's LDS,
+// and T^{-1} (symmetric, so its own transpose) is applied as the contraction
+// of the forward's fragments.  a = D m + d1 is formed with the forward's own
+// arithmetic, so every |a| > tau decision is the forward's.  A fixed grid
+// with a grid-stride loop; one FP64 slot pair per workgroup.
+template <int KT>
+__global__ __launch_bounds__(256) void k_tv_adjoint_tiles(
+    const float* __restrict__ frags, float2* __restrict__ mb, float2* __restrict__ d1b, float2* __restrict__ d2b,
+    float2* __restrict__ e, const float2* __restrict__ bb, float2* __restrict__ hyb, const float2* __restrict__ m,
+    const float2* __restrict__ d1, const float2* __restrict__ d2n, double* __restrict__ partial, int nt,
+    size_t npix, float tau, float rho, float mu, int last) {
+  constexpr int MT = DftTile<KT>::MT, NK = KT / 4;
+  extern __shared__ float lds_f[];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, grp = lane >> 4;
+  float2* bufA = reinterpret_cast<float2*>(lds_f + DftTile<KT>::FRAG + wv * tv_wave_floats(KT));
+  float2* bufB = bufA + KT * 16;
+  float* bre = reinterpret_cast<float*>(bufB);
+  float* bim = bre + KT * 16;
+  load_frags<KT>(lds_f, frags);
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  const size_t ntiles = (npix + 15) / 16;
+  double tsum = 0.0, msum = 0.0;
+  for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
+    const size_t p0 = tl * 16;
+    const bool pv = col < (int)std::min<size_t>(16, npix - p0);
+    const size_t p = p0 + col;
+    float2 w[NK], bv[NK];
+    // d1b' of this lane's frames, shared for the D' d1b' term
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = grp + 4 * k;
+      w[k] = (t < nt - 1 && pv) ? d1b[(size_t)t * npix + p] : make_float2(0.f, 0.f);
+      bufA[t * 16 + col] = w[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+    // q, as the real and imaginary operand rows
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = grp + 4 * k;
+      const bool ok = t < nt && pv;
+      const size_t o = (size_t)t * npix + p;
+      float2 q = make_float2(0.f, 0.f);
+      bv[k] = ok ? bb[o] : make_float2(0.f, 0.f);
+      if (ok) {
+        const float2 a = mb[o], z = d2b[o];
+        const float2 wprev = t > 0 ? bufA[(t - 1) * 16 + col] : make_float2(0.f, 0.f);
+        q = make_float2(fmaf(mu, bv[k].x, (a.x - z.x) + (wprev.x - w[k].x)),
+                        fmaf(mu, bv[k].y, (a.y - z.y) + (wprev.y - w[k].y)));
+      }
+      bre[t * 16 + col] = q.x;
+      bim[t * 16 + col] = q.y;
+    }
+    __builtin_amdgcn_wave_barrier();
+    mfma_v4 rre[MT], rim[MT];
+    tile_gemm<KT, false>(lds_f, bre, lane, rre);
+    tile_gemm<KT, false>(lds_f, bim, lane, rim);
+    __builtin_amdgcn_wave_barrier();
+    // rb into bufB (accumulator lane l holds frames 16 mm + 4 (l / 16) + j), m into bufA
+#pragma unroll
+    for (int mm = 0; mm < MT; ++mm)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bufB[(16 * mm + 4 * grp + j) * 16 + col] = make_float2(rre[mm][j], rim[mm][j]);
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = grp + 4 * k;
+      bufA[t * 16 + col] = (t < nt && pv) ? m[(size_t)t * npix + p] : make_float2(0.f, 0.f);
+    }
+    __builtin_amdgcn_wave_barrier();
+    float2 ab[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = grp + 4 * k;
+      ab[k] = make_float2(0.f, 0.f);
+      if (t < nt - 1 && pv) {
+        const size_t o = (size_t)t * npix + p;
+        const float2 dr = csub(bufB[(t + 1) * 16 + col], bufB[t * 16 + col]);
+        const float2 vb = csub(dr, w[k]);
+        const float2 m0 = bufA[t * 16 + col], m1 = bufA[(t + 1) * 16 + col], dd = d1[o];
+        // same arithmetic as the forward step, so the same |a| > tau decision
+        const float2 a = make_float2(m1.x - m0.x + dd.x, m1.y - m0.y + dd.y);
+        const float mag = sqrtf(fmaf(a.x, a.x, a.y * a.y));
+        if (mag > tau) {
+          const float sdot = fmaf(a.x, vb.x, a.y * vb.y) / mag;  // Re(conj(a/|a|) vb)
+          const float kk = tau / mag;
+          const float ks = kk * sdot / mag;
+          ab[k] = make_float2(fmaf(1.f - kk, vb.x, ks * a.x), fmaf(1.f - kk, vb.y, ks * a.y));
+          tsum -= (double)sdot;
+        }
+        d1b[o] = cadd(csub(w[k], dr), ab[k]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < NK; ++k) bufA[(grp + 4 * k) * 16 + col] = ab[k];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = grp + 4 * k;
+      if (t < nt && pv) {
+        const size_t o = (size_t)t * npix + p;
+        const float2 abprev = t > 0 ? bufA[(t - 1) * 16 + col] : make_float2(0.f, 0.f);
+        const float2 mnew = csub(abprev, ab[k]);  // (D' ab)_t = ab_{t-1} - ab_t
+        const float2 r = bufB[t * 16 + col], b = bv[k], z = d2b[o], dn = d2n[o];
+        const float2 xb = make_float2(rho * r.x, rho * r.y);
+        const float2 z2 = make_float2(fmaf(-mu, b.x, z.x) + xb.x, fmaf(-mu, b.y, z.y) + xb.y);
+        d2b[o] = z2;
+        e[o] = cadd(xb, z2);
+        mb[o] = mnew;
+        float2 h = cadd(hyb[o], b);
+        if (last) h = cadd(h, cadd(mnew, xb));
+        hyb[o] = h;
+        msum -= (double)fmaf(b.x, dn.x, b.y * dn.y);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();  // the next tile overwrites this wave's buffers
+  }
+  __shared__ double red[2][256];
+  red[0][threadIdx.x] = tsum;
+  red[1][threadIdx.x] = msum;
+  __syncthreads();
+  for (int k = (int)blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + k];
+      red[1][threadIdx.x] += red[1][threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] += red[0][0];
+    partial[2 * blockIdx.x + 1] += red[1][0];
+  }
+}
+
+template <int KT>
+static int tv_adjoint_launch(cs_plan* p, unsigned nblocks, float2* mb, float2* d1b, float2* d2b, float2* e,
+                             const float2* bb, float2* hyb, const float2* m, const float2* d1, const float2* d2n,
+                             double* partial, float tau, float rho, float mu, int last, hipStream_t s) {
+  constexpr int waves = 4;
+  const size_t npix = (size_t)p->desc.nv * p->desc.nh;
+  const size_t lds = ((size_t)DftTile<KT>::FRAG + (size_t)waves * tv_wave_floats(KT)) * sizeof(float);
+  static bool attr = false;
+  if (lds > 65536 && !attr) {
+    CS_HIP(hipFuncSetAttribute((const void*)k_tv_adjoint_tiles<KT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_tv_adjoint_tiles<KT>, dim3(nblocks), dim3(64 * waves), lds, s, p->tv_frags, mb, d1b, d2b, e,
+                     bb, hyb, m, d1, d2n, partial, p->desc.nt, npix, tau, rho, mu, last);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
+int launch_tv_adjoint(cs_plan* p, unsigned nblocks, float2* mb, float2* d1b, float2* d2b, float2* e,
+                      const float2* bb, float2* hyb, const float2* m, const float2* d1, const float2* d2n,
+                      double* partial, float tau, float rho, float mu, int last, hipStream_t s) {
+  switch (tv_kt(p->desc.nt)) {
+    case 16: return tv_adjoint_launch<16>(p, nblocks, mb, d1b, d2b, e, bb, hyb, m, d1, d2n, partial, tau, rho, mu, last, s);
+    case 32: return tv_adjoint_launch<32>(p, nblocks, mb, d1b, d2b, e, bb, hyb, m, d1, d2n, partial, tau, rho, mu, last, s);
+    case 48: return tv_adjoint_launch<48>(p, nblocks, mb, d1b, d2b, e, bb, hyb, m, d1, d2n, partial, tau, rho, mu, last, s);
+    default: return tv_adjoint_launch<64>(p, nblocks, mb, d1b, d2b, e, bb, hyb, m, d1, d2n, partial, tau, rho, mu, last, s);
+  }
+}
+
 // ---------------------------------------------------------------- Algorithm 1 reverse step
 //
 // Transposed Jacobian of one iteration of Algorithm 1 with Psi the unitary
