@@ -108,6 +108,23 @@ static int one_iteration(cs_plan* p, float lambda, float mu, hipStream_t s) {
   return run_iterations(p, 1, lambda, mu, nullptr, nullptr, s);
 }
 
+// L iterations of Algorithm 2 on the plan's state (m = s0, d1 = s1, x = s2,
+// d2 = s3), one at a time, keeping m_j and d1_j before step j + 1 and d2 after it
+static int tv_segment_tape(cs_grad* g, int L, float lambda, float mu, hipStream_t s) {
+  cs_plan* p = g->plan;
+  const size_t n = g->nimg;
+  int st = launch_copy_multi(CopyPairs{{p->s0, p->s1}, {g->tm[0], g->td1[0]}, 2}, n, s);
+  for (int j = 0; j < L && st == CS_OK; ++j) {
+    st = one_iteration(p, lambda, mu, s);
+    if (st != CS_OK) break;
+    if (j + 1 < L)
+      st = launch_copy_multi(CopyPairs{{p->s3, p->s0, p->s1}, {g->td2[j + 1], g->tm[j + 1], g->td1[j + 1]}, 3}, n, s);
+    else
+      st = launch_copy(p->s3, g->td2[j + 1], n, s);
+  }
+  return st;
+}
+
 // L iterations of Algorithm 1 on the plan's state (z = s2, d = s0, v = s1),
 // one at a time, keeping z before each and the completed d and u after it;
 // cont: the first of them continues the solve (completes the deferred d)
@@ -115,13 +132,13 @@ static int dft_segment_tape(cs_grad* g, int L, float lambda, float mu, bool cont
   cs_plan* p = g->plan;
   const size_t n = g->nimg;
   int st = CS_OK;
+  st = launch_copy(p->s2, g->tm[0], n, s);
   for (int j = 0; j < L && st == CS_OK; ++j) {
-    st = launch_copy(p->s2, g->tm[j], n, s);
-    if (st == CS_OK) st = run_iterations_cont(p, 1, lambda, mu, cont || j > 0, s);
-    if (st == CS_OK) st = launch_copy(p->s0, g->td1[j], n, s);
-    if (st == CS_OK) st = launch_copy(p->s3, g->td2[j], n, s);
+    st = run_iterations_cont(p, 1, lambda, mu, cont || j > 0, s);
+    // d and u after step j, and z before step j + 1 (= after step j)
+    if (st == CS_OK) st = launch_copy_multi(CopyPairs{{p->s0, p->s3, p->s2}, {g->td1[j], g->td2[j], g->tm[j + 1]}, 3},
+                                            n, s);
   }
-  if (st == CS_OK) st = launch_copy(p->s2, g->tm[L], n, s);
   return st;
 }
 
@@ -155,9 +172,8 @@ static int dft_backward(cs_grad* g, const cs_c64* grad_x, cs_c64* grad_y, float*
   for (int seg = g->nseg - 1; seg >= 0 && st == CS_OK; --seg) {
     const int L = std::min(g->every, g->iters - seg * g->every);
     if (seg != g->taped_seg) {
-      CK(launch_copy(g->ck[(size_t)seg * 4 + 0], p->s2, n, s));
-      CK(launch_copy(g->ck[(size_t)seg * 4 + 1], p->s0, n, s));
-      CK(launch_copy(g->ck[(size_t)seg * 4 + 2], p->s1, n, s));
+      CK(launch_copy_multi(CopyPairs{{g->ck[(size_t)seg * 4 + 0], g->ck[(size_t)seg * 4 + 1],
+                                      g->ck[(size_t)seg * 4 + 2]}, {p->s2, p->s0, p->s1}, 3}, n, s));
       CK(dft_segment_tape(g, L, lambda, mu, seg > 0, s));
     }
     g->taped_seg = -1;  // the tape now holds (or will hold) another segment
@@ -269,9 +285,8 @@ int cs_admm_forward_ckpt(cs_grad* g, const cs_c64* y, float lambda, float mu, cs
     CK(launch_fill(p->s1, n, zero, s));
     g->taped_seg = -1;
     for (int seg = 0; seg < g->nseg && st == CS_OK; ++seg) {
-      CK(launch_copy(p->s2, g->ck[(size_t)seg * 4 + 0], n, s));
-      CK(launch_copy(p->s0, g->ck[(size_t)seg * 4 + 1], n, s));
-      CK(launch_copy(p->s1, g->ck[(size_t)seg * 4 + 2], n, s));
+      CK(launch_copy_multi(CopyPairs{{p->s2, p->s0, p->s1}, {g->ck[(size_t)seg * 4 + 0], g->ck[(size_t)seg * 4 + 1],
+                                                             g->ck[(size_t)seg * 4 + 2]}, 3}, n, s));
       const int L = std::min(g->every, g->iters - seg * g->every);
       if (seg + 1 < g->nseg) {
         CK(run_iterations_cont(p, L, lambda, mu, seg > 0, s));
@@ -287,14 +302,15 @@ int cs_admm_forward_ckpt(cs_grad* g, const cs_c64* y, float lambda, float mu, cs
     g->ready = true;
     return CS_OK;
   }
-  CK(launch_copy(p->hy, p->s0, n, s));  // m = x
-  CK(launch_copy(p->hy, p->s2, n, s));  // x = H'y
+  CK(launch_copy_multi(CopyPairs{{p->hy, p->hy}, {p->s0, p->s2}, 2}, n, s));  // m = x = H'y
   CK(launch_fill(p->s1, n, zero, s));
   CK(launch_fill(p->s3, n, zero, s));
   float2* state[4] = {p->s0, p->s1, p->s2, p->s3};
   g->taped_seg = -1;
   for (int seg = 0; seg < g->nseg && st == CS_OK; ++seg) {
-    for (int a = 0; a < 4; ++a) CK(launch_copy(state[a], g->ck[(size_t)seg * 4 + a], n, s));
+    CK(launch_copy_multi(CopyPairs{{state[0], state[1], state[2], state[3]},
+                                   {g->ck[(size_t)seg * 4 + 0], g->ck[(size_t)seg * 4 + 1], g->ck[(size_t)seg * 4 + 2],
+                                    g->ck[(size_t)seg * 4 + 3]}, 4}, n, s));
     const int L = std::min(g->every, g->iters - seg * g->every);
     if (seg + 1 < g->nseg) {
       CK(run_iterations(p, L, lambda, mu, nullptr, nullptr, s));
@@ -302,12 +318,7 @@ int cs_admm_forward_ckpt(cs_grad* g, const cs_c64* y, float lambda, float mu, cs
       // the last segment is the first one the backward sweeps: keep its tape
       // now, so that the backward need not recompute it (with ckpt_every >= K
       // nothing is recomputed at all)
-      for (int j = 0; j < L; ++j) {
-        CK(launch_copy(p->s0, g->tm[j], n, s));
-        CK(launch_copy(p->s1, g->td1[j], n, s));
-        CK(one_iteration(p, lambda, mu, s));
-        CK(launch_copy(p->s3, g->td2[j + 1], n, s));
-      }
+      CK(tv_segment_tape(g, L, lambda, mu, s));
       if (st == CS_OK) g->taped_seg = seg;
     }
   }
@@ -351,13 +362,10 @@ int cs_admm_backward(cs_grad* g, const cs_c64* grad_x, cs_c64* grad_y, float* gr
   for (int seg = g->nseg - 1; seg >= 0 && st == CS_OK; --seg) {
     const int L = std::min(g->every, g->iters - seg * g->every);
     if (seg != g->taped_seg) {
-      for (int a = 0; a < 4; ++a) CK(launch_copy(g->ck[(size_t)seg * 4 + a], state[a], n, s));
-      for (int j = 0; j < L; ++j) {  // recompute the segment, keeping what the adjoint needs
-        CK(launch_copy(p->s0, g->tm[j], n, s));
-        CK(launch_copy(p->s1, g->td1[j], n, s));
-        CK(one_iteration(p, lambda, mu, s));
-        CK(launch_copy(p->s3, g->td2[j + 1], n, s));
-      }
+      CK(launch_copy_multi(CopyPairs{{g->ck[(size_t)seg * 4 + 0], g->ck[(size_t)seg * 4 + 1],
+                                      g->ck[(size_t)seg * 4 + 2], g->ck[(size_t)seg * 4 + 3]},
+                                     {state[0], state[1], state[2], state[3]}, 4}, n, s));
+      CK(tv_segment_tape(g, L, lambda, mu, s));  // recompute the segment, keeping what the adjoint needs
     }
     g->taped_seg = -1;  // the tape now holds (or will hold) another segment
     for (int j = L - 1; j >= 0 && st == CS_OK; --j) {

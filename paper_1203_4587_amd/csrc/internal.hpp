@@ -250,6 +250,14 @@ int launch_frame_forward(cs_plan* p, const float2* x, float2* w, hipStream_t s);
 int launch_frame_adjoint(cs_plan* p, const float2* w, float2* x, hipStream_t s);
 int launch_fill(float2* ptr, size_t n, float2 v, hipStream_t s);
 int launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s);
+constexpr int kCopyMax = 4;
+struct CopyPairs {
+  const float2* src[kCopyMax];
+  float2* dst[kCopyMax];
+  int count;
+};
+// the copies of `c` (n values each, disjoint) in one launch
+int launch_copy_multi(const CopyPairs& c, size_t n, hipStream_t s);
 // all iterations in one launch, one workgroup per readout column (even nv)
 bool column_solve_supported(const cs_plan* p);
 int launch_column_solve(cs_plan* p, int iters, float lambda, float mu, const float2* wgiven, hipStream_t s);

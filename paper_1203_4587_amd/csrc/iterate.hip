@@ -1209,6 +1209,38 @@ __global__ void k_copy(const float2* __restrict__ src, float2* __restrict__ dst,
     dst[q] = src[q];
 }
 
+// up to kCopyMax independent copies of n values each in one launch (no
+// destination may overlap a source); 16-byte accesses when every pointer is
+// 16-byte aligned and n is even
+__global__ void k_copy_multi(CopyPairs c, size_t n, int vec) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t first = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (vec) {
+    const size_t n4 = n / 2;
+    for (int a = 0; a < c.count; ++a) {
+      const float4* src = reinterpret_cast<const float4*>(c.src[a]);
+      float4* dst = reinterpret_cast<float4*>(c.dst[a]);
+      for (size_t q = first; q < n4; q += stride) dst[q] = src[q];
+    }
+  } else {
+    for (int a = 0; a < c.count; ++a)
+      for (size_t q = first; q < n; q += stride) c.dst[a][q] = c.src[a][q];
+  }
+}
+
+int launch_copy_multi(const CopyPairs& c, size_t n, hipStream_t s) {
+  if (n == 0 || c.count == 0) return CS_OK;
+  bool aligned = (n % 2) == 0;
+  for (int a = 0; a < c.count; ++a)
+    aligned = aligned && (reinterpret_cast<uintptr_t>(c.src[a]) % 16 == 0) &&
+              (reinterpret_cast<uintptr_t>(c.dst[a]) % 16 == 0);
+  const size_t units = aligned ? n / 2 : n;
+  const unsigned blocks = (unsigned)std::min<size_t>((units + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_copy_multi, dim3(blocks), dim3(256), 0, s, c, n, aligned ? 1 : 0);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
 int launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s) {
   if (n == 0) return CS_OK;
   const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
