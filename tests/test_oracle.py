@@ -210,12 +210,12 @@ def test_tdiff_adjoint(rng):
 
 
 def test_tdiff_matches_paper_matrix():
-    nt = 5
-    Dm = np.zeros((nt - 1, nt))
-    for r in range(nt - 1):
-        Dm[r, r], Dm[r, r + 1] = -1, 1
-    X = np.eye(nt)
-    np.testing.assert_array_equal(O.tdiff(X), Dm)
+    """tdiff applied to the identity reproduces the printed D_t (eq. TV),
+    stored as a fixture for n_t = 5."""
+    import os
+    Dm = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "temporal_difference_nt5.txt"))
+    nt = Dm.shape[1]
+    np.testing.assert_array_equal(O.tdiff(np.eye(nt)), Dm)
 
 
 @pytest.mark.parametrize("nt", [2, 3, 8, 33])
