@@ -192,3 +192,32 @@ def test_full_size_192x192x24_12c_k20_ckpt5_sampled_columns():
     el, em = _rel(float(gs[0]), ref["lam"]), _rel(float(gs[1]), ref["mu"])
     print("192x192x24 K=20: dy", ey, "dlam", el, "dmu", em)
     assert ey < GTOL and el < GTOL and em < GTOL
+
+
+@pytest.mark.parametrize("prior", ["tv", "dft"])
+def test_mu_other_than_the_plans_refactors(prior):
+    """A forward with a mu different from the plan's refactors the plan (as
+    cs_admm_solve does) and gives the image and gradients of a plan built
+    with that mu; with CS_FLAG_NO_REFACTOR the call is refused."""
+    from paper_1203_4587_amd import _lib
+    from paper_1203_4587_amd.api import Plan
+    from paper_1203_4587_amd.autograd import Unrolled
+    fam = "cardiac" if prior == "tv" else "periodic"
+    case = make_case(48, 16, 8, 3, accel=3, ncenter=2, prior=prior, family=fam, seed=91, sigma=0.01)
+    coil, mask, y = case.device()
+    rng = np.random.default_rng(92)
+    g = torch.from_numpy(_rand_c(rng, case.x_true.shape).astype(np.complex64)).cuda()
+    mu2 = 0.25
+    a = Plan(coil, mask, MU, prior=prior, mu_ratio=RHO)
+    ua = Unrolled(a, 6, 3)
+    xa = ua.forward_raw(y, LAM, mu2)
+    gya, gsa = ua.backward_raw(g)
+    b = Plan(coil, mask, mu2, prior=prior, mu_ratio=RHO)
+    ub = Unrolled(b, 6, 3)
+    xb = ub.forward_raw(y, LAM, mu2)
+    gyb, gsb = ub.backward_raw(g)
+    assert torch.equal(xa, xb) and torch.equal(gya, gyb) and torch.equal(gsa, gsb)
+    c = Plan(coil, mask, MU, prior=prior, mu_ratio=RHO, flags=_lib.CS_FLAG_NO_REFACTOR)
+    uc = Unrolled(c, 6, 3)
+    with pytest.raises(_lib.CsmriError, match="mu"):
+        uc.forward_raw(y, LAM, mu2)
