@@ -56,7 +56,7 @@ typedef enum {
   CS_EINVAL = 1,          /* null pointer, size out of range, mu <= 0, lambda < 0, iters < 0 */
   CS_EUNSUPPORTED = 2,    /* size outside the supported set (see above) */
   CS_ENOMEM = 3,          /* the allocator returned NULL */
-  CS_EDEVICE = 4,         /* a HIP runtime error; detail in cs_last_error() */
+  CS_EDEVICE = 4,         /* a HIP runtime or rocSOLVER error; detail in cs_last_error() */
   CS_EMU_MISMATCH = 5,    /* solve asked for another mu and CS_FLAG_NO_REFACTOR is set */
 } cs_status;
 
@@ -82,6 +82,15 @@ enum {
                                         whole waves) solves a block.  With neither XU flag the wave
                                         form is used when nv/2 is a multiple of 64.  All x-update
                                         forms give bit-identical results. */
+  CS_FLAG_EIGEN = 1u << 5,           /* set at cs_plan_create only (cs_plan_set_flags keeps it as it
+                                        is): store every block in the paper's eigen form
+                                        G = U diag(e) U' (Sec. IV-C, eq. eigen_mu; complex64 U, float e,
+                                        from an FP64 eigendecomposition) instead of the packed inverse,
+                                        and apply (mu I + G)^{-1} b = U diag(1/(mu + e)) U' b.  Any mu
+                                        then runs without refactoring (CS_FLAG_NO_REFACTOR has no
+                                        effect), at twice the factor bytes per iteration read twice;
+                                        no column-resident form.  Results agree with the packed
+                                        inverse to rounding, not bit for bit. */
 };
 
 /* Device-memory allocator used for everything the plan owns.  alloc returns

@@ -71,7 +71,7 @@ static void plan_release(cs_plan* p) {
 }
 
 static constexpr uint32_t kAllFlags =
-    CS_FLAG_NO_REFACTOR | CS_FLAG_GRAPH | CS_FLAG_COLUMN_RESIDENT | CS_FLAG_XU_WAVE | CS_FLAG_XU_GROUP;
+    CS_FLAG_NO_REFACTOR | CS_FLAG_GRAPH | CS_FLAG_COLUMN_RESIDENT | CS_FLAG_XU_WAVE | CS_FLAG_XU_GROUP | CS_FLAG_EIGEN;
 
 static int validate_flags(uint32_t f) {
   if (f & ~kAllFlags) return set_error(CS_EINVAL, "unknown flag bits");
@@ -194,13 +194,13 @@ static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, flo
       st = timed_launch(p, kKindTV, s, [&] { return launch_tv_step(p, lambda, mu, s); });
       if (st == CS_OK)
         st = timed_launch(p, kKindX, s,
-                          [&] { return launch_block_solve(p, kSolveTV, p->hy, p->s0, p->s3, p->s2, mu, s); });
+                          [&] { return launch_xupdate(p, kSolveTV, p->hy, p->s0, p->s3, p->s2, mu, s); });
     } else if (p->desc.prior == CS_PRIOR_TEMPORAL_FRAME) {
       // the first pass of a call starts from the w held in img_tmp
       st = timed_launch(p, kKindDFT, s, [&] { return launch_frame_step(p, lambda, mu, k == 0 && !cont, s); });
       if (st == CS_OK)
         st = timed_launch(p, kKindX, s,
-                          [&] { return launch_block_solve(p, kSolveDFT, p->hy, p->s3, nullptr, p->s2, mu, s); });
+                          [&] { return launch_xupdate(p, kSolveDFT, p->hy, p->s3, nullptr, p->s2, mu, s); });
     } else {
       st = timed_launch(p, kKindDFT, s, [&] {
         const bool first = k == 0 && !cont;
@@ -208,7 +208,7 @@ static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, flo
       });
       if (st == CS_OK)
         st = timed_launch(p, kKindX, s,
-                          [&] { return launch_block_solve(p, kSolveDFT, p->hy, p->s3, nullptr, p->s2, mu, s); });
+                          [&] { return launch_xupdate(p, kSolveDFT, p->hy, p->s3, nullptr, p->s2, mu, s); });
     }
     if (st == CS_OK && J_trace)
       st = timed_launch(p, kKindJ, s, [&] { return launch_objective(p, p->s2, lambda, J_trace + k, s); });
@@ -241,7 +241,9 @@ static int solve_setup(cs_plan* p, const cs_c64* y, float mu, const cs_state* st
   const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
   const bool warm = state && state->iter > 0;
   int st = CS_OK;
-  if (mu != p->mu) {
+  if (p->desc.flags & CS_FLAG_EIGEN) {
+    p->mu = mu;  // the eigen form takes mu at apply time
+  } else if (mu != p->mu) {
     if (p->desc.flags & CS_FLAG_NO_REFACTOR) return set_error(CS_EMU_MISMATCH, "mu differs from the plan's mu");
     if ((st = build_factor(p, mu, s)) != CS_OK) return st;
   }
@@ -391,7 +393,15 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
   };
   // the factor is by far the largest buffer; take it before any device work
   p->flayout = make_factor_layout(nv, (size_t)nt * nh);
-  if ((st = plan_alloc(p, &p->factor, factor_elems(p->flayout), "the factor store")) != CS_OK) return fail(st);
+  if (desc->flags & CS_FLAG_EIGEN) {
+    const size_t ublk = (size_t)nt * nh * nv * nv;
+    if ((st = plan_alloc(p, &p->eig_uh, ublk, "the eigenvector store")) != CS_OK ||
+        (st = plan_alloc(p, &p->eig_uc, ublk, "the eigenvector store")) != CS_OK ||
+        (st = plan_alloc(p, &p->eig_e, (size_t)nt * nh * nv, "the eigenvalue store")) != CS_OK)
+      return fail(st);
+  } else if ((st = plan_alloc(p, &p->factor, factor_elems(p->flayout), "the factor store")) != CS_OK) {
+    return fail(st);
+  }
   if (!make_fft_desc(nv, &p->fft_v) || !make_fft_desc(nh, &p->fft_h))
     return fail(set_error(CS_EUNSUPPORTED, "no FFT plan for this size"));
   hipError_t e = hipGetDevice(&p->device);
@@ -543,7 +553,12 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
   // coil maps [c][j][i] -> column-major [c][i][j]
   if ((st = launch_transpose(reinterpret_cast<const float2*>(coil), p->coil_cm, nc, nv, nh, s)) != CS_OK)
     return fail(st);
-  if ((st = build_factor(p, mu, s)) != CS_OK) return fail(st);
+  if (desc->flags & CS_FLAG_EIGEN) {
+    if ((st = build_factor_eigen(p, s)) != CS_OK) return fail(st);
+    p->mu = mu;
+  } else if ((st = build_factor(p, mu, s)) != CS_OK) {
+    return fail(st);
+  }
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(hip_fail(e, "hipStreamSynchronize(plan)"));
   *out = p;
@@ -622,7 +637,7 @@ int cs_apply_block_inverse(cs_plan* p, const cs_c64* b, cs_c64* x, cs_stream str
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
   hipStream_t s = S(stream);
   int st = launch_transpose(reinterpret_cast<const float2*>(b), p->img_tmp, nt, nv, nh, s);
-  if (st == CS_OK) st = launch_block_solve(p, kSolvePlain, p->img_tmp, nullptr, nullptr, p->img_tmp, p->mu, s);
+  if (st == CS_OK) st = launch_xupdate(p, kSolvePlain, p->img_tmp, nullptr, nullptr, p->img_tmp, p->mu, s);
   if (st == CS_OK) st = launch_transpose(p->img_tmp, reinterpret_cast<float2*>(x), nt, nh, nv, s);
   return st;
 }
@@ -733,7 +748,8 @@ int cs_plan_set_flags(cs_plan* p, uint32_t flags) {
   int st = validate_flags(flags);
   if (st != CS_OK) return st;
   CS_HIP(hipSetDevice(p->device));
-  set_plan_flags(p, flags);
+  // the factor's form is fixed when the plan is built
+  set_plan_flags(p, (flags & ~(uint32_t)CS_FLAG_EIGEN) | (p->desc.flags & CS_FLAG_EIGEN));
   return CS_OK;
 }
 

@@ -19,6 +19,9 @@
 // and the per-iteration product W b then reads them as contiguous runs.
 #include "internal.hpp"
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 namespace csmri {
 
 // ws block (column-major, A(r, c) at c * nv + r) = mu I + G_{i,t}
@@ -238,6 +241,92 @@ int build_factor(cs_plan* p, float mu, hipStream_t s) {
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(factor)");
   p->mu = mu;
   return CS_OK;
+}
+
+// ---------------------------------------------------------------- eigen form
+//
+// The paper's own factor (Sec. IV-C, eq. eigen_mu): G_{i,t} = U diag(e) U'
+// once per plan, after which (mu I + G)^{-1} b = U diag(1/(mu + e)) U' b for
+// any mu.  G is assembled in FP64 as above (mu = 0) and decomposed by the
+// batched Hermitian divide-and-conquer eigensolver of rocSOLVER (ascending
+// e, orthonormal eigenvectors in the columns).  Stored per block, in
+// complex64 / float:
+//   uh[j][k] = conj(U[j, k])  (row j of U, conjugated: the U' b pass reads a
+//                              contiguous row per right-hand-side value)
+//   uc[k][j] = U[j, k]        (column k of U: the U s pass reads a
+//                              contiguous column per coefficient)
+//   e[k]
+// so both passes of the apply stream their n x n values front to back.
+
+__global__ void k_pack_eigen(const double2* __restrict__ ws, const double* __restrict__ ev,
+                             float2* __restrict__ uh, float2* __restrict__ uc, float* __restrict__ eo, int n,
+                             int blk0) {
+  const int k = blockIdx.y;  // eigenvector
+  const int j = threadIdx.x;
+  if (j >= n) return;
+  const size_t nn = (size_t)n * n;
+  const size_t blk = (size_t)blk0 + blockIdx.x;
+  const double2 u = ws[(size_t)blockIdx.x * nn + (size_t)k * n + j];
+  uc[blk * nn + (size_t)k * n + j] = make_float2((float)u.x, (float)u.y);
+  uh[blk * nn + (size_t)j * n + k] = make_float2((float)u.x, (float)-u.y);
+  if (j == 0) eo[blk * n + k] = (float)ev[(size_t)blockIdx.x * n + k];
+}
+
+static int rocsolver_fail(rocblas_status r, const char* what) {
+  return set_error(CS_EDEVICE, std::string(what) + ": " + rocblas_status_to_string(r));
+}
+
+int build_factor_eigen(cs_plan* p, hipStream_t s) {
+  const int n = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
+  const size_t nblocks = (size_t)nt * nh;
+  const size_t nn = (size_t)n * n;
+  // per block: the matrix (overwritten by U), e, the tridiagonal off-diagonal, info
+  const size_t blk_bytes = nn * sizeof(double2) + 2 * (size_t)n * sizeof(double) + sizeof(rocblas_int);
+  const size_t ws_limit = (size_t)1 << 30;
+  const size_t chunk = std::max<size_t>(1, std::min(nblocks, ws_limit / blk_bytes));
+  double2* ws = static_cast<double2*>(p->alloc.get(chunk * nn * sizeof(double2)));
+  double* dv = static_cast<double*>(p->alloc.get(chunk * 2 * (size_t)n * sizeof(double)));
+  rocblas_int* info = static_cast<rocblas_int*>(p->alloc.get(std::max<size_t>(chunk * sizeof(rocblas_int), 256)));
+  rocblas_handle h = nullptr;
+  auto done = [&](int status) {
+    if (h) (void)rocblas_destroy_handle(h);
+    if (ws) p->alloc.put(ws);
+    if (dv) p->alloc.put(dv);
+    if (info) p->alloc.put(info);
+    return status;
+  };
+  if (!ws || !dv || !info) return done(set_error(CS_ENOMEM, "allocator returned NULL for the eigensolver workspace"));
+  rocblas_status r = rocblas_create_handle(&h);
+  if (r != rocblas_status_success) {
+    h = nullptr;
+    return done(rocsolver_fail(r, "rocblas_create_handle"));
+  }
+  if ((r = rocblas_set_stream(h, s)) != rocblas_status_success) return done(rocsolver_fail(r, "rocblas_set_stream"));
+  const int wg = round_up(n, 64);
+  std::vector<rocblas_int> hinfo(chunk);
+  for (size_t b0 = 0; b0 < nblocks; b0 += chunk) {
+    const int nblk = (int)std::min(chunk, nblocks - b0);
+    double* ev = dv;
+    double* offd = dv + (size_t)chunk * n;
+    hipLaunchKernelGGL(k_gram_assemble, dim3(nblk), dim3(wg), (size_t)16 * n * sizeof(float2), s, ws, p->coil_cm,
+                       p->pcol, n, nh, nc, (int)b0, 0.0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return done(hip_fail(e, "k_gram_assemble"));
+    r = rocsolver_zheevd_strided_batched(h, rocblas_evect_original, rocblas_fill_lower, n,
+                                         reinterpret_cast<rocblas_double_complex*>(ws), n, (rocblas_stride)nn, ev,
+                                         n, offd, n, info, nblk);
+    if (r != rocblas_status_success) return done(rocsolver_fail(r, "rocsolver_zheevd_strided_batched"));
+    hipLaunchKernelGGL(k_pack_eigen, dim3(nblk, n), dim3(wg), 0, s, ws, ev, p->eig_uh, p->eig_uc, p->eig_e, n,
+                       (int)b0);
+    if ((e = hipGetLastError()) != hipSuccess) return done(hip_fail(e, "k_pack_eigen"));
+    if ((e = hipMemcpyAsync(hinfo.data(), info, nblk * sizeof(rocblas_int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return done(hip_fail(e, "eigensolver status copy"));
+    for (int b = 0; b < nblk; ++b)
+      if (hinfo[b] != 0)
+        return done(set_error(CS_EDEVICE, "the eigensolver did not converge for block " + std::to_string(b0 + b)));
+  }
+  return done(CS_OK);
 }
 
 }  // namespace csmri

@@ -143,6 +143,10 @@ static int dft_segment_tape(cs_grad* g, int L, float lambda, float mu, bool cont
 }
 
 static int ensure_mu(cs_plan* p, float mu, hipStream_t s) {
+  if (p->desc.flags & CS_FLAG_EIGEN) {
+    p->mu = mu;  // the eigen form takes mu at apply time
+    return CS_OK;
+  }
   if (mu == p->mu) return CS_OK;
   if (p->desc.flags & CS_FLAG_NO_REFACTOR) return set_error(CS_EMU_MISMATCH, "mu differs from the plan's mu");
   return build_factor(p, mu, s);
@@ -178,7 +182,7 @@ static int dft_backward(cs_grad* g, const cs_c64* grad_x, cs_c64* grad_y, float*
     }
     g->taped_seg = -1;  // the tape now holds (or will hold) another segment
     for (int j = L - 1; j >= 0 && st == CS_OK; --j) {
-      CK(launch_block_solve(p, kSolvePlain, zb, nullptr, nullptr, g->bb, mu, s));  // bb = W zb
+      CK(launch_xupdate(p, kSolvePlain, zb, nullptr, nullptr, g->bb, mu, s));  // bb = W zb
       const int last = (seg == 0 && j == 0) ? 1 : 0;
       CK(launch_dft_adjoint(p, (unsigned)g->nslots, g->bb, db, zb, g->hyb, g->tm[j], g->td1[j], g->td2[j],
                             g->tm[j + 1], g->partial, tau, mu, last, s));
@@ -369,7 +373,7 @@ int cs_admm_backward(cs_grad* g, const cs_c64* grad_x, cs_c64* grad_y, float* gr
     }
     g->taped_seg = -1;  // the tape now holds (or will hold) another segment
     for (int j = L - 1; j >= 0 && st == CS_OK; --j) {
-      CK(launch_block_solve(p, kSolvePlain, g->e, nullptr, nullptr, g->bb, mu, s));  // bb = W e
+      CK(launch_xupdate(p, kSolvePlain, g->e, nullptr, nullptr, g->bb, mu, s));  // bb = W e
       if (st != CS_OK) break;
       const int last = (seg == 0 && j == 0) ? 1 : 0;
       CK(launch_tv_adjoint(p, blocks, g->mb, g->d1b, g->d2b, g->e, g->bb, g->hyb, g->tm[j], g->td1[j],

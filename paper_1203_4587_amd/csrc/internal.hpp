@@ -168,7 +168,10 @@ struct cs_plan {
   float2* coil_cm = nullptr;
 
   // factor: nt*nh blocks (t, i), block index t*nh + i, layout csmri::FactorLayout
-  float2* factor = nullptr;
+  float2* factor = nullptr;     // packed inverses (not allocated with CS_FLAG_EIGEN)
+  float2* eig_uh = nullptr;     // CS_FLAG_EIGEN: [block][j][k] conj(U[j, k]) (rows of U, conjugated)
+  float2* eig_uc = nullptr;     // CS_FLAG_EIGEN: [block][k][j] U[j, k] (columns of U)
+  float* eig_e = nullptr;       // CS_FLAG_EIGEN: [block][k] eigenvalue k of G (mu not included)
   csmri::FactorLayout flayout{};
 
   // workspaces (solver layout [t][i][j], i.e. column-contiguous)
@@ -204,6 +207,7 @@ namespace csmri {
 
 // sense.hip
 int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipStream_t s);
+int build_factor_eigen(cs_plan* p, hipStream_t s);  // CS_FLAG_EIGEN plans: U and e of every block
 // reverse step of one Algorithm 1 iteration (temporal DFT prior): see iterate.hip
 // reverse step of one Algorithm 2 iteration (temporal TV prior), after bb = W e: see iterate.hip
 int launch_tv_adjoint(cs_plan* p, unsigned nblocks, float2* mb, float2* d1b, float2* d2b, float2* e,
@@ -228,6 +232,10 @@ int fft_rows_per_group(const cs_plan* p);
 int build_factor(cs_plan* p, float mu, hipStream_t s);
 
 // iterate.hip
+// the x-update of every block in the plan's form: the packed inverse
+// (launch_block_solve), or U diag(1/(mu + e)) U' for CS_FLAG_EIGEN plans
+int launch_xupdate(cs_plan* p, int mode, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
+                   hipStream_t s);
 int launch_block_solve(cs_plan* p, int mode, const float2* hy, const float2* m, float2* d2,
                        float2* x, float mu, hipStream_t s);
 int launch_tv_step(cs_plan* p, float lambda, float mu, hipStream_t s);

@@ -1136,7 +1136,7 @@ static int column_launch(cs_plan* p, const ColumnSolveArgs& a, int threads, size
 }
 
 bool column_solve_supported(const cs_plan* p) {
-  return (p->desc.nv & 1) == 0 && p->desc.prior != CS_PRIOR_TEMPORAL_FRAME;
+  return (p->desc.nv & 1) == 0 && p->desc.prior != CS_PRIOR_TEMPORAL_FRAME && !(p->desc.flags & CS_FLAG_EIGEN);
 }
 
 int launch_column_solve(cs_plan* p, int iters, float lambda, float mu, const float2* wgiven, hipStream_t s) {
@@ -1742,5 +1742,127 @@ int launch_objective(cs_plan* p, const float2* x, float lambda, float* out, hipS
 }
 
 int objective_partial_count() { return 2 * kJBlocks; }
+
+// ---------------------------------------------------------------- x-update, eigen form
+//
+// The paper's form of the exact x-update (Sec. IV-C, eq. eigen_mu): with
+// G = U diag(e) U' stored per block, x = U diag(1/(mu + e)) U' b, for the
+// same right-hand sides and fused dual update as the packed-inverse forms.
+// One wave per block; lane l owns indices l + 64 r, r < R.
+//   pass 1: t_k = sum_j conj(U[j, k]) b_j   (row j of U, conjugated, is the
+//           contiguous uh[j][.]; b_j is broadcast from wave-private LDS)
+//   s_k = t_k / (mu + e_k)
+//   pass 2: x_j = sum_k U[j, k] s_k          (column k read as uc[k][.])
+// Neither pass needs a cross-lane reduction; each reads its n x n values
+// once, front to back, so a launch streams 2 n^2 complex64 values per block
+// (four times the packed inverse's n (n + 1) / 2).
+
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2 ld_stream2(const float2* p) {
+  const v2f v = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(p));
+  return make_float2(v.x, v.y);
+}
+
+// acc[r] += sum_j M[j][lane + 64 r] v_j for an n x n row-major M, v in LDS.
+// JC rows are loaded before any is used, so each lane keeps JC * R loads in
+// flight.
+template <int R>
+__device__ __forceinline__ void stream_matvec(const float2* __restrict__ M, const float2* v, int n, int lane,
+                                              float2 (&acc)[R]) {
+  constexpr int JC = R >= 8 ? 2 : 16 / R;
+  for (int j0 = 0; j0 < n; j0 += JC) {
+    float2 c[JC][R];
+#pragma unroll
+    for (int u = 0; u < JC; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int k = lane + 64 * r;
+        c[u][r] = (k < n && j0 + u < n) ? ld_stream2(M + (size_t)(j0 + u) * n + k) : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+    for (int u = 0; u < JC; ++u) {
+      if (j0 + u < n) {
+        const float2 vj = v[j0 + u];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = cfma(c[u][r], vj, acc[r]);
+      }
+    }
+  }
+}
+
+template <int MODE, int R>
+__global__ __launch_bounds__(64) void k_xupdate_eigen(const float2* __restrict__ uh, const float2* __restrict__ uc,
+                                                      const float* __restrict__ ev, int n, ColRange cr,
+                                                      const float2* hy, const float2* __restrict__ m,
+                                                      float2* __restrict__ d2, float2* x, float mu) {
+  extern __shared__ float2 lds[];
+  float2* bsh = lds;      // [n] right-hand side
+  float2* ssh = lds + n;  // [n] scaled coefficients s
+  const int lane = threadIdx.x;
+  const size_t blk = range_block(cr, blockIdx.x);
+  const size_t base = blk * (size_t)n;
+  const size_t nn = (size_t)n * n;
+  float2 mk[R], dk[R], acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = lane + 64 * r;
+    mk[r] = dk[r] = acc[r] = make_float2(0.f, 0.f);
+    if (j < n) bsh[j] = rhs_value<MODE>(hy, m, d2, base + j, mu, mk[r], dk[r]);
+  }
+  __builtin_amdgcn_wave_barrier();
+  stream_matvec<R>(uh + blk * nn, bsh, n, lane, acc);  // t = U' b
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int k = lane + 64 * r;
+    if (k < n) {
+      const float inv = 1.0f / (mu + ev[blk * n + k]);
+      ssh[k] = make_float2(acc[r].x * inv, acc[r].y * inv);
+    }
+    acc[r] = make_float2(0.f, 0.f);
+  }
+  __builtin_amdgcn_wave_barrier();
+  stream_matvec<R>(uc + blk * nn, ssh, n, lane, acc);  // x = U s
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = lane + 64 * r;
+    if (j < n) {
+      x[base + j] = acc[r];
+      if (MODE == kSolveTV) d2[base + j] = make_float2(dk[r].x - (mk[r].x - acc[r].x), dk[r].y - (mk[r].y - acc[r].y));
+    }
+  }
+}
+
+template <int MODE, int R>
+static void eigen_launch_r(cs_plan* p, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
+                           hipStream_t s) {
+  const int n = p->desc.nv, nh = p->desc.nh;
+  const ColRange cr{0, nh, nh};
+  const unsigned grid = (unsigned)nh * (unsigned)p->desc.nt;
+  hipLaunchKernelGGL((k_xupdate_eigen<MODE, R>), dim3(grid), dim3(64), 2 * (size_t)n * sizeof(float2), s, p->eig_uh,
+                     p->eig_uc, p->eig_e, n, cr, hy, m, d2, x, mu);
+}
+
+template <int MODE>
+static void eigen_launch(cs_plan* p, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
+                         hipStream_t s) {
+  const int r = (p->desc.nv + 63) / 64;  // nv <= 512
+  if (r == 1) eigen_launch_r<MODE, 1>(p, hy, m, d2, x, mu, s);
+  else if (r == 2) eigen_launch_r<MODE, 2>(p, hy, m, d2, x, mu, s);
+  else if (r == 3) eigen_launch_r<MODE, 3>(p, hy, m, d2, x, mu, s);
+  else if (r == 4) eigen_launch_r<MODE, 4>(p, hy, m, d2, x, mu, s);
+  else if (r <= 6) eigen_launch_r<MODE, 6>(p, hy, m, d2, x, mu, s);
+  else eigen_launch_r<MODE, 8>(p, hy, m, d2, x, mu, s);
+}
+
+int launch_xupdate(cs_plan* p, int mode, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
+                   hipStream_t s) {
+  if (!(p->desc.flags & CS_FLAG_EIGEN)) return launch_block_solve(p, mode, hy, m, d2, x, mu, s);
+  if (mode == kSolveTV) eigen_launch<kSolveTV>(p, hy, m, d2, x, mu, s);
+  else if (mode == kSolveDFT) eigen_launch<kSolveDFT>(p, hy, m, d2, x, mu, s);
+  else eigen_launch<kSolvePlain>(p, hy, m, d2, x, mu, s);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
 
 }  // namespace csmri
