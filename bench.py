@@ -333,6 +333,63 @@ def step_rows(plan, problem, y, t_plan: float, prior: str) -> dict:
     return rows
 
 
+def eigen_form(plan, problem, coil, mask, y, prior: str, steps: int) -> dict:
+    """The paper's own factor form (CS_FLAG_EIGEN: U diag(1/(mu + e)) U' per
+    block) on the same workload: plan build, x-update rate against HBM peak,
+    iteration rate, and what it saves, a refactor of the packed inverse when
+    mu changes, expressed as the iterations per mu value below which it wins."""
+    import torch
+    from paper_1203_4587_amd import _lib
+    from paper_1203_4587_amd.api import Plan
+    nt, nv, nh = problem.x_true.shape
+    lam, mu = problem.lam, problem.mu
+
+    def clock(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    out = {}
+    t0 = time.perf_counter()
+    eig = Plan(coil, mask, mu, prior=prior, mu_ratio=problem.rho, flags=_lib.CS_FLAG_EIGEN)
+    torch.cuda.synchronize()
+    out["plan_s"] = round(time.perf_counter() - t0, 3)
+    eig.solve(y, lam, 5)
+    eig_s = clock(lambda: eig.solve(y, lam, steps))
+    eig.kernel_timing(True)
+    eig.solve(y, lam, steps)
+    torch.cuda.synchronize()
+    xl, xms = eig.kernel_times().get("x_update", (0, 0.0))
+    eig.kernel_timing(False)
+    # per block: U' and U (n^2 complex64 each), e (n float); plus the right-hand
+    # side and output traffic of the packed form's x-update
+    nblk = nt * nh
+    img = 8 * nv * nh * nt
+    rhs = (5 if prior == "tv" else 3) * img
+    alg = nblk * (2 * 8 * nv * nv + 4 * nv) + rhs
+    us = xms / max(xl, 1) * 1e3
+    gbs = alg / (us * 1e-6) / 1e9 if xl else None
+    out.update({"iter_per_s": round(steps / eig_s, 2), "x_update_us": round(us, 2),
+                "x_update_algorithmic_bytes": alg,
+                "x_update_GBps": round(gbs, 1) if gbs else None,
+                "x_update_hbm_frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None,
+                "plan_bytes": int(eig.nbytes)})
+    # a mu change on the eigen plan costs nothing; on the packed plan it refactors
+    eig_mu = clock(lambda: eig.solve(y, lam, steps, mu=mu * 1.5))
+    eig.close()
+    torch.cuda.empty_cache()
+    packed_s = clock(lambda: plan.solve(y, lam, steps))
+    refactor_s = clock(lambda: plan.solve(y, lam, 0, mu=mu * 1.5)) - clock(lambda: plan.solve(y, lam, 0, mu=mu * 1.5))
+    plan.solve(y, lam, 0, mu=mu)  # back to the plan's mu (refactors again)
+    torch.cuda.synchronize()
+    per_iter_extra = (eig_s - packed_s) / steps
+    out.update({"solve_at_new_mu_s": round(eig_mu, 5), "packed_refactor_s": round(refactor_s, 5),
+                "breakeven_iterations_per_mu": round(refactor_s / per_iter_extra, 1) if per_iter_extra > 0 else None})
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +407,7 @@ def main() -> int:
     ap.add_argument("--no-unrolled", action="store_true", help="skip the differentiated-solve measurement")
     ap.add_argument("--unrolled-reps", type=int, default=10, help="timed forward+backward passes")
     ap.add_argument("--no-tune", action="store_true", help="time the default form instead of the tuned one")
+    ap.add_argument("--no-eigen", action="store_true", help="skip the eigen-form (any-mu) factor measurement")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the per-step figures (SENSE passes, plan, objective monitor)")
     ap.add_argument("--xu-form", choices=["wave", "group"], default=None,
@@ -538,6 +596,9 @@ def main() -> int:
         t_delta = time.perf_counter() - t2
         line["to_delta"] = {"tol": 1e-3, "check_every": 5, "iterations": k_done, "delta": d_last,
                             "seconds": round(t_delta, 5), "iter_per_s": round(k_done / t_delta, 2)}
+    if not args.no_eigen and not args.column_resident:
+        log("eigen-form factor ...")
+        line["eigen"] = eigen_form(plan, problem, coil, mask, y, wl["prior"], args.steps)
     plan.close()
     del x, y
     torch.cuda.empty_cache()

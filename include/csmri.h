@@ -88,9 +88,13 @@ enum {
                                         from an FP64 eigendecomposition) instead of the packed inverse,
                                         and apply (mu I + G)^{-1} b = U diag(1/(mu + e)) U' b.  Any mu
                                         then runs without refactoring (CS_FLAG_NO_REFACTOR has no
-                                        effect), at twice the factor bytes per iteration read twice;
-                                        no column-resident form.  Results agree with the packed
-                                        inverse to rounding, not bit for bit. */
+                                        effect).  U is kept twice (conjugated rows and columns, so
+                                        both products stream it), which is 4x the packed inverse's
+                                        memory and HBM bytes per x-update; the execution-form flags
+                                        (COLUMN_RESIDENT, XU_WAVE, XU_GROUP) have no effect.  Results
+                                        agree with the packed inverse to rounding, not bit for bit.
+                                        The eigendecomposition is rocSOLVER's batched zheevd, on the
+                                        plan's stream; its failure is CS_EDEVICE. */
 };
 
 /* Device-memory allocator used for everything the plan owns.  alloc returns

@@ -1791,6 +1791,37 @@ __device__ __forceinline__ void stream_matvec(const float2* __restrict__ M, cons
   }
 }
 
+// Even n: the same product with lane l owning the index pairs (2q, 2q+1),
+// q = l + 64 r, r < RP, one 16-byte load per pair and row.
+template <int RP>
+__device__ __forceinline__ void stream_matvec2(const float2* __restrict__ M, const float2* v, int n, int lane,
+                                               float2 (&a0)[RP], float2 (&a1)[RP]) {
+  constexpr int JC = RP >= 4 ? 4 : (RP == 3 ? 5 : 16 / RP);
+  const int h = n >> 1;
+  for (int j0 = 0; j0 < n; j0 += JC) {
+    float4 c[JC][RP];
+#pragma unroll
+    for (int u = 0; u < JC; ++u)
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        const int q = lane + 64 * r;
+        c[u][r] = (q < h && j0 + u < n) ? ld_stream4(M + (size_t)(j0 + u) * n + 2 * q)
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+    for (int u = 0; u < JC; ++u) {
+      if (j0 + u < n) {
+        const float2 vj = v[j0 + u];
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+          a0[r] = cfma(make_float2(c[u][r].x, c[u][r].y), vj, a0[r]);
+          a1[r] = cfma(make_float2(c[u][r].z, c[u][r].w), vj, a1[r]);
+        }
+      }
+    }
+  }
+}
+
 template <int MODE, int R>
 __global__ __launch_bounds__(64) void k_xupdate_eigen(const float2* __restrict__ uh, const float2* __restrict__ uc,
                                                       const float* __restrict__ ev, int n, ColRange cr,
@@ -1833,6 +1864,66 @@ __global__ __launch_bounds__(64) void k_xupdate_eigen(const float2* __restrict__
   }
 }
 
+template <int MODE, int RP>
+__global__ __launch_bounds__(64) void k_xupdate_eigen2(const float2* __restrict__ uh, const float2* __restrict__ uc,
+                                                       const float* __restrict__ ev, int n, ColRange cr,
+                                                       const float2* hy, const float2* __restrict__ m,
+                                                       float2* __restrict__ d2, float2* x, float mu) {
+  extern __shared__ float2 lds[];
+  float2* bsh = lds;      // [n] right-hand side
+  float2* ssh = lds + n;  // [n] scaled coefficients s
+  const int lane = threadIdx.x;
+  const int h = n >> 1;
+  const size_t blk = range_block(cr, blockIdx.x);
+  const size_t base = blk * (size_t)n;
+  const size_t nn = (size_t)n * n;
+  float2 m0[RP], m1[RP], e0[RP], e1[RP], a0[RP], a1[RP];
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int q = lane + 64 * r;
+    m0[r] = m1[r] = e0[r] = e1[r] = a0[r] = a1[r] = make_float2(0.f, 0.f);
+    if (q < h) {
+      bsh[2 * q] = rhs_value<MODE>(hy, m, d2, base + 2 * q, mu, m0[r], e0[r]);
+      bsh[2 * q + 1] = rhs_value<MODE>(hy, m, d2, base + 2 * q + 1, mu, m1[r], e1[r]);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  stream_matvec2<RP>(uh + blk * nn, bsh, n, lane, a0, a1);  // t = U' b
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int q = lane + 64 * r;
+    if (q < h) {
+      const float i0 = 1.0f / (mu + ev[blk * n + 2 * q]), i1 = 1.0f / (mu + ev[blk * n + 2 * q + 1]);
+      ssh[2 * q] = make_float2(a0[r].x * i0, a0[r].y * i0);
+      ssh[2 * q + 1] = make_float2(a1[r].x * i1, a1[r].y * i1);
+    }
+    a0[r] = a1[r] = make_float2(0.f, 0.f);
+  }
+  __builtin_amdgcn_wave_barrier();
+  stream_matvec2<RP>(uc + blk * nn, ssh, n, lane, a0, a1);  // x = U s
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int q = lane + 64 * r;
+    if (q < h) {
+      *reinterpret_cast<float4*>(x + base + 2 * q) = make_float4(a0[r].x, a0[r].y, a1[r].x, a1[r].y);
+      if (MODE == kSolveTV)
+        *reinterpret_cast<float4*>(d2 + base + 2 * q) =
+            make_float4(e0[r].x - (m0[r].x - a0[r].x), e0[r].y - (m0[r].y - a0[r].y),
+                        e1[r].x - (m1[r].x - a1[r].x), e1[r].y - (m1[r].y - a1[r].y));
+    }
+  }
+}
+
+template <int MODE, int RP>
+static void eigen_launch_p(cs_plan* p, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
+                           hipStream_t s) {
+  const int n = p->desc.nv, nh = p->desc.nh;
+  const ColRange cr{0, nh, nh};
+  const unsigned grid = (unsigned)nh * (unsigned)p->desc.nt;
+  hipLaunchKernelGGL((k_xupdate_eigen2<MODE, RP>), dim3(grid), dim3(64), 2 * (size_t)n * sizeof(float2), s,
+                     p->eig_uh, p->eig_uc, p->eig_e, n, cr, hy, m, d2, x, mu);
+}
+
 template <int MODE, int R>
 static void eigen_launch_r(cs_plan* p, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
                            hipStream_t s) {
@@ -1846,7 +1937,16 @@ static void eigen_launch_r(cs_plan* p, const float2* hy, const float2* m, float2
 template <int MODE>
 static void eigen_launch(cs_plan* p, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
                          hipStream_t s) {
-  const int r = (p->desc.nv + 63) / 64;  // nv <= 512
+  const int n = p->desc.nv;  // <= 512
+  if ((n & 1) == 0) {
+    const int rp = pairs_per_lane(n);
+    if (rp == 1) eigen_launch_p<MODE, 1>(p, hy, m, d2, x, mu, s);
+    else if (rp == 2) eigen_launch_p<MODE, 2>(p, hy, m, d2, x, mu, s);
+    else if (rp == 3) eigen_launch_p<MODE, 3>(p, hy, m, d2, x, mu, s);
+    else eigen_launch_p<MODE, 4>(p, hy, m, d2, x, mu, s);
+    return;
+  }
+  const int r = (n + 63) / 64;
   if (r == 1) eigen_launch_r<MODE, 1>(p, hy, m, d2, x, mu, s);
   else if (r == 2) eigen_launch_r<MODE, 2>(p, hy, m, d2, x, mu, s);
   else if (r == 3) eigen_launch_r<MODE, 3>(p, hy, m, d2, x, mu, s);
