@@ -54,7 +54,16 @@ def kernel_source_sha() -> str:
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-def measured_traffic(kind: str, workload: str, steps: int):
+def eigen_source_sha() -> str:
+    """Fingerprint of the eigen-form x-update kernels: iterate.hip from its
+    eigen-form section to the end of the file."""
+    with open(os.path.join(ROOT, "paper_1203_4587_amd", "csrc", "iterate.hip"), encoding="utf-8") as f:
+        text = f.read()
+    text = text[text.index("// ---------------------------------------------------------------- x-update, eigen form"):]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def measured_traffic(kind: str, workload: str, steps: int, sha_fn=None):
     """HBM bytes per launch of `kind` from the committed rocprofv3 PMC summary
     (profiles/<kind>_<workload>_traffic.json), or None when it is missing or
     was taken on a different kernel source.  The single-launch solve's record
@@ -65,7 +74,7 @@ def measured_traffic(kind: str, workload: str, steps: int):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sha") != kernel_source_sha() or rec.get("workload") != workload:
+    if rec.get("kernel_sha") != (sha_fn or kernel_source_sha)() or rec.get("workload") != workload:
         return None
     if "bytes_per_iteration" in rec:
         return int(rec["bytes_per_iteration"] * steps)
@@ -333,7 +342,7 @@ def step_rows(plan, problem, y, t_plan: float, prior: str) -> dict:
     return rows
 
 
-def eigen_form(plan, problem, coil, mask, y, prior: str, steps: int) -> dict:
+def eigen_form(plan, problem, coil, mask, y, prior: str, steps: int, workload: str) -> dict:
     """The paper's own factor form (CS_FLAG_EIGEN: U diag(1/(mu + e)) U' per
     block) on the same workload: plan build, x-update rate against HBM peak,
     iteration rate, and what it saves, a refactor of the packed inverse when
@@ -375,6 +384,9 @@ def eigen_form(plan, problem, coil, mask, y, prior: str, steps: int) -> dict:
                 "x_update_algorithmic_bytes": alg,
                 "x_update_GBps": round(gbs, 1) if gbs else None,
                 "x_update_hbm_frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None,
+                "x_update_kernel": f"k_xupdate_{'eigen2' if nv % 2 == 0 else 'eigen'}",
+                "x_update_traffic": measured_traffic(f"x_update_{'eigen2' if nv % 2 == 0 else 'eigen'}", workload,
+                                                     1, eigen_source_sha),
                 "plan_bytes": int(eig.nbytes)})
     # a mu change on the eigen plan costs nothing; on the packed plan it refactors
     eig_mu = clock(lambda: eig.solve(y, lam, steps, mu=mu * 1.5))
@@ -598,7 +610,7 @@ def main() -> int:
                             "seconds": round(t_delta, 5), "iter_per_s": round(k_done / t_delta, 2)}
     if not args.no_eigen and not args.column_resident:
         log("eigen-form factor ...")
-        line["eigen"] = eigen_form(plan, problem, coil, mask, y, wl["prior"], args.steps)
+        line["eigen"] = eigen_form(plan, problem, coil, mask, y, wl["prior"], args.steps, args.workload)
     plan.close()
     del x, y
     torch.cuda.empty_cache()
