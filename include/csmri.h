@@ -94,7 +94,9 @@ enum {
                                         (COLUMN_RESIDENT, XU_WAVE, XU_GROUP) have no effect.  Results
                                         agree with the packed inverse to rounding, not bit for bit.
                                         The eigendecomposition is rocSOLVER's batched zheevd, on the
-                                        plan's stream; its failure is CS_EDEVICE. */
+                                        plan's stream; its failure is CS_EDEVICE.  Its FP64 workspace
+                                        comes from the plan's allocator; rocBLAS allocates its own
+                                        internal workspace with hipMalloc, once per plan build. */
 };
 
 /* Device-memory allocator used for everything the plan owns.  alloc returns

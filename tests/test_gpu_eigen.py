@@ -158,3 +158,46 @@ def test_eigen_batch_slice():
     xs = Batch(slices).solve(ys, [LAM, LAM], 12)
     for x, r in zip(xs, refs):
         assert torch.equal(x, r)
+
+
+@pytest.mark.parametrize("prior", ["tv", "dft"])
+@pytest.mark.parametrize("what", ["empty_frame", "full_sampling"])
+def test_eigen_degenerate_blocks(prior, what):
+    """Blocks whose eigendecomposition is degenerate: a frame with no sampled
+    line (G = 0: every e = 0, x = b / mu) and full sampling (G = I for
+    sum-of-squares maps: one eigenvalue of multiplicity nv, U any orthonormal
+    basis)."""
+    from paper_1203_4587_amd.api import Plan
+    case = _case((48, 16, 8, 3), prior, seed=61)
+    if what == "empty_frame":
+        case.mask[3] = 0
+    else:
+        case.mask = np.ones_like(case.mask)
+    case.y = c64(O.forward(case.x_true, case.coil, case.mask))
+    coil, mask, y = case.device()
+    plan = Plan(coil, mask, MU, prior=prior, mu_ratio=RHO, flags=_flag())
+    x = plan.solve(y, LAM, 15).cpu().numpy()
+    ref = O.solve(case.y, case.coil, case.mask, prior, LAM, MU, RHO, 15)["x"]
+    err = rel_l2(x, ref)
+    print(prior, what, "rel_l2", err)
+    assert err < TOL
+
+
+def test_eigen_full_size_tv_256x256x32_8c_sampled_columns():
+    """The 256x256x32, 8-coil, R=8 temporal-TV workload at full size on an
+    eigen-form plan, at the benchmark's iteration count; the oracle recomputes
+    five columns exactly (temporal priors never couple columns)."""
+    from paper_1203_4587_amd import synthetic as S
+    from paper_1203_4587_amd.api import Plan
+    from tests.helpers import Case
+    case = Case(S.CONFIGS["tv256"]())
+    p = case.p
+    coil, mask, y = case.device()
+    plan = Plan(coil, mask, p.mu, prior="tv", mu_ratio=p.rho, flags=_flag())
+    x = plan.solve(y, p.lam, p.iters).cpu().numpy()
+    nh = p.x_true.shape[2]
+    cols = np.array(sorted({0, 1, nh // 3, nh // 2 + 1, nh - 1}))
+    ref = O.solve(case.y, case.coil, case.mask, "tv", p.lam, p.mu, p.rho, p.iters, cols=cols)
+    err = rel_l2(x[:, :, cols], ref["x"])
+    print("tv256 eigen sampled rel_l2", err)
+    assert err < TOL
