@@ -654,10 +654,6 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
   const int col = lane & 15, grp = lane >> 4;
   const bool pv = col < count;
   const size_t p = p0 + col;
-  // all four streams are issued before anything waits on them: x and d2 are
-  // only needed after the shrinkage, but loading them here overlaps their
-  // latency with that of m and d1
-  float2 xv[NK], zv[NK];
   // m -> buf0, d1 -> buf1 (rows t, 16 pixels)
   {
     float2 mv[NK], dv[NK];
@@ -668,8 +664,6 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
       const size_t o = (size_t)t * npix + p;
       mv[k] = ok ? m[o] : make_float2(0.f, 0.f);
       dv[k] = (ok && t < nt - 1) ? d1[o] : make_float2(0.f, 0.f);
-      xv[k] = ok ? x[o] : make_float2(0.f, 0.f);
-      zv[k] = ok ? d2[o] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
@@ -702,6 +696,15 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
   float* bre = reinterpret_cast<float*>(buf0);
   float* bim = bre + KT * 16;
   {
+    float2 xv[NK], zv[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = grp + 4 * k;
+      const bool ok = t < nt && pv;
+      const size_t o = (size_t)t * npix + p;
+      xv[k] = ok ? x[o] : make_float2(0.f, 0.f);
+      zv[k] = ok ? d2[o] : make_float2(0.f, 0.f);
+    }
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
       const int t = grp + 4 * k;
