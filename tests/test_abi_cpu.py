@@ -96,6 +96,33 @@ def test_allocator_failure_is_enomem(lib):
     assert calls and calls[0] >= 256 * 32 * (256 * 257 // 2) * 8
 
 
+def test_eigen_plan_asks_first_for_both_eigenvector_copies(lib):
+    """With CS_FLAG_EIGEN the first (largest) request is U stored twice
+    instead of the packed inverse; a NULL from the allocator is CS_ENOMEM."""
+    calls = []
+
+    def alloc(nbytes, ctx):
+        calls.append(nbytes)
+        return None
+
+    def free(ptr, ctx):
+        raise AssertionError("nothing was allocated")
+    a = _lib.CsAllocator(_lib.ALLOC_FN(alloc), _lib.FREE_FN(free), None)
+    d = _desc(nv=256, nh=256, nt=32, nc=8)
+    d.flags = _lib.CS_FLAG_EIGEN
+    st, h = _create(lib, d, alloc=a)
+    assert st == _lib.CS_ENOMEM and h.value is None
+    assert calls == [256 * 32 * 256 * 256 * 8]
+
+
+def test_header_flag_values_match_the_binding():
+    text = open(os.path.join(ROOT, "include", "csmri.h")).read()
+    found = dict(re.findall(r"\b(CS_FLAG_[A-Z_]+)\s*=\s*1u\s*<<\s*(\d+)", text))
+    assert "CS_FLAG_EIGEN" in found and len(found) == 6
+    for name, bit in found.items():
+        assert getattr(_lib, name) == 1 << int(bit), name
+
+
 def test_null_plan_calls_are_einval(lib):
     assert lib.cs_apply_A(None, FAKE, FAKE, None) == _lib.CS_EINVAL
     assert lib.cs_apply_AH(None, FAKE, FAKE, None) == _lib.CS_EINVAL
