@@ -155,7 +155,10 @@ int cs_apply_A(cs_plan* plan, const cs_c64* x, cs_c64* y, cs_stream stream);
  * rows of y (other rows are ignored and may hold anything). */
 int cs_apply_AH(cs_plan* plan, const cs_c64* y, cs_c64* x, cs_stream stream);
 
-/* x = (mu I + H'H)^{-1} b with the plan's mu (eq. eigen_mu), b and x images. */
+/* x = (mu I + H'H)^{-1} b with the plan's mu (eq. eigen_mu), b and x images
+ * [nt][nv][nh]; x may alias b.  The plan's mu is the one it was created with,
+ * or the mu of its latest solve or forward pass if that one differed (a
+ * packed plan refactored for it; a CS_FLAG_EIGEN plan just takes it over). */
 int cs_apply_block_inverse(cs_plan* plan, const cs_c64* b, cs_c64* x, cs_stream stream);
 
 /* Run `iters` ADMM iterations on data y (Algorithm 2 for the TV prior,

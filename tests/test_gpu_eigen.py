@@ -109,11 +109,19 @@ def test_flag_is_fixed_at_creation_and_forms_are_ignored():
     case = _case((32, 8, 6, 2), "tv", seed=11)
     coil, mask, y = case.device()
     plan = Plan(coil, mask, MU, prior="tv", mu_ratio=RHO, flags=_flag())
+    nt, nv, nh = plan.image_shape
+    assert plan.nbytes >= 2 * nt * nh * nv * nv * 8 + nt * nh * nv * 4   # U twice and e
     ref = plan.solve(y, LAM, 10)
     for f in (_lib.CS_FLAG_COLUMN_RESIDENT, _lib.CS_FLAG_XU_WAVE, _lib.CS_FLAG_XU_GROUP | _lib.CS_FLAG_GRAPH, 0):
         plan.flags = f
         assert plan.flags & _flag()
         assert torch.equal(plan.solve(y, LAM, 10), ref), f
+    # graph replays of the eigen x-update, with eager work in between
+    plan.flags = _lib.CS_FLAG_GRAPH
+    for rep in range(3):
+        assert torch.equal(plan.solve(y, LAM, 10), ref), rep
+        plan.apply_AH(y)
+        torch.cuda.synchronize()
     packed = Plan(coil, mask, MU, prior="tv", mu_ratio=RHO)
     packed.flags = _flag()
     assert not packed.flags & _flag()
