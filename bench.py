@@ -54,13 +54,27 @@ def kernel_source_sha() -> str:
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-def eigen_source_sha() -> str:
-    """Fingerprint of the eigen-form x-update kernels: iterate.hip from its
-    eigen-form section to the end of the file."""
+_EIGEN_MARK = "// ---------------------------------------------------------------- x-update, eigen form"
+_WAVE2_MARK = "// ---------------------------------------------------------------- x-update, two blocks per wave"
+
+
+def _iterate_section(start: str, end: str | None) -> str:
     with open(os.path.join(ROOT, "paper_1203_4587_amd", "csrc", "iterate.hip"), encoding="utf-8") as f:
         text = f.read()
-    text = text[text.index("// ---------------------------------------------------------------- x-update, eigen form"):]
-    return hashlib.sha256(text.encode()).hexdigest()[:16]
+    text = text[text.index(start):]
+    return text[:text.index(end)] if end else text
+
+
+def eigen_source_sha() -> str:
+    """Fingerprint of the eigen-form x-update kernels: iterate.hip's eigen-form
+    section (up to the two-blocks-per-wave section)."""
+    return hashlib.sha256(_iterate_section(_EIGEN_MARK, _WAVE2_MARK).encode()).hexdigest()[:16]
+
+
+def wave2_source_sha() -> str:
+    """Fingerprint of the two-blocks-per-wave x-update: iterate.hip from that
+    section to the end (its kernel, launchers and the x-update dispatch)."""
+    return hashlib.sha256(_iterate_section(_WAVE2_MARK, None).encode()).hexdigest()[:16]
 
 
 def measured_traffic(kind: str, workload: str, steps: int, sha_fn=None):
@@ -537,14 +551,17 @@ def main() -> int:
     if kind == "x_update":
         # which x-update kernel ran (the forms move the same bytes; counters are per kernel)
         f = plan.flags
+        sha_fn = None
         if nv % 2:
             family = "rows"
+        elif (f & _lib.CS_FLAG_XU_WAVE) and nv % 64 == 0 and (nv // 2) % 64:
+            family, sha_fn = "wave2", wave2_source_sha   # two blocks per wave (nv = 64, 192)
         elif not (f & _lib.CS_FLAG_XU_GROUP) and ((f & _lib.CS_FLAG_XU_WAVE) or (nv // 2) % 64 == 0):
             family = "wave"
         else:
             family = "pairs"
         kdesc += f"; kernel k_xupdate_{family}"
-        traffic = measured_traffic(f"x_update_{family}", args.workload, args.steps)
+        traffic = measured_traffic(f"x_update_{family}", args.workload, args.steps, sha_fn)
     else:
         traffic = measured_traffic(kind, args.workload, args.steps)
 

@@ -77,7 +77,9 @@ enum {
                                         and replay it (not while cs_kernel_timing is on) */
   CS_FLAG_COLUMN_RESIDENT = 1u << 2, /* run all iterations in one launch, one workgroup per readout
                                         column, instead of two launches per iteration; same results */
-  CS_FLAG_XU_WAVE = 1u << 3,         /* phase form, even nv: one 64-lane wave solves a block */
+  CS_FLAG_XU_WAVE = 1u << 3,         /* phase form, even nv: one 64-lane wave solves a block, or two
+                                        blocks when nv = 64 or 192 (nv/2 row pairs do not fill whole
+                                        waves, nv pairs do) */
   CS_FLAG_XU_GROUP = 1u << 4,        /* phase form, even nv: a workgroup of nv/2 lanes (rounded up to
                                         whole waves) solves a block.  With neither XU flag the wave
                                         form is used when nv/2 is a multiple of 64.  All x-update

@@ -1955,9 +1955,174 @@ static void eigen_launch(cs_plan* p, const float2* hy, const float2* m, float2* 
   else eigen_launch_r<MODE, 8>(p, hy, m, d2, x, mu, s);
 }
 
+// ---------------------------------------------------------------- x-update, two blocks per wave
+//
+// The packed-inverse product of the wave form (same wrapped diagonals, same
+// operations in the same order, so bit-identical results) for even n whose
+// n/2 row pairs do not fill whole waves but whose 2 (n/2) do: n = 64 and
+// n = 192.  Wave w solves blocks 2w and 2w + 1; slot r of lane l is the pair
+// index P = l + 64 r over both blocks, block b = [P >= n/2], rows
+// 2 (P - b n/2) and 2 (P - b n/2) + 1.  Every lane is busy on every load,
+// where one block per wave would leave a quarter (n = 192) or half (n = 64)
+// of the slots idle.  Each block keeps its own right-hand side and staged
+// diagonals in the wave's LDS.
+
+template <int UNR, int RP>
+struct Diag2Chunk {
+  float4 c[UNR][RP];
+};
+
+template <int UNR, int RP>
+__device__ __forceinline__ void load_chunk2(Diag2Chunk<UNR, RP>& ch, const float2* __restrict__ W,
+                                            const FactorLayout& L, const size_t (&blk)[RP], const int (&q)[RP],
+                                            const bool (&act)[RP], int s0) {
+#pragma unroll
+  for (int u = 0; u < UNR; ++u)
+#pragma unroll
+    for (int r = 0; r < RP; ++r)
+      ch.c[u][r] = (act[r] && s0 + u < L.F) ? ld_stream4(W + diag_offset(L, blk[r], s0 + u) + 2 * q[r])
+                                            : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+template <int UNR, int RP>
+__device__ __forceinline__ void apply_chunk2(const Diag2Chunk<UNR, RP>& ch, const FactorLayout& L, int s0,
+                                             const int (&boff)[RP], const int (&q)[RP], const bool (&act)[RP],
+                                             const float2* bsh, float2* dsh, float2 (&a0)[RP], float2 (&a1)[RP]) {
+  const int n = L.n, n2 = 2 * L.n;
+#pragma unroll
+  for (int u = 0; u < UNR; ++u)
+#pragma unroll
+    for (int r = 0; r < RP; ++r)
+      if (act[r]) *reinterpret_cast<float4*>(dsh + u * n2 + boff[r] + 2 * q[r]) = ch.c[u][r];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int u = 0; u < UNR; ++u) {
+    const int s = s0 + u;
+    if (s < L.F) {
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        if (act[r]) {
+          const float2* bb = bsh + boff[r];
+          const float2* d = dsh + u * n2 + boff[r];
+          const int k0 = 2 * q[r], k1 = k0 + 1;
+          int p0 = k0 + s, p1 = k1 + s, q0 = k0 - s, q1 = k1 - s;
+          p0 -= p0 >= n ? n : 0;
+          p1 -= p1 >= n ? n : 0;
+          q0 += q0 < 0 ? n : 0;
+          q1 += q1 < 0 ? n : 0;
+          a0[r] = cfma(make_float2(ch.c[u][r].x, ch.c[u][r].y), bb[p0], a0[r]);
+          a1[r] = cfma(make_float2(ch.c[u][r].z, ch.c[u][r].w), bb[p1], a1[r]);
+          a0[r] = cfmac(d[q0], bb[q0], a0[r]);
+          a1[r] = cfmac(d[q1], bb[q1], a1[r]);
+        }
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int MODE, int UNR, int RP>
+__global__ __launch_bounds__(64) void k_xupdate_wave2(const float2* __restrict__ W, FactorLayout L, const float2* hy,
+                                                      const float2* __restrict__ m, float2* __restrict__ d2,
+                                                      float2* x, float mu) {
+  extern __shared__ float2 lds[];
+  const int n = L.n, h = n >> 1, F = L.F;
+  float2* bsh = lds;          // [2][n] right-hand sides
+  float2* dsh = lds + 2 * n;  // [UNR][2][n] staged diagonals
+  const int lane = threadIdx.x;
+  size_t blk[RP];
+  int q[RP], boff[RP];
+  bool act[RP];
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    const int P = lane + 64 * r;  // < 2 h = 64 RP
+    const int b = P >= h ? 1 : 0;
+    q[r] = P - b * h;
+    boff[r] = b * n;
+    blk[r] = 2 * (size_t)blockIdx.x + b;
+    act[r] = blk[r] < L.nblk;
+  }
+  Diag2Chunk<UNR, RP> A, B;
+  if (F > 1) load_chunk2<UNR, RP>(A, W, L, blk, q, act, 1);
+  float2 b0[RP], b1[RP], m0[RP], m1[RP], e0[RP], e1[RP], a0[RP], a1[RP];
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    b0[r] = b1[r] = m0[r] = m1[r] = e0[r] = e1[r] = a0[r] = a1[r] = make_float2(0.f, 0.f);
+    if (act[r]) {
+      const size_t base = blk[r] * (size_t)n;
+      b0[r] = rhs_value<MODE>(hy, m, d2, base + 2 * q[r], mu, m0[r], e0[r]);
+      b1[r] = rhs_value<MODE>(hy, m, d2, base + 2 * q[r] + 1, mu, m1[r], e1[r]);
+      const float4 c = ld_stream4(W + diag_offset(L, blk[r], 0) + 2 * q[r]);
+      a0[r] = cmul(make_float2(c.x, c.y), b0[r]);
+      a1[r] = cmul(make_float2(c.z, c.w), b1[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RP; ++r)
+    if (act[r])
+      *reinterpret_cast<float4*>(bsh + boff[r] + 2 * q[r]) = make_float4(b0[r].x, b0[r].y, b1[r].x, b1[r].y);
+  __builtin_amdgcn_wave_barrier();
+  for (int s0 = 1; s0 < F; s0 += 2 * UNR) {
+    if (s0 + UNR < F) load_chunk2<UNR, RP>(B, W, L, blk, q, act, s0 + UNR);
+    apply_chunk2<UNR, RP>(A, L, s0, boff, q, act, bsh, dsh, a0, a1);
+    if (s0 + 2 * UNR < F) load_chunk2<UNR, RP>(A, W, L, blk, q, act, s0 + 2 * UNR);
+    if (s0 + UNR < F) apply_chunk2<UNR, RP>(B, L, s0 + UNR, boff, q, act, bsh, dsh, a0, a1);
+  }
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    if (act[r]) {
+      const float2* hd = W + half_offset(L, blk[r]);
+      const float2* bb = bsh + boff[r];
+      const int k0 = 2 * q[r], k1 = k0 + 1;
+      a0[r] = k0 < h ? cfma(hd[k0], bb[k0 + h], a0[r]) : cfmac(hd[k0 - h], bb[k0 - h], a0[r]);
+      a1[r] = k1 < h ? cfma(hd[k1], bb[k1 + h], a1[r]) : cfmac(hd[k1 - h], bb[k1 - h], a1[r]);
+      const size_t base = blk[r] * (size_t)n;
+      *reinterpret_cast<float4*>(x + base + k0) = make_float4(a0[r].x, a0[r].y, a1[r].x, a1[r].y);
+      if (MODE == kSolveTV)
+        *reinterpret_cast<float4*>(d2 + base + k0) =
+            make_float4(e0[r].x - (m0[r].x - a0[r].x), e0[r].y - (m0[r].y - a0[r].y),
+                        e1[r].x - (m1[r].x - a1[r].x), e1[r].y - (m1[r].y - a1[r].y));
+    }
+  }
+}
+
+// diagonals per chunk: with two blocks the wave's LDS holds (1 + UNR) 2n
+// values, and 4 (15 KB at n = 192) limits a CU to 10 such waves; 2 measured
+// 182.6 us per 192x192x40 launch against 214.6 us for 4 and 196.8 us for
+// the one-block-per-workgroup pairs form
+constexpr int kWave2Unroll = 2;
+
+// n = 64 or 192: the two-blocks-per-wave form replaces the one-block wave form
+static bool wave2_shape(int n) { return n % 64 == 0 && (n / 2) % 64 != 0; }
+
+template <int MODE, int RP>
+static void wave2_launch(cs_plan* p, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
+                         hipStream_t s) {
+  const FactorLayout& L = p->flayout;
+  constexpr int UNR = kWave2Unroll;
+  const size_t lds = (size_t)(1 + UNR) * 2 * L.n * sizeof(float2);
+  const unsigned grid = (unsigned)((L.nblk + 1) / 2);
+  hipLaunchKernelGGL((k_xupdate_wave2<MODE, UNR, RP>), dim3(grid), dim3(64), lds, s, p->factor, L, hy, m, d2, x, mu);
+}
+
+template <int MODE>
+static void wave2_dispatch(cs_plan* p, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
+                           hipStream_t s) {
+  if (p->desc.nv == 64) wave2_launch<MODE, 1>(p, hy, m, d2, x, mu, s);
+  else wave2_launch<MODE, 3>(p, hy, m, d2, x, mu, s);
+}
+
 int launch_xupdate(cs_plan* p, int mode, const float2* hy, const float2* m, float2* d2, float2* x, float mu,
                    hipStream_t s) {
-  if (!(p->desc.flags & CS_FLAG_EIGEN)) return launch_block_solve(p, mode, hy, m, d2, x, mu, s);
+  const uint32_t f = p->desc.flags;
+  if (!(f & CS_FLAG_EIGEN)) {
+    if (!(f & CS_FLAG_XU_WAVE) || !wave2_shape(p->desc.nv)) return launch_block_solve(p, mode, hy, m, d2, x, mu, s);
+    if (mode == kSolveTV) wave2_dispatch<kSolveTV>(p, hy, m, d2, x, mu, s);
+    else if (mode == kSolveDFT) wave2_dispatch<kSolveDFT>(p, hy, m, d2, x, mu, s);
+    else wave2_dispatch<kSolvePlain>(p, hy, m, d2, x, mu, s);
+    CS_HIP(hipGetLastError());
+    return CS_OK;
+  }
   if (mode == kSolveTV) eigen_launch<kSolveTV>(p, hy, m, d2, x, mu, s);
   else if (mode == kSolveDFT) eigen_launch<kSolveDFT>(p, hy, m, d2, x, mu, s);
   else eigen_launch<kSolvePlain>(p, hy, m, d2, x, mu, s);

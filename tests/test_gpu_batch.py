@@ -117,7 +117,10 @@ def test_batch_with_per_slice_forms():
 
 
 @pytest.mark.parametrize("shape,prior", [((128, 16, 16, 3), "tv"), ((192, 12, 24, 3), "dft"),
-                                         ((12, 8, 6, 2), "tv"), ((256, 8, 8, 2), "dft")], ids=str)
+                                         ((12, 8, 6, 2), "tv"), ((256, 8, 8, 2), "dft"),
+                                         # two blocks per wave (n = 64, 192), odd block counts
+                                         ((64, 9, 3, 2), "tv"), ((192, 3, 3, 2), "tv"), ((64, 12, 5, 2), "dft")],
+                         ids=str)
 def test_xupdate_forms_are_bit_identical(shape, prior):
     from paper_1203_4587_amd import _lib
     from paper_1203_4587_amd.api import Plan

@@ -167,23 +167,34 @@ def test_full_size_tv_256x256x32_8c_sampled_columns():
     recomputes five columns exactly."""
     case = Case(S.CONFIGS["tv256"]())
     p = case.p
-    _, _, x = _run(case, "tv", p.lam, p.mu, p.rho, p.iters)
+    plan, y, x = _run(case, "tv", p.lam, p.mu, p.rho, p.iters)
     cols = _sampled_columns(p.x_true.shape[2])
     ref = _oracle(case, "tv", p.lam, p.mu, p.rho, p.iters, cols=cols)
     err = rel_l2(x.cpu().numpy()[:, :, cols], ref["x"])
     print("tv256 sampled rel_l2", err)
     assert err < TOL
+    _tuned_equals(plan, y, p, x)
+
+
+def _tuned_equals(plan, y, p, x):
+    """The benchmark's configuration: the form the tuner picks (graph replay
+    and an x-update form), after warm-up solves, gives the same bits."""
+    plan.tune(y, p.lam, iters=10)
+    plan.solve(y, p.lam, 10)
+    for _ in range(2):
+        assert torch.equal(plan.solve(y, p.lam, p.iters), x)
 
 
 def test_full_size_dft_192x192x40_12c_sampled_columns():
     case = Case(S.CONFIGS["dft192"]())
     p = case.p
-    _, _, x = _run(case, "dft", p.lam, p.mu, p.rho, p.iters)
+    plan, y, x = _run(case, "dft", p.lam, p.mu, p.rho, p.iters)
     cols = _sampled_columns(p.x_true.shape[2])
     ref = _oracle(case, "dft", p.lam, p.mu, p.rho, p.iters, cols=cols)
     err = rel_l2(x.cpu().numpy()[:, :, cols], ref["x"])
     print("dft192 sampled rel_l2", err)
     assert err < TOL
+    _tuned_equals(plan, y, p, x)
 
 
 FORM_CASES = [((64, 32, 10, 4), "tv"), ((64, 32, 10, 4), "dft"), ((96, 24, 40, 3), "dft"),
