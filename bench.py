@@ -554,7 +554,7 @@ def main() -> int:
         sha_fn = None
         if nv % 2:
             family = "rows"
-        elif (f & _lib.CS_FLAG_XU_WAVE) and nv % 64 == 0 and (nv // 2) % 64:
+        elif not (f & _lib.CS_FLAG_XU_GROUP) and nv % 64 == 0 and (nv // 2) % 64:
             family, sha_fn = "wave2", wave2_source_sha   # two blocks per wave (nv = 64, 192)
         elif not (f & _lib.CS_FLAG_XU_GROUP) and ((f & _lib.CS_FLAG_XU_WAVE) or (nv // 2) % 64 == 0):
             family = "wave"

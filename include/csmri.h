@@ -82,8 +82,8 @@ enum {
                                         waves, nv pairs do) */
   CS_FLAG_XU_GROUP = 1u << 4,        /* phase form, even nv: a workgroup of nv/2 lanes (rounded up to
                                         whole waves) solves a block.  With neither XU flag the wave
-                                        form is used when nv/2 is a multiple of 64.  All x-update
-                                        forms give bit-identical results. */
+                                        form is used when nv/2 is a multiple of 64 and for nv = 64 and
+                                        192.  All x-update forms give bit-identical results. */
   CS_FLAG_EIGEN = 1u << 5,           /* set at cs_plan_create only (cs_plan_set_flags keeps it as it
                                         is): store every block in the paper's eigen form
                                         G = U diag(e) U' (Sec. IV-C, eq. eigen_mu; complex64 U, float e,

@@ -2092,7 +2092,7 @@ __global__ __launch_bounds__(64) void k_xupdate_wave2(const float2* __restrict__
 // the one-block-per-workgroup pairs form
 constexpr int kWave2Unroll = 2;
 
-// n = 64 or 192: the two-blocks-per-wave form replaces the one-block wave form
+// n = 64 or 192: the two-blocks-per-wave form replaces the one-block wave form and is the default there
 static bool wave2_shape(int n) { return n % 64 == 0 && (n / 2) % 64 != 0; }
 
 template <int MODE, int RP>
@@ -2116,7 +2116,8 @@ int launch_xupdate(cs_plan* p, int mode, const float2* hy, const float2* m, floa
                    hipStream_t s) {
   const uint32_t f = p->desc.flags;
   if (!(f & CS_FLAG_EIGEN)) {
-    if (!(f & CS_FLAG_XU_WAVE) || !wave2_shape(p->desc.nv)) return launch_block_solve(p, mode, hy, m, d2, x, mu, s);
+    // n = 64, 192: two blocks per wave unless the workgroup form is asked for
+    if ((f & CS_FLAG_XU_GROUP) || !wave2_shape(p->desc.nv)) return launch_block_solve(p, mode, hy, m, d2, x, mu, s);
     if (mode == kSolveTV) wave2_dispatch<kSolveTV>(p, hy, m, d2, x, mu, s);
     else if (mode == kSolveDFT) wave2_dispatch<kSolveDFT>(p, hy, m, d2, x, mu, s);
     else wave2_dispatch<kSolvePlain>(p, hy, m, d2, x, mu, s);
