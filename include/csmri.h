@@ -66,8 +66,9 @@ typedef enum {
   CS_PRIOR_TEMPORAL_FRAME = 2, /* Algorithm 1 with the overcomplete tight frame Psi = [I; F] / sqrt(2)
                                   (identity and unitary DFT along frames; Psi'Psi = I, Psi Psi' != I),
                                   including the (1/mu)(I - Psi Psi') term of the w-update (Sec. IV-A).
-                                  Coefficients have 2 nt frames (identity part first).  No J_trace,
-                                  no Delta-driven solve, no column-resident form. */
+                                  Coefficients have 2 nt frames (identity part first).  J(k) is taken
+                                  at the coefficients w_k, lambda ||w_k||_1 + ||y - H Psi' w_k||^2
+                                  (eq. L1unconst).  No column-resident form. */
 } cs_prior;
 
 enum {
@@ -171,8 +172,10 @@ int cs_apply_block_inverse(cs_plan* plan, const cs_c64* b, cs_c64* x, cs_stream 
  *   CS_FLAG_NO_REFACTOR, which makes the call return CS_EMU_MISMATCH.
  *   state may be NULL (fresh start, nothing returned) -- see cs_state.
  *   J_trace, if not NULL, is a device float[iters] that receives the
- *   objective J(k) after each iteration (lambda ||D_t x||_1 + ||y - Hx||^2, or
- *   lambda ||Psi x||_1 + ||y - Hx||^2), used for Delta(k) of eq. r_ratio.
+ *   objective J(k) after each iteration (lambda ||D_t x||_1 + ||y - Hx||^2,
+ *   lambda ||Psi x||_1 + ||y - Hx||^2, or for the frame lambda ||w||_1 +
+ *   ||y - H Psi' w||^2), used for Delta(k) of eq. r_ratio.  On the frame prior
+ *   each evaluation also completes w and d, which leaves results bit-identical.
  * iters == 0 writes H'y (the algorithms' initial x) to x_out.
  * Execution: two launches per iteration (temporal step, x-update).  With
  * CS_FLAG_COLUMN_RESIDENT, even nv and no J_trace, all iterations run in one

@@ -251,7 +251,7 @@ def admm_analysis(Hy: np.ndarray, fac: BlockFactor, lam: float, mu: float, rho: 
 
 def admm_synthesis(Hy: np.ndarray, fac: BlockFactor, lam: float, mu: float, iters: int,
                    psi=tdft, psi_adj=tdft_adj, state: dict | None = None,
-                   callback=None) -> dict:
+                   callback=None, callback_w=None) -> dict:
     """Algorithm 1 for a tight frame Psi (Psi'Psi = I); default Psi = temporal DFT.
 
     Initialisation: d = 0, w = Psi H'y.  Each iteration:
@@ -279,6 +279,8 @@ def admm_synthesis(Hy: np.ndarray, fac: BlockFactor, lam: float, mu: float, iter
         d = d - (w - v)
         if callback is not None:
             callback(k0 + k + 1, psi_adj(w))
+        if callback_w is not None:
+            callback_w(k0 + k + 1, w)
     return {"x": psi_adj(w), "w": w, "v": v, "d": d, "iter": k0 + iters}
 
 
@@ -297,6 +299,14 @@ def objective_dft(x, y, coil, mask, lam) -> float:
     """J = lambda ||w||_1 + ||y - H Psi' w||^2 at w = Psi x (eq. L1unconst)."""
     r = (y * mask[:, None, :, None]) - forward(x, coil, mask)
     return float(lam * np.abs(tdft(x)).sum() + (np.abs(r) ** 2).sum())
+
+
+def objective_synthesis(w, y, coil, mask, lam, psi_adj=tdft_adj) -> float:
+    """J = lambda ||w||_1 + ||y - H Psi' w||^2 (eq. L1unconst) at the
+    coefficients w themselves: for an overcomplete frame w need not equal
+    Psi Psi' w, so the value is not a function of x = Psi' w alone."""
+    r = (y * mask[:, None, :, None]) - forward(psi_adj(w), coil, mask)
+    return float(lam * np.abs(w).sum() + (np.abs(r) ** 2).sum())
 
 
 def delta(j_prev: float, j_cur: float) -> float:

@@ -177,8 +177,13 @@ int run_iterations(cs_plan* p, int32_t iters, float lambda, float mu, float* J_t
   // plain loop is recorded into that graph instead of a cached one
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   CS_HIP(hipStreamIsCapturing(s, &cap));
-  if ((p->desc.flags & CS_FLAG_GRAPH) && cap == hipStreamCaptureStatusNone && !p->timing && iters > 0)
-    return run_phase_graph(p, iters, lambda, mu, J_trace, wgiven, s);
+  if ((p->desc.flags & CS_FLAG_GRAPH) && cap == hipStreamCaptureStatusNone && !p->timing && iters > 0) {
+    const int st = run_phase_graph(p, iters, lambda, mu, J_trace, wgiven, s);
+    // a replay runs no host code: the frame state is what the captured loop
+    // leaves, completed exactly when its last iteration evaluated J
+    p->frame_w_ready = J_trace != nullptr;
+    return st;
+  }
   return run_phase_loop(p, iters, lambda, mu, J_trace, wgiven, s);
 }
 
@@ -196,11 +201,20 @@ static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, flo
         st = timed_launch(p, kKindX, s,
                           [&] { return launch_xupdate(p, kSolveTV, p->hy, p->s0, p->s3, p->s2, mu, s); });
     } else if (p->desc.prior == CS_PRIOR_TEMPORAL_FRAME) {
-      // the first pass of a call starts from the w held in img_tmp
-      st = timed_launch(p, kKindDFT, s, [&] { return launch_frame_step(p, lambda, mu, k == 0 && !cont, s); });
+      // a pass after the set-up or after an objective evaluation starts from
+      // the completed w held in img_tmp
+      const bool from_w = p->frame_w_ready;
+      st = timed_launch(p, kKindDFT, s, [&] { return launch_frame_step(p, lambda, mu, from_w ? 1 : 0, s); });
+      p->frame_w_ready = false;
       if (st == CS_OK)
         st = timed_launch(p, kKindX, s,
                           [&] { return launch_xupdate(p, kSolveDFT, p->hy, p->s3, nullptr, p->s2, mu, s); });
+      if (st == CS_OK && J_trace) {
+        // J(k) is taken at w_k (eq. L1unconst), which the next pass would
+        // otherwise complete in registers: complete it (and d_k) here
+        st = launch_frame_finish(p, s);
+        p->frame_w_ready = true;
+      }
     } else {
       st = timed_launch(p, kKindDFT, s, [&] {
         const bool first = k == 0 && !cont;
@@ -284,6 +298,7 @@ static int solve_setup(cs_plan* p, const cs_c64* y, float mu, const cs_state* st
       CK(launch_fill(p->s0, 2 * nimg, zero, s));           // d_0 = 0
       CK(launch_fill(p->s1, 2 * nimg, zero, s));           // v_0 = 0
     }
+    p->frame_w_ready = true;
   } else {
     if (warm) {
       CK(in_t(state->s0, p->img_tmp, nt));                 // w, used as is by the first pass
@@ -325,7 +340,8 @@ static int solve_finish(cs_plan* p, int32_t iters, cs_c64* x_out, cs_state* stat
       if (iters > 0 || !warm) {
         // w and d of the last iteration (the pass that follows an iteration
         // completes them); a fresh start with no iteration returns w_0 = Psi H'y
-        if (iters > 0) CK(launch_frame_finish(p, s));
+        if (!p->frame_w_ready) CK(launch_frame_finish(p, s));
+        p->frame_w_ready = true;
         CK(out_t(p->img_tmp, state->s0, 2 * nt));
         CK(out_t(p->s1, state->s1, 2 * nt));
         CK(out_t(p->s0, state->s2, 2 * nt));
@@ -646,8 +662,6 @@ int cs_admm_solve(cs_plan* p, const cs_c64* y, float lambda, float mu, int32_t i
                   cs_state* state, float* J_trace, cs_stream stream) {
   if (!p || !y || !x_out) return set_error(CS_EINVAL, "plan, y and x_out must not be NULL");
   if (iters < 0) return set_error(CS_EINVAL, "iters must be >= 0");
-  if (J_trace && p->desc.prior == CS_PRIOR_TEMPORAL_FRAME)
-    return set_error(CS_EUNSUPPORTED, "no objective trace for the overcomplete frame prior");
   int st = solve_check(p, lambda, mu, state);
   if (st != CS_OK) return st;
   CS_HIP(hipSetDevice(p->device));
@@ -665,8 +679,6 @@ int cs_admm_solve_until(cs_plan* p, const cs_c64* y, float lambda, float mu, int
   if (max_iters < 1) return set_error(CS_EINVAL, "max_iters must be >= 1");
   if (check_every < 1) return set_error(CS_EINVAL, "check_every must be >= 1");
   if (!std::isfinite(tol)) return set_error(CS_EINVAL, "tol must be finite");
-  if (p->desc.prior == CS_PRIOR_TEMPORAL_FRAME)
-    return set_error(CS_EUNSUPPORTED, "no objective monitor for the overcomplete frame prior");
   int st = solve_check(p, lambda, mu, state);
   if (st != CS_OK) return st;
   CS_HIP(hipSetDevice(p->device));

@@ -194,6 +194,10 @@ struct cs_plan {
 
   // per-kernel event timing (cs_kernel_timing)
   bool timing = false;
+  // overcomplete frame prior: img_tmp holds a completed w (and s0 the
+  // completed d) -- after the set-up of a solve and after launch_frame_finish --
+  // rather than the deferred state an iteration leaves for the next frame pass
+  bool frame_w_ready = false;
   struct TimedLaunch {
     int kind;
     hipEvent_t start, stop;

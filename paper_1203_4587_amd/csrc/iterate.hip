@@ -1598,8 +1598,8 @@ int launch_dft_adjoint(cs_plan* p, unsigned nblocks, const float2* bb, float2* d
 // J = lambda * l1 + ||y - H x||^2 (eqs. L1an_pri / L1unconst), evaluated in
 // hybrid (ky, i) space: F_h is unitary, so the data term equals
 // sum_{t,c,r,i} |(M_t F_v (s_c . x))[r, i] - (F_h' y)[r, i]|^2 over sampled
-// rows r.  l1 = sum |D_t x| (TV) or sum |Psi x| (DFT), moduli of complex
-// values.  Partial sums are FP64 and reduced in a fixed order, so the value
+// rows r.  l1 = sum |D_t x| (TV), sum |Psi x| (DFT) or, for the overcomplete
+// frame, sum |w| over the completed coefficients (moduli of complex values).  Partial sums are FP64 and reduced in a fixed order, so the value
 // is bit-reproducible run to run.
 constexpr int kJBlocks = 1024;
 constexpr int kJThreads = 256;
@@ -1623,6 +1623,17 @@ __global__ __launch_bounds__(kJThreads) void k_l1_tv_partial(const float2* __res
     const float2 a = x[q + npix], b = x[q];
     const double dx = (double)a.x - b.x, dy = (double)a.y - b.y;
     acc += sqrt(dx * dx + dy * dy);
+  }
+  block_reduce_store(acc, part + blockIdx.x);
+}
+
+// l1 of the coefficients w themselves (overcomplete frame prior: 2 nt frames)
+__global__ __launch_bounds__(kJThreads) void k_l1_abs_partial(const float2* __restrict__ w, size_t count,
+                                                              double* __restrict__ part) {
+  double acc = 0.0;
+  for (size_t q = (size_t)blockIdx.x * kJThreads + threadIdx.x; q < count; q += (size_t)kJBlocks * kJThreads) {
+    const float2 a = w[q];
+    acc += sqrt((double)a.x * a.x + (double)a.y * a.y);
   }
   block_reduce_store(acc, part + blockIdx.x);
 }
@@ -1722,6 +1733,10 @@ int launch_objective(cs_plan* p, const float2* x, float lambda, float* out, hipS
   if (st != CS_OK) return st;
   if (p->desc.prior == CS_PRIOR_TEMPORAL_TV) {
     hipLaunchKernelGGL(k_l1_tv_partial, dim3(kJBlocks), dim3(kJThreads), 0, s, x, nt, npix,
+                       p->jpart + kJBlocks);
+  } else if (p->desc.prior == CS_PRIOR_TEMPORAL_FRAME) {
+    // J at the completed coefficients w (img_tmp); x = Psi' w for the data term
+    hipLaunchKernelGGL(k_l1_abs_partial, dim3(kJBlocks), dim3(kJThreads), 0, s, p->img_tmp, 2 * (size_t)nt * npix,
                        p->jpart + kJBlocks);
   } else {
     switch (dft_kp(nt)) {

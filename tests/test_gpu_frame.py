@@ -1,8 +1,8 @@
 """GPU parity of Algorithm 1 with the overcomplete tight temporal frame
 Psi = [I; F] / sqrt(2) (CS_PRIOR_TEMPORAL_FRAME) against the FP64 oracle:
 images and the coefficient state (w, v, d) within relative l2 1e-4 after a
-fixed iteration count, warm starts bit for bit, and the execution forms
-that apply (graph replay, batches)."""
+fixed iteration count, warm starts bit for bit, the execution forms that
+apply (graph replay, batches), the J(k) trace and the Delta(k)-driven stop."""
 import numpy as np
 import pytest
 
@@ -90,16 +90,89 @@ def test_frame_resume_zero_iterations_and_graph():
             assert torch.equal(g.solve(y, LAM, 20), x20), flags
 
 
-def test_frame_unsupported_calls():
+def _oracle_J(case, iters):
+    """J(k) = lambda ||w_k||_1 + ||y - H Psi' w_k||^2 (eq. L1unconst) of the
+    FP64 oracle for k = 0 .. iters, J(0) at w_0 = Psi H'y."""
+    Hy = O.adjoint(case.y, case.coil, case.mask)
+    fac = O.BlockFactor(case.coil, case.mask)
+    J = [O.objective_synthesis(O.tframe(Hy), case.y, case.coil, case.mask, LAM, psi_adj=O.tframe_adj)]
+    cb = lambda k, w: J.append(O.objective_synthesis(w, case.y, case.coil, case.mask, LAM, psi_adj=O.tframe_adj))
+    O.admm_synthesis(Hy, fac, LAM, MU, iters, psi=O.tframe, psi_adj=O.tframe_adj, callback_w=cb)
+    return J
+
+
+@pytest.mark.parametrize("shape", [(48, 32, 12, 3), (27, 18, 5, 2), (16, 8, 40, 2)], ids=str)
+def test_frame_objective_trace_matches_oracle(shape):
+    """The J(k) trace is taken at the completed coefficients w_k; evaluating
+    it completes w and d between iterations, which leaves the image and the
+    state bit-identical to an untraced solve (also under graph replay)."""
     from paper_1203_4587_amd import _lib
     from paper_1203_4587_amd.api import Plan
-    case = _case((32, 8, 6, 2), seed=9)
+    case = _case(shape, seed=shape[0] + 3)
+    coil, mask, y = case.device()
+    iters = 12
+    plan = Plan(coil, mask, MU, prior="frame")
+    st = plan.new_state()
+    x, J = plan.solve(y, LAM, iters, state=st, trace=True)
+    Jref = _oracle_J(case, iters)[1:]
+    J = J.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(J, Jref, rtol=1e-4)
+    d = [O.delta(a, b) for a, b in zip(J[:-1], J[1:])]
+    dref = [O.delta(a, b) for a, b in zip(Jref[:-1], Jref[1:])]
+    np.testing.assert_allclose(d, dref, atol=1e-4)
+    plain = Plan(coil, mask, MU, prior="frame")
+    st2 = plain.new_state()
+    assert torch.equal(plain.solve(y, LAM, iters, state=st2), x)
+    for n in ("s0", "s1", "s2"):
+        assert torch.equal(getattr(st, n), getattr(st2, n)), n
+    g = Plan(coil, mask, MU, prior="frame", flags=_lib.CS_FLAG_GRAPH)
+    for _ in range(3):
+        st3 = g.new_state()
+        xg, Jg = g.solve(y, LAM, iters, state=st3, trace=True)
+        assert torch.equal(xg, x) and torch.equal(Jg.cpu(), torch.from_numpy(J.astype(np.float32)))
+        for n in ("s0", "s1", "s2"):
+            assert torch.equal(getattr(st3, n), getattr(st, n)), n
+        del xg, Jg  # lets the next call reuse the buffers, so the cached graph replays
+        torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("check_every", [4, 1])
+def test_frame_delta_driven_solve_stops_where_the_oracle_does(check_every):
+    """cs_admm_solve_until on the frame prior: the stop iteration matches the
+    oracle's under the blocked rule, and the image and state equal a
+    fixed-count solve of that many iterations bit for bit."""
+    from paper_1203_4587_amd.api import Plan
+    case = _case((48, 24, 8, 3), seed=61)
+    max_iters = 60
+    J = _oracle_J(case, max_iters)
+    checks, k = [], 0
+    while k < max_iters:
+        k = min(k + check_every, max_iters)
+        checks.append((k, (J[k - 1] - J[k]) / J[k]))
+    deltas = [dd for _, dd in checks]
+    target = None
+    for a in range(3, len(checks) - 1):
+        lo = deltas[a]
+        if min(deltas[:a]) > 1.25 * lo and lo > 0:
+            target = (a, (min(deltas[:a]) * lo) ** 0.5)
+            break
+    assert target is not None, deltas
+    a, tol = target
+    k_ref = checks[a][0]
     coil, mask, y = case.device()
     plan = Plan(coil, mask, MU, prior="frame")
-    with pytest.raises(_lib.CsmriError, match="objective"):
-        plan.solve(y, LAM, 5, trace=True)
-    with pytest.raises(_lib.CsmriError, match="objective"):
-        plan.solve_until(y, LAM, 10)
+    st = plan.new_state()
+    x, k, delta = plan.solve_until(y, LAM, max_iters, tol=tol, check_every=check_every, state=st)
+    print("frame", check_every, "stop", k, "oracle", k_ref, "delta", delta, checks[a][1], "tol", tol)
+    assert k == k_ref
+    assert abs(delta - checks[a][1]) <= 0.05 * abs(checks[a][1])
+    ref_plain = Plan(coil, mask, MU, prior="frame")
+    st2 = ref_plain.new_state()
+    assert torch.equal(x, ref_plain.solve(y, LAM, k, state=st2))
+    for n in ("s0", "s1", "s2"):
+        assert torch.equal(getattr(st, n), getattr(st2, n)), n
+    assert st.iter == st2.iter == k
+    assert rel_l2(x.cpu().numpy(), _oracle(case, k)["x"]) < TOL
 
 
 def test_frame_slice_in_a_batch():

@@ -537,3 +537,14 @@ def test_objectives_match_dense_definitions(rng):
     Px = np.einsum("ft,tji->fji", Fm, x)
     J_dft = lam * np.abs(Px).sum() + np.vdot(r, r).real
     assert np.isclose(O.objective_dft(x, y, coil, mask, lam), J_dft, rtol=1e-13)
+    # synthesis objective at coefficients w of the frame Psi = [I; F] / sqrt(2)
+    # (2 nt coefficient frames, identity part first): x = Psi' w from the dense
+    # matrices, and the l1 term on w itself
+    w = crandn(rng, 2 * nt, nv, nh)
+    Psi = np.vstack([np.eye(nt), Fm]) / np.sqrt(2.0)
+    xw = np.einsum("kt,kji->tji", Psi.conj(), w)
+    rw = y.ravel() - H @ xw.ravel()
+    J_frame = lam * np.abs(w).sum() + np.vdot(rw, rw).real
+    assert np.isclose(O.objective_synthesis(w, y, coil, mask, lam, psi_adj=O.tframe_adj), J_frame, rtol=1e-13)
+    # with the orthonormal DFT it is the DFT objective at x = Psi' w
+    assert np.isclose(O.objective_synthesis(O.tdft(x), y, coil, mask, lam), J_dft, rtol=1e-13)
