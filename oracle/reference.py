@@ -127,10 +127,6 @@ class BlockFactor:
         x = self.U @ (Uh_b / (self.e[..., None] + mu))
         return np.moveaxis(x[..., 0], 1, -1)
 
-    def gram(self, t: int, ci: int) -> np.ndarray:
-        U, e = self.U[t, ci], self.e[t, ci]
-        return (U * e) @ U.conj().T
-
 
 # --------------------------------------------------------------------------
 # Shrinkage and temporal operators
@@ -161,20 +157,27 @@ def tdiff_adj(v: np.ndarray) -> np.ndarray:
     return out
 
 
-def tv_system_solve(r: np.ndarray, rho: float) -> np.ndarray:
-    """m = (rho I + D_t' D_t)^{-1} r along the frame axis (the m-update of
-    Algorithm 2 with R = D_t).  The matrix is tridiagonal, diagonal
-    [rho+1, rho+2, ..., rho+2, rho+1], off-diagonals -1; solved exactly."""
+def tv_normal_solve(r: np.ndarray, a: float, b: float) -> np.ndarray:
+    """m = (a D_t' D_t + b I)^{-1} r along the frame axis, a >= 0, b > 0.
+
+    D_t' D_t is the path-graph Laplacian of eq. TV (non-periodic): diagonal
+    [1, 2, ..., 2, 1], off-diagonals -1.  The banded system is solved exactly."""
     nt = r.shape[0]
     flat = r.reshape(nt, -1)
     if nt == 1:
-        return (flat / rho).reshape(r.shape)
+        return (flat / b).reshape(r.shape)
     ab = np.zeros((3, nt))
-    ab[0, 1:] = -1.0
-    ab[2, :-1] = -1.0
-    ab[1, :] = rho + 2.0
-    ab[1, 0] = ab[1, -1] = rho + 1.0
+    ab[0, 1:] = -a
+    ab[2, :-1] = -a
+    ab[1, :] = 2.0 * a + b
+    ab[1, 0] = ab[1, -1] = a + b
     return scipy.linalg.solve_banded((1, 1), ab, flat).reshape(r.shape)
+
+
+def tv_system_solve(r: np.ndarray, rho: float) -> np.ndarray:
+    """m = (rho I + D_t' D_t)^{-1} r, the matrix of the m-update of Algorithm 2
+    with R = D_t divided through by mu_1 (rho = mu_2 / mu_1)."""
+    return tv_normal_solve(r, 1.0, rho)
 
 
 def tdft(z: np.ndarray) -> np.ndarray:
@@ -203,27 +206,36 @@ def tframe_adj(w: np.ndarray) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# Algorithm 2: ADMM_Analysis with R = D_t (Sec. IV-B)
+# ADMM for the two split problems (Sec. II-B, Sec. IV-A, Sec. IV-B)
 # --------------------------------------------------------------------------
+#
+# Both algorithms are the ADMM template of eqs. admm_ex1-admm_ex3 applied to a
+# split problem: minimise the augmented Lagrangian over each primal variable
+# in turn, holding the others fixed, then move every scaled dual d along the
+# residual of its constraint (eq. admm_ex3).  Each primal step below is that
+# exact minimiser: the l1 prox for v, and the normal equations of the
+# quadratic sub-problems for m, x and w.
+
+
+def prox_l1(c: np.ndarray, lam: float, pen: float) -> np.ndarray:
+    """argmin_v lam ||v||_1 + pen ||v - c||^2 = soft(c, lam / (2 pen)): the
+    minimiser is separable, and per entry it is the complex soft threshold of
+    Sec. III (complex l1 = sum of moduli)."""
+    return soft(c, lam / (2.0 * pen))
 
 
 def admm_analysis(Hy: np.ndarray, fac: BlockFactor, lam: float, mu: float, rho: float,
                   iters: int, state: dict | None = None, callback=None) -> dict:
-    """Algorithm 2 with temporal TV.  mu is mu_2, rho = mu_2 / mu_1.
+    """Algorithm 2 (Sec. IV-B) with R = D_t: ADMM on the split problem of
+    eq. anL1_2, min lam ||v||_1 + ||y - Hx||^2 subject to v = D_t m, m = x.
 
-    Hy: H'y restricted to the factor's columns, shape (nt, nv, k).
-    Returns the final state {x, m, d1, d2, iter}.  Initialisation follows the
-    algorithm: d1 = d2 = 0, x = H'y, m = x, unless ``state`` is given.
-    Each iteration, in the algorithm's order:
-        v  = soft(D m + d1, lambda / (2 mu_1))
-        m  = (mu_2/mu_1 I + D'D)^{-1} [D'(v - d1) + mu_2/mu_1 (x + d2)]
-        x  = (mu_2 I + H'H)^{-1} [H'y + mu_2 (m - d2)]
-        d1 = d1 - (v - D m)
-        d2 = d2 - (m - x)
-    """
+    mu is mu_2 and rho = mu_2 / mu_1, so mu_1 = mu / rho.  Hy is H'y restricted
+    to the factor's columns, shape (nt, nv, k).  The augmented Lagrangian adds
+    mu_1 ||v - D_t m - d1||^2 + mu_2 ||m - x - d2||^2.  Start (Algorithm 2):
+    d1 = d2 = 0, x = H'y, m = x, unless ``state`` continues an earlier run.
+    Returns the state {x, m, d1, d2, iter}."""
     mu2 = mu
     mu1 = mu / rho
-    tau = lam / (2.0 * mu1)
     if state is None:
         x = Hy.copy()
         m = x.copy()
@@ -234,34 +246,42 @@ def admm_analysis(Hy: np.ndarray, fac: BlockFactor, lam: float, mu: float, rho: 
         x, m, d1, d2 = (np.array(state[n], dtype=np.complex128) for n in ("x", "m", "d1", "d2"))
         k0 = int(state.get("iter", 0))
     for k in range(iters):
-        v = soft(tdiff(m) + d1, tau)
-        m = tv_system_solve(tdiff_adj(v - d1) + rho * (x + d2), rho)
+        # v: only lam ||v||_1 + mu_1 ||v - (D_t m + d1)||^2 depends on v
+        v = prox_l1(tdiff(m) + d1, lam, mu1)
+        # m: mu_1 ||D_t m - (v - d1)||^2 + mu_2 ||m - (x + d2)||^2 is quadratic;
+        # its normal equations are (mu_1 D_t'D_t + mu_2 I) m = mu_1 D_t'(v - d1) + mu_2 (x + d2)
+        m = tv_normal_solve(mu1 * tdiff_adj(v - d1) + mu2 * (x + d2), mu1, mu2)
+        # x: ||y - Hx||^2 + mu_2 ||x - (m - d2)||^2 gives (H'H + mu_2 I) x = H'y + mu_2 (m - d2),
+        # solved exactly with the per-block eigendecompositions (eq. eigen_mu)
         x = fac.solve(Hy + mu2 * (m - d2), mu2)
-        d1 = d1 - (v - tdiff(m))
-        d2 = d2 - (m - x)
+        # scaled duals follow their constraints' residuals, d1 for v = D_t m and d2 for m = x
+        d1 = d1 + (tdiff(m) - v)
+        d2 = d2 + (x - m)
         if callback is not None:
             callback(k0 + k + 1, x)
     return {"x": x, "m": m, "d1": d1, "d2": d2, "iter": k0 + iters}
 
 
-# --------------------------------------------------------------------------
-# Algorithm 1: ADMM_Synthesis with a tight frame Psi (Sec. IV-A)
-# --------------------------------------------------------------------------
+def tight_frame_system_solve(q: np.ndarray, fac: BlockFactor, mu: float, psi, psi_adj) -> np.ndarray:
+    """(mu I + Psi H'H Psi')^{-1} q for a tight frame (Psi'Psi = I), by the
+    matrix inversion lemma of Sec. IV-A in its final two-term form:
+        (1/mu)(q - Psi Psi' q) + Psi (mu I + H'H)^{-1} Psi' q.
+    (The first line of that derivation lacks a 1/mu on its second term; the
+    final form is the one that inverts the matrix.)"""
+    pq = psi_adj(q)
+    return (q - psi(pq)) / mu + psi(fac.solve(pq, mu))
 
 
 def admm_synthesis(Hy: np.ndarray, fac: BlockFactor, lam: float, mu: float, iters: int,
                    psi=tdft, psi_adj=tdft_adj, state: dict | None = None,
                    callback=None, callback_w=None) -> dict:
-    """Algorithm 1 for a tight frame Psi (Psi'Psi = I); default Psi = temporal DFT.
+    """Algorithm 1 (Sec. IV-A): ADMM on the split problem of eq. syntL1,
+    min lam ||v||_1 + ||y - H Psi' w||^2 subject to v = w, for a tight frame
+    Psi (Psi'Psi = I); the default Psi is the unitary temporal DFT.
 
-    Initialisation: d = 0, w = Psi H'y.  Each iteration:
-        v = soft(w - d, lambda / (2 mu))
-        w = (1/mu)(I - Psi Psi')[Psi H'y + mu (v + d)]
-            + Psi (mu I + H'H)^{-1} [H'y + mu Psi'(v + d)]
-        d = d - (w - v)
-    Returns {x = Psi' w, w, v, d, iter}.
-    """
-    tau = lam / (2.0 * mu)
+    The augmented Lagrangian adds mu ||w - v - d||^2.  Start (Algorithm 1):
+    d = 0, w = Psi H'y, unless ``state`` continues an earlier run.
+    Returns {x = Psi' w, w, v, d, iter}."""
     if state is None:
         w = psi(Hy)
         d = np.zeros_like(w)
@@ -272,11 +292,13 @@ def admm_synthesis(Hy: np.ndarray, fac: BlockFactor, lam: float, mu: float, iter
         k0 = int(state.get("iter", 0))
     PsiHy = psi(Hy)
     for k in range(iters):
-        v = soft(w - d, tau)
-        q = PsiHy + mu * (v + d)
-        frame_part = (q - psi(psi_adj(q))) / mu
-        w = frame_part + psi(fac.solve(Hy + mu * psi_adj(v + d), mu))
-        d = d - (w - v)
+        # v: lam ||v||_1 + mu ||v - (w - d)||^2
+        v = prox_l1(w - d, lam, mu)
+        # w: ||y - H Psi' w||^2 + mu ||w - (v + d)||^2 has the normal equations
+        # (Psi H'H Psi' + mu I) w = Psi H'y + mu (v + d)
+        w = tight_frame_system_solve(PsiHy + mu * (v + d), fac, mu, psi, psi_adj)
+        # scaled dual of the constraint v = w
+        d = d + (v - w)
         if callback is not None:
             callback(k0 + k + 1, psi_adj(w))
         if callback_w is not None:

@@ -231,6 +231,21 @@ def test_tv_system_solve(rng, nt):
     np.testing.assert_allclose(ev, np.sort(rho + 2 - 2 * np.cos(np.pi * np.arange(nt) / nt)), atol=1e-12)
 
 
+@pytest.mark.parametrize("nt", [1, 2, 5, 16])
+def test_tv_normal_solve_dense(rng, nt):
+    """(a D'D + b I) m = r, with D'D formed from the printed D_t by dense
+    matrix products (the fixture of eq. TV extended to nt frames)."""
+    a, b = 2.5, 0.3
+    Dm = np.zeros((nt - 1, nt))
+    for t in range(nt - 1):
+        Dm[t, t], Dm[t, t + 1] = -1.0, 1.0
+    r = crandn(rng, nt, 3)
+    m = O.tv_normal_solve(r, a, b)
+    np.testing.assert_allclose((a * Dm.T @ Dm + b * np.eye(nt)) @ m, r, atol=1e-12)
+    # the Algorithm 2 form divided through by mu_1 is the same system
+    np.testing.assert_allclose(O.tv_system_solve(r, b / a), a * m, atol=1e-12)
+
+
 def test_tdft_unitary_and_bruteforce(rng):
     nt = 6
     z = crandn(rng, nt, 2)
@@ -447,6 +462,18 @@ def test_resume_equals_uninterrupted(rng):
     b = O.admm_synthesis(Hy, fac, 0.01, 0.1, 20, state=b)
     for k in ("x", "w", "v", "d"):
         np.testing.assert_allclose(a[k], b[k], atol=1e-15)
+
+
+def test_delta_literal_values():
+    """Delta(k) = (J(k-1) - J(k)) / J(k) (eq. r_ratio) on literal values: the
+    numerator is the drop from the previous to the current objective and the
+    denominator is the current one, so a rise gives a negative ratio."""
+    assert O.delta(3.0, 2.0) == 0.5                 # drop of 1 over J(k) = 2 (not over J(k-1) = 3)
+    assert O.delta(2.0, 3.0) == -1.0 / 3.0          # J rises: negative
+    assert O.delta(5.0, 5.0) == 0.0
+    assert O.delta(1.001, 1.0) == pytest.approx(0.001, rel=1e-12)
+    # sign and denominator: (J(k) - J(k-1)) / J(k) or a division by J(k-1) both fail here
+    assert O.delta(4.0, 1.0) == 3.0
 
 
 def test_delta_and_objective_decrease():
