@@ -97,9 +97,20 @@ enum {
                                         (COLUMN_RESIDENT, XU_WAVE, XU_GROUP) have no effect.  Results
                                         agree with the packed inverse to rounding, not bit for bit.
                                         The eigendecomposition is rocSOLVER's batched zheevd, on the
-                                        plan's stream; its failure is CS_EDEVICE.  Its FP64 workspace
-                                        comes from the plan's allocator; rocBLAS allocates its own
-                                        internal workspace with hipMalloc, once per plan build. */
+                                        plan's stream; its failure is CS_EDEVICE.  Its FP64 matrices and
+                                        the library's own device workspace (sized by rocBLAS's size
+                                        query) both come from the plan's allocator and are released
+                                        before cs_plan_create returns; the rocBLAS handle runs on that
+                                        caller-allocated workspace (CS_EDEVICE if it would not). */
+  CS_FLAG_CHECK_FINITE = 1u << 6,    /* reject non-finite inputs with CS_EINVAL before any work: the
+                                        coil maps (cs_plan_create), the sampled rows of y (cs_apply_AH,
+                                        cs_admm_solve, cs_admm_solve_until, cs_batch_solve,
+                                        cs_admm_forward_ckpt; unsampled rows are ignored as always),
+                                        x (cs_apply_A), b (cs_apply_block_inverse) and grad_x
+                                        (cs_admm_backward).  lambda and mu are checked whatever the
+                                        flags.  Each check reads one int back and synchronises the
+                                        stream, so a checked call cannot be recorded under stream
+                                        capture (CS_EINVAL). */
 };
 
 /* Device-memory allocator used for everything the plan owns.  alloc returns
@@ -154,8 +165,11 @@ int cs_plan_bytes(const cs_plan* plan, size_t* bytes);
  * element of y; rows ky that frame t does not sample are set to zero. */
 int cs_apply_A(cs_plan* plan, const cs_c64* x, cs_c64* y, cs_stream stream);
 
-/* x = H' y: x_t = sum_c conj(s_c) . F' M_t y_{t,c}.  Reads only the sampled
- * rows of y (other rows are ignored and may hold anything). */
+/* x = H' y, the adjoint of cs_apply_A (H' = S' F~' of the stacked operator
+ * H = F~ S, Sec. II-A, eqs. H_1, S, F; H'y is the initial x of Algorithm 2
+ * and the constant part of every x-update, Sec. IV-B):
+ * x_t = sum_c conj(s_c) . F' M_t y_{t,c}.  Reads only the sampled rows of y
+ * (other rows are ignored and may hold anything). */
 int cs_apply_AH(cs_plan* plan, const cs_c64* y, cs_c64* x, cs_stream stream);
 
 /* x = (mu I + H'H)^{-1} b with the plan's mu (eq. eigen_mu), b and x images
@@ -218,7 +232,10 @@ int cs_plan_tune(cs_plan* plan, const cs_c64* y, float lambda, int32_t iters, cs
                  int32_t cap, int32_t* count, cs_stream stream);
 
 /* The paper's stopping rule (Sec. V, eq. r_ratio): iterate until
- * Delta(k) = (J(k-1) - J(k)) / J(k) < tol, or max_iters iterations.  Delta is
+ * |Delta(k)| < tol, Delta(k) = (J(k-1) - J(k)) / J(k), or max_iters
+ * iterations.  The magnitude is compared because ADMM does not decrease J
+ * monotonically: a check at which J rose by more than tol does not stop the
+ * solve (tol <= 0 never stops it before max_iters).  Delta is
  * checked every `check_every` iterations (J is evaluated at the last two
  * iterations of each block of check_every, or at every iteration when
  * check_every == 1, J(0) being taken at the initial iterate), so the solve
@@ -315,9 +332,11 @@ int cs_admm_backward(cs_grad* grad, const cs_c64* grad_x, cs_c64* grad_y, float*
  * the solve's stream (0 stops; either call clears the accumulated times).
  * cs_kernel_times waits for those events and fills up to `max` records, one
  * per kernel kind, with the number of launches and their summed device time;
- * *count receives the number of kinds seen.  Kinds: "tv_step", "dft_step",
- * "x_update", "objective" (phase-kernel form) and "column_solve" (one launch
- * running all iterations, one workgroup per readout column).  Event records add a few microseconds of host
+ * *count receives the number of kinds seen.  Kinds: "tv_step", "dft_step"
+ * (also the frame prior's step), "x_update", "objective", "frame_finish" (the
+ * pass that completes the frame prior's w and d before each objective
+ * evaluation) (phase-kernel form) and "column_solve" (one launch running all
+ * iterations, one workgroup per readout column).  Event records add a few microseconds of host
  * work per launch and nothing to the kernels themselves. */
 typedef struct {
   char name[24];

@@ -27,6 +27,7 @@ CS_FLAG_COLUMN_RESIDENT = 1 << 2
 CS_FLAG_XU_WAVE = 1 << 3
 CS_FLAG_XU_GROUP = 1 << 4
 CS_FLAG_EIGEN = 1 << 5
+CS_FLAG_CHECK_FINITE = 1 << 6
 
 # every function declared in include/csmri.h
 EXPORTED = (

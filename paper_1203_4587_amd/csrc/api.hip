@@ -70,8 +70,8 @@ static void plan_release(cs_plan* p) {
   delete p;
 }
 
-static constexpr uint32_t kAllFlags =
-    CS_FLAG_NO_REFACTOR | CS_FLAG_GRAPH | CS_FLAG_COLUMN_RESIDENT | CS_FLAG_XU_WAVE | CS_FLAG_XU_GROUP | CS_FLAG_EIGEN;
+static constexpr uint32_t kAllFlags = CS_FLAG_NO_REFACTOR | CS_FLAG_GRAPH | CS_FLAG_COLUMN_RESIDENT |
+                                      CS_FLAG_XU_WAVE | CS_FLAG_XU_GROUP | CS_FLAG_EIGEN | CS_FLAG_CHECK_FINITE;
 
 static int validate_flags(uint32_t f) {
   if (f & ~kAllFlags) return set_error(CS_EINVAL, "unknown flag bits");
@@ -99,8 +99,10 @@ static int validate_desc(const cs_plan_desc* d) {
 static inline hipStream_t S(cs_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
 // ---------------------------------------------------------------- timing
-enum KernelKind { kKindTV = 0, kKindDFT = 1, kKindX = 2, kKindJ = 3, kKindColumn = 4, kKinds = 5 };
-static const char* kKindNames[kKinds] = {"tv_step", "dft_step", "x_update", "objective", "column_solve"};
+enum KernelKind { kKindTV = 0, kKindDFT = 1, kKindX = 2, kKindJ = 3, kKindColumn = 4, kKindFrameFinish = 5,
+                  kKinds = 6 };
+static const char* kKindNames[kKinds] = {"tv_step", "dft_step", "x_update", "objective", "column_solve",
+                                         "frame_finish"};
 
 static hipEvent_t pool_event(cs_plan* p) {
   if (p->pool_next == p->event_pool.size()) {
@@ -128,13 +130,21 @@ static int timed_launch(cs_plan* p, int kind, hipStream_t s, F launch) {
 static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
                           const float2* wgiven, hipStream_t s, bool cont = false);
 
-// CS_FLAG_GRAPH: the phase-kernel loop is captured once per distinct
-// (iters, lambda, mu, J_trace, wgiven) and replayed from the plan's cache
+// CS_FLAG_GRAPH: the phase-kernel loop is captured once per distinct key and
+// replayed from the plan's cache.  The key holds everything the recorded
+// launches bake in: iters, lambda, mu, J_trace, wgiven, the FFT tiles of the
+// objective's SENSE pass and, for the overcomplete frame prior, whether the
+// first pass starts from a completed w (after a set-up or an objective
+// evaluation) or from the deferred state an iteration leaves.
 static int run_phase_graph(cs_plan* p, int32_t iters, float lambda, float mu, float* J_trace,
                            const float2* wgiven, hipStream_t s) {
   float lm[2] = {lambda, mu};
+  const bool frame = p->desc.prior == CS_PRIOR_TEMPORAL_FRAME;
+  const intptr_t tiles = (intptr_t)(((uint64_t)(uint32_t)p->fft_cw << 32) | (uint32_t)p->fft_rb);
   void* key[8] = {reinterpret_cast<void*>((intptr_t)iters), nullptr, J_trace, const_cast<float2*>(wgiven),
-                  reinterpret_cast<void*>((intptr_t)(wgiven != nullptr)), nullptr, nullptr, nullptr};
+                  reinterpret_cast<void*>((intptr_t)(wgiven != nullptr)),
+                  reinterpret_cast<void*>((intptr_t)(frame && p->frame_w_ready ? 1 : 0)),
+                  reinterpret_cast<void*>(tiles), nullptr};
   std::memcpy(&key[1], lm, sizeof(lm));
   if (!p->graph || std::memcmp(key, p->graph_key, sizeof(key)) != 0) {
     if (p->graph) {
@@ -212,7 +222,7 @@ static int run_phase_loop(cs_plan* p, int32_t iters, float lambda, float mu, flo
       if (st == CS_OK && J_trace) {
         // J(k) is taken at w_k (eq. L1unconst), which the next pass would
         // otherwise complete in registers: complete it (and d_k) here
-        st = launch_frame_finish(p, s);
+        st = timed_launch(p, kKindFrameFinish, s, [&] { return launch_frame_finish(p, s); });
         p->frame_w_ready = true;
       }
     } else {
@@ -254,7 +264,8 @@ static int solve_setup(cs_plan* p, const cs_c64* y, float mu, const cs_state* st
                        hipStream_t s) {
   const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
   const bool warm = state && state->iter > 0;
-  int st = CS_OK;
+  int st = check_finite_kspace(p, reinterpret_cast<const float2*>(y), s, "y");
+  if (st != CS_OK) return st;
   if (p->desc.flags & CS_FLAG_EIGEN) {
     p->mu = mu;  // the eigen form takes mu at apply time
   } else if (mu != p->mu) {
@@ -547,7 +558,8 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
       (st = plan_alloc(p, &p->s3, nimg, "state")) ||
       (st = plan_alloc(p, &p->img_tmp, ncoef, "image workspace")) ||
       (st = plan_alloc(p, &p->jpart, (size_t)objective_partial_count(), "objective partials")) ||
-      (st = plan_alloc(p, &p->jdev, 2, "objective values")))
+      (st = plan_alloc(p, &p->jdev, 2, "objective values")) ||
+      (st = plan_alloc(p, &p->check_flag, 1, "check flag")))
     return fail(st);
   p->jpart_len = objective_partial_count();
 
@@ -566,6 +578,8 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
   UP(p->dft_frags, hfrag.data(), hfrag.size() * sizeof(float));
   UP(p->tv_frags, htfrag.data(), htfrag.size() * sizeof(float));
 #undef UP
+  if ((st = check_finite_values(p, reinterpret_cast<const float2*>(coil), npix * nc, s, "coil")) != CS_OK)
+    return fail(st);
   // coil maps [c][j][i] -> column-major [c][i][j]
   if ((st = launch_transpose(reinterpret_cast<const float2*>(coil), p->coil_cm, nc, nv, nh, s)) != CS_OK)
     return fail(st);
@@ -633,16 +647,22 @@ int cs_plan_bytes(const cs_plan* plan, size_t* bytes) {
   return CS_OK;
 }
 
+static size_t image_values(const cs_plan* p) { return (size_t)p->desc.nv * p->desc.nh * p->desc.nt; }
+
 int cs_apply_A(cs_plan* p, const cs_c64* x, cs_c64* y, cs_stream stream) {
   if (!p || !x || !y) return set_error(CS_EINVAL, "plan, x and y must not be NULL");
   CS_HIP(hipSetDevice(p->device));
+  int st = check_finite_values(p, reinterpret_cast<const float2*>(x), image_values(p), S(stream), "x");
+  if (st != CS_OK) return st;
   return launch_forward(p, reinterpret_cast<const float2*>(x), false, reinterpret_cast<float2*>(y), S(stream));
 }
 
 int cs_apply_AH(cs_plan* p, const cs_c64* y, cs_c64* x, cs_stream stream) {
   if (!p || !x || !y) return set_error(CS_EINVAL, "plan, x and y must not be NULL");
   CS_HIP(hipSetDevice(p->device));
-  int st = launch_adjoint_rows(p, reinterpret_cast<const float2*>(y), S(stream));
+  int st = check_finite_kspace(p, reinterpret_cast<const float2*>(y), S(stream), "y");
+  if (st != CS_OK) return st;
+  st = launch_adjoint_rows(p, reinterpret_cast<const float2*>(y), S(stream));
   if (st != CS_OK) return st;
   return launch_adjoint_image(p, reinterpret_cast<float2*>(x), false, S(stream));
 }
@@ -652,7 +672,8 @@ int cs_apply_block_inverse(cs_plan* p, const cs_c64* b, cs_c64* x, cs_stream str
   CS_HIP(hipSetDevice(p->device));
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
   hipStream_t s = S(stream);
-  int st = launch_transpose(reinterpret_cast<const float2*>(b), p->img_tmp, nt, nv, nh, s);
+  int st = check_finite_values(p, reinterpret_cast<const float2*>(b), image_values(p), s, "b");
+  if (st == CS_OK) st = launch_transpose(reinterpret_cast<const float2*>(b), p->img_tmp, nt, nv, nh, s);
   if (st == CS_OK) st = launch_xupdate(p, kSolvePlain, p->img_tmp, nullptr, nullptr, p->img_tmp, p->mu, s);
   if (st == CS_OK) st = launch_transpose(p->img_tmp, reinterpret_cast<float2*>(x), nt, nh, nv, s);
   return st;
@@ -725,7 +746,10 @@ int cs_admm_solve_until(cs_plan* p, const cs_c64* y, float lambda, float mu, int
     const double j0 = have_j0 ? p->jhost[0] : jprev, j1 = p->jhost[1];
     jprev = p->jhost[1];
     last_delta = (j0 - j1) / j1;
-    stop = last_delta < (double)tol;
+    // converged when the relative change of J is small either way: ADMM does
+    // not decrease J monotonically, and a block in which J rose by more than
+    // tol is not a stall
+    stop = std::fabs(last_delta) < (double)tol;
   }
   if (st != CS_OK) return st;
   *iters_done = k;
@@ -737,13 +761,17 @@ int cs_admm_solve_until(cs_plan* p, const cs_c64* y, float lambda, float mu, int
 
 // ---------------------------------------------------------------- flags and tuning
 
-static void set_plan_flags(cs_plan* p, uint32_t flags) {
-  if (flags == p->desc.flags) return;
-  if (p->graph) {  // the cached graph holds the kernels of the old form
-    (void)hipDeviceSynchronize();
+static void drop_graph(cs_plan* p) {
+  if (p->graph) {
+    (void)hipDeviceSynchronize();  // the cached graph may still run
     (void)hipGraphExecDestroy(p->graph);
     p->graph = nullptr;
   }
+}
+
+static void set_plan_flags(cs_plan* p, uint32_t flags) {
+  if (flags == p->desc.flags) return;
+  drop_graph(p);  // the cached graph holds the kernels of the old form
   p->desc.flags = flags;
 }
 
@@ -859,9 +887,10 @@ int cs_plan_tune(cs_plan* p, const cs_c64* y, float lambda, int32_t iters, cs_tu
     return set_error(CS_EDEVICE, "hipEventCreate failed");
   }
   int st = tune_fft_tiles(p, y, s, e0, e1);
-  // a fresh start on y: state in the plan's workspaces, x written to img_tmp
-  if (st == CS_OK)
-    st = cs_admm_solve(p, y, lambda, p->mu, 0, reinterpret_cast<cs_c64*>(p->img_tmp), nullptr, nullptr, stream);
+  // a fresh start on y: the algorithm's initial state in the plan's
+  // workspaces (no image is written out, so img_tmp keeps the frame prior's w_0)
+  const float2* wgiven = nullptr;
+  if (st == CS_OK) st = solve_setup(p, y, p->mu, nullptr, &wgiven, s);
   if (st != CS_OK) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -878,7 +907,11 @@ int cs_plan_tune(cs_plan* p, const cs_c64* y, float lambda, int32_t iters, cs_tu
     for (size_t i = 0; i < cand.size(); ++i) {
       set_plan_flags(p, keep | cand[i] | (original & ~(forms | keep)));
       used[i] = p->desc.flags;
-      if ((st = run_iterations(p, iters, lambda, p->mu, nullptr, nullptr, s)) != CS_OK) break;  // warm-up
+      // two untimed runs: the first may start from the set-up's state, which
+      // the frame prior's first pass records differently, so the timed run
+      // replays the graph the second one recorded
+      if ((st = run_iterations(p, iters, lambda, p->mu, nullptr, nullptr, s)) != CS_OK) break;
+      if ((st = run_iterations(p, iters, lambda, p->mu, nullptr, nullptr, s)) != CS_OK) break;
       hipError_t e = hipEventRecord(e0, s);
       if (e == hipSuccess) st = run_iterations(p, iters, lambda, p->mu, nullptr, nullptr, s);
       if (e == hipSuccess && st == CS_OK) e = hipEventRecord(e1, s);
@@ -905,6 +938,8 @@ int cs_plan_tune(cs_plan* p, const cs_c64* y, float lambda, int32_t iters, cs_tu
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   set_plan_flags(p, st == CS_OK ? best : original);
+  // the cached graph was recorded mid-solve, from the tuning runs' state
+  drop_graph(p);
   if (count) *count = n;
   return st;
 }
@@ -994,6 +1029,10 @@ int cs_batch_solve(cs_batch* b, const cs_c64* const* y, const float* lambda, int
   }
   CS_HIP(hipSetDevice(b->plans[0]->device));
   hipStream_t s = S(stream);
+  for (size_t i = 0; i < n; ++i) {
+    const int st = check_finite_kspace(b->plans[i], reinterpret_cast<const float2*>(y[i]), s, "y");
+    if (st != CS_OK) return set_error(st, "slice " + std::to_string(i) + ": " + g_last_error);
+  }
   std::vector<const void*> key;
   key.push_back(reinterpret_cast<const void*>((intptr_t)iters));
   for (size_t i = 0; i < n; ++i) {
@@ -1003,6 +1042,14 @@ int cs_batch_solve(cs_batch* b, const cs_c64* const* y, const float* lambda, int
     key.push_back(x_out[i]);
     key.push_back(reinterpret_cast<const void*>((intptr_t)lb));
     key.push_back(reinterpret_cast<const void*>((intptr_t)b->plans[i]->desc.flags));
+    // a slice's plan may be used on its own in between: a solve at another mu
+    // refactors it (the recorded kernels carry mu), and new FFT tiles change
+    // the recorded SENSE launches
+    uint32_t mb;
+    std::memcpy(&mb, &b->plans[i]->mu, sizeof(mb));
+    key.push_back(reinterpret_cast<const void*>((intptr_t)mb));
+    key.push_back(reinterpret_cast<const void*>((intptr_t)b->plans[i]->fft_cw));
+    key.push_back(reinterpret_cast<const void*>((intptr_t)b->plans[i]->fft_rb));
   }
   if (!b->graph || key != b->key) {
     if (b->graph) {
@@ -1042,7 +1089,8 @@ int cs_batch_solve(cs_batch* b, const cs_c64* const* y, const float* lambda, int
       const bool saved_timing = p->timing;
       const uint32_t saved_flags = p->desc.flags;
       p->timing = false;
-      p->desc.flags &= ~(uint32_t)CS_FLAG_GRAPH;  // recorded straight into the batch graph
+      // recorded straight into the batch graph; y was checked above
+      p->desc.flags &= ~(uint32_t)(CS_FLAG_GRAPH | CS_FLAG_CHECK_FINITE);
       st = cs_admm_solve(p, y[i], lambda[i], p->mu, iters, x_out[i], nullptr, nullptr, b->streams[i]);
       p->timing = saved_timing;
       p->desc.flags = saved_flags;

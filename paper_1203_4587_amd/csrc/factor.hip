@@ -288,8 +288,10 @@ int build_factor_eigen(cs_plan* p, hipStream_t s) {
   double* dv = static_cast<double*>(p->alloc.get(chunk * 2 * (size_t)n * sizeof(double)));
   rocblas_int* info = static_cast<rocblas_int*>(p->alloc.get(std::max<size_t>(chunk * sizeof(rocblas_int), 256)));
   rocblas_handle h = nullptr;
+  void* lib_ws = nullptr;  // the solver's internal workspace, also from the plan's allocator
   auto done = [&](int status) {
     if (h) (void)rocblas_destroy_handle(h);
+    if (lib_ws) p->alloc.put(lib_ws);
     if (ws) p->alloc.put(ws);
     if (dv) p->alloc.put(dv);
     if (info) p->alloc.put(info);
@@ -302,6 +304,27 @@ int build_factor_eigen(cs_plan* p, hipStream_t s) {
     return done(rocsolver_fail(r, "rocblas_create_handle"));
   }
   if ((r = rocblas_set_stream(h, s)) != rocblas_status_success) return done(rocsolver_fail(r, "rocblas_set_stream"));
+  // the solver's device workspace: its size for the largest chunk comes from
+  // rocBLAS's size query (no kernel runs in query mode), the memory from the
+  // plan's allocator, and the handle is switched to that user-owned workspace
+  // so that it allocates none of its own
+  {
+    if ((r = rocblas_start_device_memory_size_query(h)) != rocblas_status_success)
+      return done(rocsolver_fail(r, "rocblas_start_device_memory_size_query"));
+    (void)rocsolver_zheevd_strided_batched(h, rocblas_evect_original, rocblas_fill_lower, n,
+                                           reinterpret_cast<rocblas_double_complex*>(ws), n, (rocblas_stride)nn,
+                                           dv, n, dv + (size_t)chunk * n, n, info, (rocblas_int)chunk);
+    size_t lib_bytes = 0;
+    if ((r = rocblas_stop_device_memory_size_query(h, &lib_bytes)) != rocblas_status_success)
+      return done(rocsolver_fail(r, "rocblas_stop_device_memory_size_query"));
+    lib_bytes = std::max<size_t>(lib_bytes, 256);
+    lib_ws = p->alloc.get(lib_bytes);
+    if (!lib_ws) return done(set_error(CS_ENOMEM, "allocator returned NULL for the eigensolver's library workspace"));
+    if ((r = rocblas_set_workspace(h, lib_ws, lib_bytes)) != rocblas_status_success)
+      return done(rocsolver_fail(r, "rocblas_set_workspace"));
+    if (rocblas_is_managing_device_memory(h))
+      return done(set_error(CS_EDEVICE, "the rocBLAS handle did not take the caller-allocated workspace"));
+  }
   const int wg = round_up(n, 64);
   std::vector<rocblas_int> hinfo(chunk);
   for (size_t b0 = 0; b0 < nblocks; b0 += chunk) {

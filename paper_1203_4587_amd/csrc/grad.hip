@@ -271,7 +271,8 @@ int cs_admm_forward_ckpt(cs_grad* g, const cs_c64* y, float lambda, float mu, cs
   CS_HIP(hipSetDevice(p->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   g->ready = false;
-  int st = ensure_mu(p, mu, s);
+  int st = check_finite_kspace(p, reinterpret_cast<const float2*>(y), s, "y");
+  if (st == CS_OK) st = ensure_mu(p, mu, s);
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
   const size_t n = g->nimg;
   const float2 zero = make_float2(0.f, 0.f);
@@ -344,7 +345,9 @@ int cs_admm_backward(cs_grad* g, const cs_c64* grad_x, cs_c64* grad_y, float* gr
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const float lambda = g->lambda, mu = g->mu, rho = p->desc.mu_ratio;
   const float tau = lambda * rho / (2.0f * mu);  // as the forward step computes it
-  int st = ensure_mu(p, mu, s);
+  int st = check_finite_values(p, reinterpret_cast<const float2*>(grad_x),
+                               (size_t)p->desc.nv * p->desc.nh * p->desc.nt, s, "grad_x");
+  if (st == CS_OK) st = ensure_mu(p, mu, s);
   if (st != CS_OK) return st;
   if (g->dft) return dft_backward(g, grad_x, grad_y, grad_lambda_mu, s);
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;

@@ -186,6 +186,8 @@ struct cs_plan {
   double* jpart = nullptr;      // objective partial sums
   float* jdev = nullptr;        // [2] objective values read back by the Delta-driven solve
   float* jhost = nullptr;       // [2] pinned host copy (hipHostMalloc, on first use)
+  int* check_flag = nullptr;    // CS_FLAG_CHECK_FINITE: set to 1 by a check that meets a non-finite value
+  size_t column_lds_attr = 0;   // dynamic LDS size enabled for this plan's column-resident kernel
   int jpart_len = 0;
 
   hipGraphExec_t graph = nullptr;  // cached iteration graph
@@ -228,6 +230,10 @@ int launch_adjoint_rows(cs_plan* p, const float2* y, hipStream_t s);  // y -> p-
 int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nblocks, hipStream_t s);
 int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s);  // p->ktmp -> x
 int launch_transpose(const float2* in, float2* out, int frames, int rows, int cols, hipStream_t s);
+// CS_FLAG_CHECK_FINITE (no-ops without it): CS_EINVAL if the sampled rows of
+// k-space y, or the n values at x, hold a NaN or an infinity; synchronise s
+int check_finite_kspace(cs_plan* p, const float2* y, hipStream_t s, const char* what);
+int check_finite_values(cs_plan* p, const float2* x, size_t n, hipStream_t s, const char* what);
 int fft_cols_per_group(const cs_plan* p);
 int fft_cols_limit(const cs_plan* p);
 int fft_rows_per_group(const cs_plan* p);

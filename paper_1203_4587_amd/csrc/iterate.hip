@@ -1116,11 +1116,12 @@ __global__ __launch_bounds__(512) void k_column_solve(ColumnSolveArgs a) {
 
 template <int PRIOR, int NT, int RP>
 static int column_launch_rp(cs_plan* p, const ColumnSolveArgs& a, int threads, size_t lds, hipStream_t s) {
-  static size_t lds_set = 0;  // largest dynamic LDS size enabled so far for this instantiation
-  if (lds > 65536 && lds > lds_set) {
+  // a plan launches one instantiation on one device; the attribute is set on
+  // that device the first time this plan needs more than the default
+  if (lds > 65536 && lds > p->column_lds_attr) {
     CS_HIP(hipFuncSetAttribute((const void*)k_column_solve<PRIOR, NT, RP>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    lds_set = lds;
+    p->column_lds_attr = lds;
   }
   hipLaunchKernelGGL((k_column_solve<PRIOR, NT, RP>), dim3(p->desc.nh), dim3(threads), lds, s, a);
   CS_HIP(hipGetLastError());

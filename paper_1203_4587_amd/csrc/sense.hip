@@ -385,4 +385,70 @@ int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s) 
   return CS_OK;
 }
 
+// ---------------------------------------------------------------- finite-value checks
+//
+// CS_FLAG_CHECK_FINITE: an input holding a NaN or an infinity is rejected
+// before any work.  Each kernel stores 1 into *flag when it meets one (every
+// writer stores the same value, so the stores need no ordering).
+
+// one workgroup per sampled line (t, c, r): the rows of k-space a solve reads
+__global__ void k_nonfinite_rows(const float2* __restrict__ y, const int32_t* __restrict__ rows, int mrow, int nc,
+                                 int nv, int nh, int* __restrict__ flag) {
+  const int line = blockIdx.x;  // (t * nc + c) * mrow + r
+  const int r = line % mrow, tc = line / mrow, t = tc / nc;
+  const int ky = rows[(size_t)t * mrow + r];
+  if (ky < 0) return;
+  const float2* src = y + ((size_t)tc * nv + ky) * nh;
+  bool bad = false;
+  for (int i = threadIdx.x; i < nh; i += blockDim.x) {
+    const float2 v = src[i];
+    bad |= !(isfinite(v.x) && isfinite(v.y));
+  }
+  if (bad) *flag = 1;
+}
+
+__global__ void k_nonfinite(const float2* __restrict__ x, size_t n, int* __restrict__ flag) {
+  bool bad = false;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 v = x[i];
+    bad |= !(isfinite(v.x) && isfinite(v.y));
+  }
+  if (bad) *flag = 1;
+}
+
+// clears *flag, runs the check, reads the flag back (synchronises s)
+template <typename F>
+static int run_finite_check(cs_plan* p, hipStream_t s, const char* what, F launch) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  CS_HIP(hipStreamIsCapturing(s, &cap));
+  if (cap != hipStreamCaptureStatusNone)
+    return set_error(CS_EINVAL, "CS_FLAG_CHECK_FINITE reads its result back and cannot run under stream capture");
+  CS_HIP(hipMemsetAsync(p->check_flag, 0, sizeof(int), s));
+  launch();
+  CS_HIP(hipGetLastError());
+  int h = 0;
+  CS_HIP(hipMemcpyAsync(&h, p->check_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  CS_HIP(hipStreamSynchronize(s));
+  if (h) return set_error(CS_EINVAL, std::string(what) + " holds a non-finite value (CS_FLAG_CHECK_FINITE)");
+  return CS_OK;
+}
+
+int check_finite_kspace(cs_plan* p, const float2* y, hipStream_t s, const char* what) {
+  if (!(p->desc.flags & CS_FLAG_CHECK_FINITE) || p->m_max == 0) return CS_OK;
+  const int mrow = std::max(p->m_max, 1);
+  const unsigned lines = (unsigned)((size_t)p->desc.nt * p->desc.nc * mrow);
+  return run_finite_check(p, s, what, [&] {
+    hipLaunchKernelGGL(k_nonfinite_rows, dim3(lines), dim3(256), 0, s, y, p->rows, mrow, p->desc.nc, p->desc.nv,
+                       p->desc.nh, p->check_flag);
+  });
+}
+
+int check_finite_values(cs_plan* p, const float2* x, size_t n, hipStream_t s, const char* what) {
+  if (!(p->desc.flags & CS_FLAG_CHECK_FINITE) || n == 0) return CS_OK;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  return run_finite_check(p, s, what, [&] {
+    hipLaunchKernelGGL(k_nonfinite, dim3(blocks), dim3(256), 0, s, x, n, p->check_flag);
+  });
+}
+
 }  // namespace csmri

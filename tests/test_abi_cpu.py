@@ -118,7 +118,7 @@ def test_eigen_plan_asks_first_for_both_eigenvector_copies(lib):
 def test_header_flag_values_match_the_binding():
     text = open(os.path.join(ROOT, "include", "csmri.h")).read()
     found = dict(re.findall(r"\b(CS_FLAG_[A-Z_]+)\s*=\s*1u\s*<<\s*(\d+)", text))
-    assert "CS_FLAG_EIGEN" in found and len(found) == 6
+    assert "CS_FLAG_CHECK_FINITE" in found and len(found) == 7
     for name, bit in found.items():
         assert getattr(_lib, name) == 1 << int(bit), name
 

@@ -116,6 +116,35 @@ def test_batch_with_per_slice_forms():
         assert torch.equal(xs[k], plain[k]), k
 
 
+def test_batch_replays_after_a_slice_plan_solved_at_another_mu():
+    """A slice's plan used on its own at another mu refactors in place; the
+    next batch solve must record again with that mu (the recorded kernels carry
+    mu) and equal a plain plan built with it.  New FFT tiles re-record too."""
+    from paper_1203_4587_amd.api import Plan
+    cases = _small_cases()
+    batch, ys, dev = _batch(cases)
+    iters = 10
+    xs = batch.solve(ys, LAMS, iters)           # records with mu = MU
+    torch.cuda.synchronize()
+    mu2 = 0.37
+    for k in (0, 1):
+        batch.plan(k).solve(ys[k], LAMS[k], 3, mu=mu2)   # refactors slice k's plan for mu2
+    xs = batch.solve(ys, LAMS, iters)
+    for k in range(len(SMALL)):
+        coil, mask, y = dev[k]
+        mu_k = mu2 if k in (0, 1) else MU
+        plain = Plan(coil, mask, mu_k, prior=SMALL[k][1], mu_ratio=RHO).solve(y, LAMS[k], iters)
+        assert torch.equal(xs[k], plain), k
+    case = cases[0]
+    ref = O.solve(case.y, case.coil, case.mask, SMALL[0][1], LAMS[0], mu2, RHO, iters)
+    assert rel_l2(xs[0].cpu().numpy(), ref["x"]) < TOL
+    cw, rb = batch.plan(2).fft_tiles
+    batch.plan(2).fft_tiles = (max(1, cw // 2), max(1, rb // 2))
+    xs2 = batch.solve(ys, LAMS, iters)
+    for k in range(len(SMALL)):
+        assert torch.equal(xs2[k], xs[k]), k
+
+
 @pytest.mark.parametrize("shape,prior", [((128, 16, 16, 3), "tv"), ((192, 12, 24, 3), "dft"),
                                          ((12, 8, 6, 2), "tv"), ((256, 8, 8, 2), "dft"),
                                          # two blocks per wave (n = 64, 192), odd block counts
