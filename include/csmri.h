@@ -172,6 +172,26 @@ int cs_apply_A(cs_plan* plan, const cs_c64* x, cs_c64* y, cs_stream stream);
  * (other rows are ignored and may hold anything). */
 int cs_apply_AH(cs_plan* plan, const cs_c64* y, cs_c64* x, cs_stream stream);
 
+/* cs_apply_AH without a plan, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): x = H'y for the operator that desc (nv, nh, nt, nc; prior,
+ * mu_ratio and flags are ignored), coil [nc][nv][nh] and mask [nt][nv] define,
+ * with the same layouts, conventions and kernels as cs_apply_AH.  It makes no
+ * allocation and no host round trip: every intermediate (the sampled-row
+ * tables built on the device from mask, the twiddles, the coil maps in
+ * column-major order, the hybrid-space rows and the column-major image of a
+ * chunk of frames) lives in one fixed 64 MiB device array of the library,
+ * which each GPU the call runs on holds until the process ends.  Frames are
+ * processed in chunks that fit it; the tables, the coil maps and one frame
+ * must fit (about 8 nv nh (2 nc + 1) bytes), else CS_EUNSUPPORTED.  Runs on
+ * the current device.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, two threads) race and give undefined
+ * results; calls ordered on one stream are safe.  Nothing left in the array by
+ * an earlier call is read.  Errors: CS_EINVAL (NULL pointer, size < 1),
+ * CS_EUNSUPPORTED (sizes as for cs_plan_create, or beyond the array). */
+int cs_apply_AH_noalloc(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* mask, const cs_c64* y,
+                        cs_c64* x, cs_stream stream);
+
 /* x = (mu I + H'H)^{-1} b with the plan's mu (eq. eigen_mu), b and x images
  * [nt][nv][nh]; x may alias b.  The plan's mu is the one it was created with,
  * or the mu of its latest solve or forward pass if that one differed (a

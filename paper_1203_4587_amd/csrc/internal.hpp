@@ -229,6 +229,14 @@ int launch_adjoint_rows(cs_plan* p, const float2* y, hipStream_t s);  // y -> p-
 // sum |M_t F_v (s_c . x) - ktmp|^2, one FP64 partial per workgroup of an nblocks grid (x column-major)
 int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nblocks, hipStream_t s);
 int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s);  // p->ktmp -> x
+// the two adjoint passes on explicit buffers (the plan launchers above call
+// these): hyb is [nt][nc][nh][m_max], rows [nt][m_max] padded with -1, mcnt
+// [nt] (rows r >= mcnt[t] are neither written nor read), x column-major
+int launch_adjoint_rows_raw(const float2* y, float2* hyb, const int32_t* rows, const int32_t* mcnt, const FftDesc& fh,
+                            const float2* twh, int nv, int nh, int nt, int nc, int m_max, int rb, hipStream_t s);
+int launch_adjoint_vertical_raw(const float2* hyb, const float2* coil_cm, float2* x, const int32_t* rows,
+                                const int32_t* mcnt, const FftDesc& fv, const float2* twv, int nv, int nh, int nt,
+                                int nc, int m_max, int cw, hipStream_t s);
 int launch_transpose(const float2* in, float2* out, int frames, int rows, int cols, hipStream_t s);
 // CS_FLAG_CHECK_FINITE (no-ops without it): CS_EINVAL if the sampled rows of
 // k-space y, or the n values at x, hold a NaN or an infinity; synchronise s

@@ -360,27 +360,41 @@ int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nbloc
   return CS_OK;
 }
 
-int launch_adjoint_rows(cs_plan* p, const float2* y, hipStream_t s) {
-  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
-  if (p->m_max == 0) return CS_OK;
-  const int rb = fft_rows_per_group(p);
+int launch_adjoint_rows_raw(const float2* y, float2* hyb, const int32_t* rows, const int32_t* mcnt, const FftDesc& fh,
+                            const float2* twh, int nv, int nh, int nt, int nc, int m_max, int rb, hipStream_t s) {
   const size_t lds = (size_t)(nh + rb * (nh + 1)) * sizeof(float2);
-  dim3 g(ceil_div(p->m_max, rb), nt, nc);
-  hipLaunchKernelGGL(k_adj_horizontal, g, dim3(kFftThreads), lds, s, y, p->ktmp, p->rows, p->mcnt,
-                     p->fft_h, p->tw_h, nv, nh, nc, p->m_max, rb, 1.0f / std::sqrt((float)nh));
+  dim3 g(ceil_div(m_max, rb), nt, nc);
+  hipLaunchKernelGGL(k_adj_horizontal, g, dim3(kFftThreads), lds, s, y, hyb, rows, mcnt, fh, twh, nv, nh, nc,
+                     m_max, rb, 1.0f / std::sqrt((float)nh));
   CS_HIP(hipGetLastError());
   return CS_OK;
 }
 
-int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s) {
-  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
-  const int cw = fft_cols_per_group(p);
-  float2* xo = x_colmajor ? x : p->img_tmp;
+int launch_adjoint_vertical_raw(const float2* hyb, const float2* coil_cm, float2* x, const int32_t* rows,
+                                const int32_t* mcnt, const FftDesc& fv, const float2* twv, int nv, int nh, int nt,
+                                int nc, int m_max, int cw, hipStream_t s) {
   auto k = cw * nv <= 256 ? k_adj_vertical<256> : k_adj_vertical<512>;
-  hipLaunchKernelGGL(k, dim3(vertical_grid(p, cw)), dim3(64 * kVWaves), vertical_lds(p, cw), s, p->ktmp,
-                     p->coil_cm, xo, p->rows, p->mcnt, p->fft_v, p->tw_v, nv, nh, nt, nc, p->m_max, cw,
-                     1.0f / std::sqrt((float)nv));
+  const size_t units = (size_t)nt * ceil_div(nh, cw);
+  const unsigned grid = (unsigned)std::min<size_t>((units + kVWaves - 1) / kVWaves, 65535);
+  const size_t lds = (size_t)(nv + kVWaves * cw * nv) * sizeof(float2);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kVWaves), lds, s, hyb, coil_cm, x, rows, mcnt, fv, twv, nv, nh, nt,
+                     nc, m_max, cw, 1.0f / std::sqrt((float)nv));
   CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
+int launch_adjoint_rows(cs_plan* p, const float2* y, hipStream_t s) {
+  if (p->m_max == 0) return CS_OK;
+  return launch_adjoint_rows_raw(y, p->ktmp, p->rows, p->mcnt, p->fft_h, p->tw_h, p->desc.nv, p->desc.nh,
+                                 p->desc.nt, p->desc.nc, p->m_max, fft_rows_per_group(p), s);
+}
+
+int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s) {
+  const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
+  float2* xo = x_colmajor ? x : p->img_tmp;
+  int st = launch_adjoint_vertical_raw(p->ktmp, p->coil_cm, xo, p->rows, p->mcnt, p->fft_v, p->tw_v, nv, nh, nt,
+                                       p->desc.nc, p->m_max, fft_cols_per_group(p), s);
+  if (st != CS_OK) return st;
   if (!x_colmajor) return launch_transpose(p->img_tmp, x, nt, nh, nv, s);
   return CS_OK;
 }
