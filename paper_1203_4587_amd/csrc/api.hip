@@ -3,6 +3,8 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <new>
 
 #include "internal.hpp"
@@ -38,6 +40,20 @@ void DeviceAlloc::put(void* ptr) {
   } else {
     (void)hipFree(ptr);
   }
+}
+
+int ensure_dynamic_lds(const void* kernel, size_t bytes) {
+  if (bytes <= 65536) return CS_OK;
+  int dev = 0;
+  CS_HIP(hipGetDevice(&dev));
+  static std::mutex mutex;
+  static std::map<std::pair<const void*, int>, size_t> enabled;
+  std::lock_guard<std::mutex> lock(mutex);
+  size_t& have = enabled[{kernel, dev}];
+  if (have >= bytes) return CS_OK;
+  CS_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  have = bytes;
+  return CS_OK;
 }
 
 int objective_partial_count();

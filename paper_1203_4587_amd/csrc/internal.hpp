@@ -125,6 +125,18 @@ int hip_fail(hipError_t e, const char* what);
     hipError_t _e = (expr);                            \
     if (_e != hipSuccess) return hip_fail(_e, #expr);  \
   } while (0)
+// returns from the enclosing function on a cs_status other than CS_OK
+#define CS_HIP_STATUS(expr)             \
+  do {                                  \
+    const int _st = (expr);             \
+    if (_st != CS_OK) return _st;       \
+  } while (0)
+
+// Raise `kernel`'s dynamic-LDS limit on the current device to at least
+// `bytes` when they exceed the default 64 KiB.  The attribute belongs to a
+// (kernel, device) pair, so the sizes already set are kept per pair in a
+// mutex-guarded table; repeated calls cost a lookup.
+int ensure_dynamic_lds(const void* kernel, size_t bytes);
 
 // ---------------------------------------------------------------- plan
 struct DeviceAlloc {
@@ -187,7 +199,6 @@ struct cs_plan {
   float* jdev = nullptr;        // [2] objective values read back by the Delta-driven solve
   float* jhost = nullptr;       // [2] pinned host copy (hipHostMalloc, on first use)
   int* check_flag = nullptr;    // CS_FLAG_CHECK_FINITE: set to 1 by a check that meets a non-finite value
-  size_t column_lds_attr = 0;   // dynamic LDS size enabled for this plan's column-resident kernel
   int jpart_len = 0;
 
   hipGraphExec_t graph = nullptr;  // cached iteration graph

@@ -246,13 +246,119 @@ __device__ __forceinline__ void xupdate_wave_block(const float2* __restrict__ W,
   __builtin_amdgcn_wave_barrier();
 }
 
-template <int MODE, int UNR, int RP>
+// The same wave-per-block solve with n a compile-time constant N, the only
+// sizes the phase form runs it at being N = 128, 256, 384, 512 (N/2 row pairs
+// fill RP = N/128 lanes per wave exactly).  Every guard then disappears: the
+// chunks of UNR diagonals tile s = 0 .. F-1 (F = N/2, a multiple of UNR) with
+// diagonal 0 peeled into the first one, and the right-hand side is staged
+// twice in LDS (b[k] = b[k + N]) so that b_{k+s} and b_{k-s} (mod N) are read
+// at k + s and k - s + N without a wrap, as pairs with constant offsets.  The
+// FMAs and their order are those of xupdate_wave_block, so the results are
+// bit-identical.  LDS: 2N right-hand side values, UNR N staged diagonals.
+template <int MODE, int N, int UNR>
+struct WaveSolveN {
+  static constexpr int H = N / 2, F = N / 2, RP = N / 128, NCH = F / UNR;
+  static_assert(N % 128 == 0 && F % UNR == 0, "wave solve sizes");
+  static constexpr size_t kLdsValues = (size_t)(2 + UNR) * N;
+
+  static __device__ __forceinline__ void load(float4 (&c)[UNR][RP], const float2* __restrict__ W,
+                                               const FactorLayout& L, size_t blk, int s0, int lane) {
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int r = 0; r < RP; ++r) c[u][r] = ld_stream4(W + diag_offset(L, blk, s0 + u) + 2 * (lane + 64 * r));
+  }
+
+  // diagonals s0 .. s0 + UNR - 1 (FIRST: s0 = 0, whose diagonal 0 starts the sums)
+  template <bool FIRST>
+  static __device__ __forceinline__ void apply(const float4 (&c)[UNR][RP], int s0, int lane, const float2* bsh,
+                                                float2* dsh, float2 (&a0)[RP], float2 (&a1)[RP]) {
+#pragma unroll
+    for (int u = FIRST ? 1 : 0; u < UNR; ++u)
+#pragma unroll
+      for (int r = 0; r < RP; ++r) *reinterpret_cast<float4*>(dsh + u * N + 2 * (lane + 64 * r)) = c[u][r];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int k0 = 2 * (lane + 64 * r);
+      const float2* bp = bsh + k0 + s0;                  // b_{k0+s} = bp[u]
+      const float2* bm = bsh + k0 + N - s0 - (UNR - 1);  // b_{k0-s} = bm[UNR - 1 - u]
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        if (FIRST && u == 0) {
+          a0[r] = cmul(make_float2(c[0][r].x, c[0][r].y), bp[0]);
+          a1[r] = cmul(make_float2(c[0][r].z, c[0][r].w), bp[1]);
+          continue;
+        }
+        const int s = s0 + u;
+        const float2* d = dsh + u * N;
+        int q0 = k0 - s, q1 = k0 + 1 - s;
+        q0 += q0 < 0 ? N : 0;
+        q1 += q1 < 0 ? N : 0;
+        a0[r] = cfma(make_float2(c[u][r].x, c[u][r].y), bp[u], a0[r]);
+        a1[r] = cfma(make_float2(c[u][r].z, c[u][r].w), bp[u + 1], a1[r]);
+        a0[r] = cfmac(d[q0], bm[UNR - 1 - u], a0[r]);
+        a1[r] = cfmac(d[q1], bm[UNR - u], a1[r]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+
+  static __device__ __forceinline__ void solve(const float2* __restrict__ W, const FactorLayout& L, size_t blk,
+                                                int lane, float2* bsh, float2* dsh, const float2* hy,
+                                                const float2* __restrict__ m, float2* __restrict__ d2, float2* x,
+                                                float mu) {
+    const size_t base = blk * (size_t)N;
+    float4 A[UNR][RP], B[UNR][RP];
+    load(A, W, L, blk, 0, lane);
+    float2 m0[RP], m1[RP], e0[RP], e1[RP], a0[RP], a1[RP];
+    // a previous block's epilogue of this wave may still be reading bsh; the
+    // wave executes in order, so a compiler barrier is all that is needed
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int q = lane + 64 * r;
+      const float2 b0 = rhs_value<MODE>(hy, m, d2, base + 2 * q, mu, m0[r], e0[r]);
+      const float2 b1 = rhs_value<MODE>(hy, m, d2, base + 2 * q + 1, mu, m1[r], e1[r]);
+      const float4 bb = make_float4(b0.x, b0.y, b1.x, b1.y);
+      *reinterpret_cast<float4*>(bsh + 2 * q) = bb;
+      *reinterpret_cast<float4*>(bsh + N + 2 * q) = bb;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // chunk c covers s = c UNR .. c UNR + UNR - 1: A holds the even chunks and
+    // B the odd ones, the next chunk's loads in flight during this one's work
+    if (NCH > 1) load(B, W, L, blk, UNR, lane);
+    apply<true>(A, 0, lane, bsh, dsh, a0, a1);
+    for (int c = 1; c + 1 < NCH; c += 2) {
+      load(A, W, L, blk, (c + 1) * UNR, lane);
+      apply<false>(B, c * UNR, lane, bsh, dsh, a0, a1);
+      if (c + 2 < NCH) load(B, W, L, blk, (c + 2) * UNR, lane);
+      apply<false>(A, (c + 1) * UNR, lane, bsh, dsh, a0, a1);
+    }
+    if (NCH % 2 == 0) apply<false>(B, (NCH - 1) * UNR, lane, bsh, dsh, a0, a1);
+    const float2* hd = W + half_offset(L, blk);
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      const int k0 = 2 * (lane + 64 * r), k1 = k0 + 1;
+      a0[r] = k0 < H ? cfma(hd[k0], bsh[k0 + H], a0[r]) : cfmac(hd[k0 - H], bsh[k0 - H], a0[r]);
+      a1[r] = k1 < H ? cfma(hd[k1], bsh[k1 + H], a1[r]) : cfmac(hd[k1 - H], bsh[k1 - H], a1[r]);
+      *reinterpret_cast<float4*>(x + base + k0) = make_float4(a0[r].x, a0[r].y, a1[r].x, a1[r].y);
+      if (MODE == kSolveTV)
+        *reinterpret_cast<float4*>(d2 + base + k0) =
+            make_float4(e0[r].x - (m0[r].x - a0[r].x), e0[r].y - (m0[r].y - a0[r].y),
+                        e1[r].x - (m1[r].x - a1[r].x), e1[r].y - (m1[r].y - a1[r].y));
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+};
+
+template <int MODE, int N, int UNR>
 __global__ __launch_bounds__(64) void k_xupdate_wave(const float2* __restrict__ W, FactorLayout L, ColRange cr,
                                                      const float2* hy, const float2* __restrict__ m,
                                                      float2* __restrict__ d2, float2* x, float mu) {
   extern __shared__ float2 lds[];
-  xupdate_wave_block<MODE, UNR, RP>(W, L, range_block(cr, blockIdx.x), threadIdx.x, lds, lds + L.n, hy, m, d2, x,
-                                    mu);
+  WaveSolveN<MODE, N, UNR>::solve(W, L, range_block(cr, blockIdx.x), threadIdx.x, lds, lds + 2 * N, hy, m, d2, x,
+                                  mu);
 }
 
 // Odd n: lane k owns row k; the rotated c_s[k-s] is re-read from the same
@@ -296,15 +402,24 @@ constexpr int kXUnrollCol = 4;  // diagonals per chunk, column-resident solve (8
 // row pairs per lane: nv/2 pairs over 64 lanes
 inline int pairs_per_lane(int n) { return ((n >> 1) + 63) / 64; }
 
-template <int MODE, int RP>
+// diagonals per chunk of the compile-time-n wave solve: 2.  Measured at n = 256
+// (256x256x32 blocks, one box, two interleaved rounds): 355.1-356.8 us with 2,
+// 358.9-359.9 us with 4 and 356.2-358.9 us with 8, against 363.4-365.5 us for
+// the run-time-n form above; a loads-only stream of the same factor layout
+// takes 308.7-309.3 us.  Neither loading the half diagonal with the first
+// chunk nor persistent waves that prefetch the next block changed the time.
+template <int N>
+constexpr int wave_unroll() { return 2; }
+
+template <int MODE, int N>
 static void xupdate_wave_launch(cs_plan* p, const ColRange& cr, const float2* hy, const float2* m, float2* d2,
                                 float2* x, float mu, hipStream_t s) {
-  const FactorLayout& L = p->flayout;
-  constexpr int UNR = kXUnroll;
-  const size_t lds = (size_t)(1 + UNR) * L.n * sizeof(float2);
+  constexpr int UNR = wave_unroll<N>();
+  using K = WaveSolveN<MODE, N, UNR>;
+  const size_t lds = K::kLdsValues * sizeof(float2);
   const unsigned grid = (unsigned)cr.w * (unsigned)p->desc.nt;
-  hipLaunchKernelGGL((k_xupdate_wave<MODE, UNR, RP>), dim3(grid), dim3(64), lds, s, p->factor, L, cr, hy, m, d2, x,
-                     mu);
+  hipLaunchKernelGGL((k_xupdate_wave<MODE, N, UNR>), dim3(grid), dim3(64), lds, s, p->factor, p->flayout, cr, hy,
+                     m, d2, x, mu);
 }
 
 template <int MODE>
@@ -314,12 +429,15 @@ static void xupdate_launch(cs_plan* p, const ColRange& cr, const float2* hy, con
   const int n = L.n;
   const uint32_t f = p->desc.flags;
   const unsigned grid = (unsigned)cr.w * (unsigned)p->desc.nt;
-  const bool wave = (n & 1) == 0 && !(f & CS_FLAG_XU_GROUP) && ((f & CS_FLAG_XU_WAVE) || (n / 2) % 64 == 0);
+  // the wave form runs at n = 128, 256, 384, 512 (n/2 a multiple of 64); the
+  // workgroup form covers every other even n (n = 64 and 192 normally take the
+  // two-blocks-per-wave form before reaching here)
+  const bool wave = n % 128 == 0 && !(f & CS_FLAG_XU_GROUP);
   if (wave) {
-    const int rp = pairs_per_lane(n);
-    if (rp == 1) xupdate_wave_launch<MODE, 1>(p, cr, hy, m, d2, x, mu, s);
-    else if (rp == 2) xupdate_wave_launch<MODE, 2>(p, cr, hy, m, d2, x, mu, s);
-    else xupdate_wave_launch<MODE, 4>(p, cr, hy, m, d2, x, mu, s);
+    if (n == 128) xupdate_wave_launch<MODE, 128>(p, cr, hy, m, d2, x, mu, s);
+    else if (n == 256) xupdate_wave_launch<MODE, 256>(p, cr, hy, m, d2, x, mu, s);
+    else if (n == 384) xupdate_wave_launch<MODE, 384>(p, cr, hy, m, d2, x, mu, s);
+    else xupdate_wave_launch<MODE, 512>(p, cr, hy, m, d2, x, mu, s);
   } else if ((n & 1) == 0) {
     const int wg = (std::max(n / 2, 1) + 63) / 64 * 64;
     const size_t lds = (size_t)(1 + kXUnroll) * n * sizeof(float2);
@@ -582,12 +700,7 @@ static int dft_tiles_launch(cs_plan* p, const float2* in, float2* d, float2* v, 
   const size_t pix0 = (size_t)i0 * p->desc.nv, pix1 = (size_t)i1 * p->desc.nv;
   const int waves = dft_waves(KP);
   const size_t lds = dft_lds_bytes(KP, waves);
-  static bool attr = false;
-  if (lds > 65536 && !attr) {
-    CS_HIP(hipFuncSetAttribute((const void*)k_dft_tiles<KP, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    attr = true;
-  }
+  CS_HIP_STATUS(ensure_dynamic_lds((const void*)k_dft_tiles<KP, MODE>, lds));
   const size_t ntiles = (pix1 - pix0 + 15) / 16;
   // one tile per wave where the grid fits on the chip at once (the grid-stride
   // loop covers larger images)
@@ -654,6 +767,13 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
   const int col = lane & 15, grp = lane >> 4;
   const bool pv = col < count;
   const size_t p = p0 + col;
+  // every stream is requested up front (x and d2 are first needed for r):
+  // one memory round trip per tile instead of two.  Measured at 256x256x32
+  // (one box, three interleaved rounds): 24.4-24.6 us against 25.6-26.1 us
+  // with x and d2 loaded after the shrink; a 16-pixel tile per wave stays
+  // best (two tiles per wave with the next tile's loads issued inside the
+  // current one: 26.2 us at 178 VGPRs)
+  float2 xv[NK], zv[NK];
   // m -> buf0, d1 -> buf1 (rows t, 16 pixels)
   {
     float2 mv[NK], dv[NK];
@@ -664,6 +784,14 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
       const size_t o = (size_t)t * npix + p;
       mv[k] = ok ? m[o] : make_float2(0.f, 0.f);
       dv[k] = (ok && t < nt - 1) ? d1[o] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = grp + 4 * k;
+      const bool ok = t < nt && pv;
+      const size_t o = (size_t)t * npix + p;
+      xv[k] = ok ? x[o] : make_float2(0.f, 0.f);
+      zv[k] = ok ? d2[o] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
@@ -696,15 +824,6 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
   float* bre = reinterpret_cast<float*>(buf0);
   float* bim = bre + KT * 16;
   {
-    float2 xv[NK], zv[NK];
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      const int t = grp + 4 * k;
-      const bool ok = t < nt && pv;
-      const size_t o = (size_t)t * npix + p;
-      xv[k] = ok ? x[o] : make_float2(0.f, 0.f);
-      zv[k] = ok ? d2[o] : make_float2(0.f, 0.f);
-    }
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
       const int t = grp + 4 * k;
@@ -777,11 +896,7 @@ static int tv_tiles_launch(cs_plan* p, float tau, float rho, int i0, int i1, hip
   const size_t pix0 = (size_t)i0 * p->desc.nv, pix1 = (size_t)i1 * p->desc.nv;
   constexpr int waves = 4;
   const size_t lds = ((size_t)DftTile<KT>::FRAG + (size_t)waves * tv_wave_floats(KT)) * sizeof(float);
-  static bool attr = false;
-  if (lds > 65536 && !attr) {
-    CS_HIP(hipFuncSetAttribute((const void*)k_tv_tiles<KT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr = true;
-  }
+  CS_HIP_STATUS(ensure_dynamic_lds((const void*)k_tv_tiles<KT>, lds));
   const size_t ntiles = (pix1 - pix0 + 15) / 16;
   const unsigned grid = (unsigned)std::min<size_t>((ntiles + waves - 1) / waves, 65535);
   hipLaunchKernelGGL(k_tv_tiles<KT>, dim3(grid), dim3(64 * waves), lds, s, p->tv_frags, p->s0, p->s1, p->s2, p->s3,
@@ -985,12 +1100,7 @@ static int frame_tiles_launch(cs_plan* p, const float2* xt, float2* u, float2* v
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
   const int waves = dft_waves(KP);
   const size_t lds = dft_lds_bytes(KP, waves);
-  static bool attr = false;
-  if (lds > 65536 && !attr) {
-    CS_HIP(hipFuncSetAttribute((const void*)k_frame_tiles<KP, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    attr = true;
-  }
+  CS_HIP_STATUS(ensure_dynamic_lds((const void*)k_frame_tiles<KP, MODE>, lds));
   const size_t ntiles = (npix + 15) / 16;
   const unsigned grid = (unsigned)std::min<size_t>((ntiles + waves - 1) / waves, 2048);
   hipLaunchKernelGGL((k_frame_tiles<KP, MODE>), dim3(grid), dim3(64 * waves), lds, s, p->dft_frags, xt, u, v, d, w,
@@ -1116,13 +1226,7 @@ __global__ __launch_bounds__(512) void k_column_solve(ColumnSolveArgs a) {
 
 template <int PRIOR, int NT, int RP>
 static int column_launch_rp(cs_plan* p, const ColumnSolveArgs& a, int threads, size_t lds, hipStream_t s) {
-  // a plan launches one instantiation on one device; the attribute is set on
-  // that device the first time this plan needs more than the default
-  if (lds > 65536 && lds > p->column_lds_attr) {
-    CS_HIP(hipFuncSetAttribute((const void*)k_column_solve<PRIOR, NT, RP>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    p->column_lds_attr = lds;
-  }
+  CS_HIP_STATUS(ensure_dynamic_lds((const void*)k_column_solve<PRIOR, NT, RP>, lds));
   hipLaunchKernelGGL((k_column_solve<PRIOR, NT, RP>), dim3(p->desc.nh), dim3(threads), lds, s, a);
   CS_HIP(hipGetLastError());
   return CS_OK;
@@ -1404,12 +1508,7 @@ static int tv_adjoint_launch(cs_plan* p, unsigned nblocks, float2* mb, float2* d
   constexpr int waves = 4;
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
   const size_t lds = ((size_t)DftTile<KT>::FRAG + (size_t)waves * tv_wave_floats(KT)) * sizeof(float);
-  static bool attr = false;
-  if (lds > 65536 && !attr) {
-    CS_HIP(hipFuncSetAttribute((const void*)k_tv_adjoint_tiles<KT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    attr = true;
-  }
+  CS_HIP_STATUS(ensure_dynamic_lds((const void*)k_tv_adjoint_tiles<KT>, lds));
   hipLaunchKernelGGL(k_tv_adjoint_tiles<KT>, dim3(nblocks), dim3(64 * waves), lds, s, p->tv_frags, mb, d1b, d2b, e,
                      bb, hyb, m, d1, d2n, partial, p->desc.nt, npix, tau, rho, mu, last);
   CS_HIP(hipGetLastError());
@@ -1565,12 +1664,7 @@ static int dft_adjoint_launch(cs_plan* p, unsigned nblocks, const float2* bb, fl
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
   const int waves = dft_waves(KP);
   const size_t lds = dft_lds_bytes(KP, waves);
-  static bool attr = false;
-  if (lds > 65536 && !attr) {
-    CS_HIP(hipFuncSetAttribute((const void*)k_dft_adjoint<KP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    attr = true;
-  }
+  CS_HIP_STATUS(ensure_dynamic_lds((const void*)k_dft_adjoint<KP>, lds));
   hipLaunchKernelGGL(k_dft_adjoint<KP>, dim3(nblocks), dim3(64 * waves), lds, s, p->dft_frags, bb, db, zb, hyb,
                      zprev, dprev, u, z, partial, p->desc.nt, npix, tau, mu, last);
   CS_HIP(hipGetLastError());
@@ -1688,12 +1782,7 @@ static int l1_dft_launch(cs_plan* p, const float2* x, double* part, hipStream_t 
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
   const int waves = dft_waves(KP);
   const size_t lds = dft_lds_bytes(KP, waves);
-  static bool attr = false;
-  if (lds > 65536 && !attr) {
-    CS_HIP(hipFuncSetAttribute((const void*)k_l1_dft_tiles<KP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    attr = true;
-  }
+  CS_HIP_STATUS(ensure_dynamic_lds((const void*)k_l1_dft_tiles<KP>, lds));
   hipLaunchKernelGGL(k_l1_dft_tiles<KP>, dim3(kJBlocks), dim3(64 * waves), lds, s, p->dft_frags, x, p->desc.nt, npix,
                      part);
   CS_HIP(hipGetLastError());
