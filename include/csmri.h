@@ -230,13 +230,15 @@ int cs_plan_set_flags(cs_plan* plan, uint32_t flags);
  * them.  0 selects the default: as many columns as fit 256 values (one when
  * nv > 256) and as many rows as fit 4096 values.  Larger values are clipped to
  * 512 values per column group and 4096 per row group.  Results do not depend
- * on them. */
+ * on them.  At nv = 256 the vertical passes, and at nh = 256 the horizontal
+ * ones, run length-256 register transforms with fixed tiles (4 columns per
+ * wave, 16 rows per workgroup) and ignore the corresponding value. */
 int cs_plan_fft_tiles(const cs_plan* plan, int32_t* cols, int32_t* rows);
 int cs_plan_set_fft_tiles(cs_plan* plan, int32_t cols, int32_t rows);
 
 /* Autotuner: first picks the FFT tiles (every pair from the largest tiles down
  * to 1/16 of their columns and 1/4 of their rows, timed on H'y of y plus the
- * vertical forward pass), then times `iters` iterations (after as many
+ * vertical forward pass; a value the passes ignore is not swept), then times `iters` iterations (after as many
  * untimed ones) of every execution form the plan supports -- phase form with
  * each x-update form (graph-replayed), and the column-resident form -- on the
  * data y, in three interleaved rounds, and keeps the form with the fastest

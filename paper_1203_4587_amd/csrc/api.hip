@@ -460,11 +460,14 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
     for (int j = 0; j < nv; ++j) p->h_mcnt[t] += hmask[(size_t)t * nv + j] != 0;
   p->m_max = *std::max_element(p->h_mcnt.begin(), p->h_mcnt.end());
   const int mrow = std::max(p->m_max, 1);
-  std::vector<int32_t> hrows((size_t)nt * mrow, -1);
+  std::vector<int32_t> hrows((size_t)nt * mrow, -1), hrinv((size_t)nt * nv, -1);
   for (int t = 0; t < nt; ++t) {
     int r = 0;
     for (int j = 0; j < nv; ++j)
-      if (hmask[(size_t)t * nv + j]) hrows[(size_t)t * mrow + r++] = j;
+      if (hmask[(size_t)t * nv + j]) {
+        hrinv[(size_t)t * nv + j] = r;
+        hrows[(size_t)t * mrow + r++] = j;
+      }
   }
   // FP64 first column of F_v' M_t F_v: p_t[l] = (1/nv) sum_{ky in Omega_t} exp(+2 pi i ky l / nv)
   std::vector<double2> hp((size_t)nt * nv);
@@ -557,6 +560,7 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
   const size_t ksz = (size_t)nt * nc * mrow * nh;
   if ((st = plan_alloc(p, &p->rows, hrows.size(), "rows")) ||
       (st = plan_alloc(p, &p->mcnt, (size_t)nt, "mcnt")) ||
+      (st = plan_alloc(p, &p->rinv, hrinv.size(), "rinv")) ||
       (st = plan_alloc(p, &p->mask, hmask.size(), "mask")) ||
       (st = plan_alloc(p, &p->pcol, hp.size(), "pcol")) ||
       (st = plan_alloc(p, &p->tw_v, (size_t)nv, "tw_v")) ||
@@ -586,6 +590,7 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
   } while (0)
   UP(p->rows, hrows.data(), hrows.size() * sizeof(int32_t));
   UP(p->mcnt, p->h_mcnt.data(), (size_t)nt * sizeof(int32_t));
+  UP(p->rinv, hrinv.data(), hrinv.size() * sizeof(int32_t));
   UP(p->mask, hmask.data(), hmask.size());
   UP(p->pcol, hp.data(), hp.size() * sizeof(double2));
   UP(p->tw_v, htwv.data(), htwv.size() * sizeof(float2));
@@ -828,6 +833,7 @@ int cs_plan_set_fft_tiles(cs_plan* p, int32_t cols, int32_t rows) {
 // workgroup) pair from the largest down to 1/16 (columns) and 1/4 (rows) of
 // it is timed on H'y of y (the adjoint passes) followed by the vertical
 // forward pass, which the objective uses; the fastest is kept in the plan.
+// The length-256 passes have fixed tiles, so a knob they ignore is not swept.
 static int tune_fft_tiles(cs_plan* p, const cs_c64* y, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int save_cw = p->fft_cw, save_rb = p->fft_rb;
   p->fft_cw = 0;
@@ -835,9 +841,10 @@ static int tune_fft_tiles(cs_plan* p, const cs_c64* y, hipStream_t s, hipEvent_t
   const int cw_default = fft_cols_per_group(p);
   const int cw_full = fft_cols_limit(p), rb_full = fft_rows_per_group(p);
   std::vector<int> cws, rbs;
-  for (int d = 1; d <= 16; d *= 2)
+  const int cw_div = p->desc.nv == 256 ? 1 : 16, rb_div = p->desc.nh == 256 ? 1 : 4;
+  for (int d = 1; d <= cw_div; d *= 2)
     if (cw_full / d >= 1 && (cws.empty() || cws.back() != cw_full / d)) cws.push_back(cw_full / d);
-  for (int d = 1; d <= 4; d *= 2)
+  for (int d = 1; d <= rb_div; d *= 2)
     if (rb_full / d >= 1 && (rbs.empty() || rbs.back() != rb_full / d)) rbs.push_back(rb_full / d);
   float best = -1.f;
   int bcw = cw_full, brb = rb_full, st = CS_OK;

@@ -165,4 +165,73 @@ __device__ __forceinline__ void fft_wave(float2* buf, const FftDesc& d, const fl
   fft_passes<SIGN, 64, WE, true>(buf, d, tw, nbatch, stride, lane);
 }
 
+// ---------------------------------------------------------------- register DFTs
+//
+// Length-16 DFT of values held by one lane, v[k] <- sum_n v[n] exp(SIGN 2 pi i
+// n k / 16), as 4 x 4 Cooley-Tukey: n = 4 n1 + n2, k = k1 + 4 k2.  Four
+// length-4 DFTs over n1, the twiddles exp(SIGN 2 pi i n2 k1 / 16), four
+// length-4 DFTs over n2; every index is a compile-time constant, so the whole
+// transform stays in registers.
+
+template <int SIGN>
+__device__ __forceinline__ void dft4_regs(float2& a, float2& b, float2& c, float2& d) {
+  const float2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = csub(b, d);
+  // (SIGN i) t3
+  const float2 wt3 = SIGN < 0 ? make_float2(t3.y, -t3.x) : make_float2(-t3.y, t3.x);
+  a = cadd(t0, t2);
+  b = cadd(t1, wt3);
+  c = csub(t0, t2);
+  d = csub(t1, wt3);
+}
+
+// exp(SIGN 2 pi i m / 16) * u for the m that occur (m = n2 k1 <= 9)
+template <int SIGN, int M>
+__device__ __forceinline__ float2 w16_mul(float2 u) {
+  constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;  // cos, sin (pi / 8)
+  constexpr float h = 0.70710678118654752440f;                                 // cos (pi / 4)
+  constexpr int m = M % 16;
+  // (c + SIGN i s) u with c = cos(2 pi m / 16), s = sin(2 pi m / 16)
+  auto rot = [](float2 v, float c, float sn) {
+    const float ss = SIGN < 0 ? -sn : sn;
+    return make_float2(fmaf(c, v.x, -(ss * v.y)), fmaf(c, v.y, ss * v.x));
+  };
+  if constexpr (m == 0) return u;
+  else if constexpr (m == 4) return SIGN < 0 ? make_float2(u.y, -u.x) : make_float2(-u.y, u.x);
+  else if constexpr (m == 8) return make_float2(-u.x, -u.y);
+  else if constexpr (m == 1) return rot(u, c1, s1);
+  else if constexpr (m == 2) return rot(u, h, h);
+  else if constexpr (m == 3) return rot(u, s1, c1);
+  else if constexpr (m == 6) return rot(u, -h, h);
+  else {
+    static_assert(m == 9, "twiddle index of the 4 x 4 split");
+    return rot(u, -c1, -s1);
+  }
+}
+
+template <int SIGN>
+__device__ __forceinline__ void dft16_regs(float2 (&v)[16]) {
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4_regs<SIGN>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+  // v[4 k1 + n2] now holds the length-4 DFT over n1 at frequency k1
+  v[5] = w16_mul<SIGN, 1>(v[5]);
+  v[6] = w16_mul<SIGN, 2>(v[6]);
+  v[7] = w16_mul<SIGN, 3>(v[7]);
+  v[9] = w16_mul<SIGN, 2>(v[9]);
+  v[10] = w16_mul<SIGN, 4>(v[10]);
+  v[11] = w16_mul<SIGN, 6>(v[11]);
+  v[13] = w16_mul<SIGN, 3>(v[13]);
+  v[14] = w16_mul<SIGN, 6>(v[14]);
+  v[15] = w16_mul<SIGN, 9>(v[15]);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4_regs<SIGN>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+  // v[4 k1 + k2] holds frequency k1 + 4 k2: reorder to natural order
+  float2 o[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = o[k];
+}
+
 }  // namespace csmri

@@ -165,6 +165,7 @@ struct cs_plan {
   std::vector<int32_t> h_mcnt;  // sampled rows per frame
   int32_t* rows = nullptr;      // [nt][m_max] sampled ky, padded with -1
   int32_t* mcnt = nullptr;      // [nt]
+  int32_t* rinv = nullptr;      // [nt][nv] r with rows[t][r] = ky, or -1 for an unsampled ky
   uint8_t* mask = nullptr;      // [nt][nv]
   double2* pcol = nullptr;      // [nt][nv] first column of F_v' M_t F_v (FP64)
 
@@ -245,9 +246,10 @@ int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s);
 // [nt] (rows r >= mcnt[t] are neither written nor read), x column-major
 int launch_adjoint_rows_raw(const float2* y, float2* hyb, const int32_t* rows, const int32_t* mcnt, const FftDesc& fh,
                             const float2* twh, int nv, int nh, int nt, int nc, int m_max, int rb, hipStream_t s);
+// rinv [nt][nv]: r of each sampled ky (-1 for the others), read by the nv = 256 kernels
 int launch_adjoint_vertical_raw(const float2* hyb, const float2* coil_cm, float2* x, const int32_t* rows,
-                                const int32_t* mcnt, const FftDesc& fv, const float2* twv, int nv, int nh, int nt,
-                                int nc, int m_max, int cw, hipStream_t s);
+                                const int32_t* mcnt, const int32_t* rinv, const FftDesc& fv, const float2* twv,
+                                int nv, int nh, int nt, int nc, int m_max, int cw, hipStream_t s);
 int launch_transpose(const float2* in, float2* out, int frames, int rows, int cols, hipStream_t s);
 // CS_FLAG_CHECK_FINITE (no-ops without it): CS_EINVAL if the sampled rows of
 // k-space y, or the n values at x, hold a NaN or an infinity; synchronise s

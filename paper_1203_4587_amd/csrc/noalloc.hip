@@ -49,17 +49,32 @@ static int scratch_address(int device, unsigned char** out) {
 // to nv, and their count.  Block nt: the twiddles exp(-2 pi i q / n) of both
 // axes, rounded from FP64 as the plan's tables are.
 __global__ void k_noalloc_tables(const uint8_t* __restrict__ mask, int32_t* __restrict__ rows,
-                                 int32_t* __restrict__ mcnt, float2* __restrict__ tw_v, float2* __restrict__ tw_h,
-                                 int nv, int nh, int nt) {
+                                 int32_t* __restrict__ mcnt, int32_t* __restrict__ rinv, float2* __restrict__ tw_v,
+                                 float2* __restrict__ tw_h, int nv, int nh, int nt) {
   const int t = blockIdx.x;
   if (t < nt) {
-    if (threadIdx.x != 0) return;
+    // every entry starts at -1 (all threads), then one thread walks the mask
+    // in order and stores only for sampled rows.  (Written this way on
+    // purpose: a form that selected "sampled ? r : -1" inside the one-thread
+    // loop was compiled into a scalar select on an unrelated condition flag,
+    // which left r in the entries of unsampled rows.)
     int32_t* rw = rows + (size_t)t * nv;
+    int32_t* ri = rinv + (size_t)t * nv;
+    for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+      rw[j] = -1;
+      ri[j] = -1;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     int r = 0;
-    for (int j = 0; j < nv; ++j)
-      if (mask[(size_t)t * nv + j]) rw[r++] = j;
+    for (int j = 0; j < nv; ++j) {
+      if (mask[(size_t)t * nv + j]) {
+        ri[j] = r;
+        rw[r] = j;
+        ++r;
+      }
+    }
     mcnt[t] = r;
-    for (int q = r; q < nv; ++q) rw[q] = -1;
     return;
   }
   for (int q = threadIdx.x; q < nv; q += blockDim.x) {
@@ -77,7 +92,7 @@ static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 // Byte layout of `scratch` for one call; frames_per_chunk == 0 means the
 // sizes do not fit.
 struct NoallocLayout {
-  size_t rows, mcnt, tw_v, tw_h, coil, hyb, img;
+  size_t rows, mcnt, rinv, tw_v, tw_h, coil, hyb, img;
   size_t need;           // bytes for the tables, the coil maps and one frame
   int frames_per_chunk;
 };
@@ -89,6 +104,8 @@ static NoallocLayout noalloc_layout(int nv, int nh, int nt, int nc) {
   off += align256((size_t)nt * nv * sizeof(int32_t));
   L.mcnt = off;
   off += align256((size_t)nt * sizeof(int32_t));
+  L.rinv = off;
+  off += align256((size_t)nt * nv * sizeof(int32_t));
   L.tw_v = off;
   off += align256((size_t)nv * sizeof(float2));
   L.tw_h = off;
@@ -131,12 +148,14 @@ extern "C" int cs_apply_AH_noalloc(const cs_plan_desc* desc, const cs_c64* coil,
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   auto* rows = reinterpret_cast<int32_t*>(base + L.rows);
   auto* mcnt = reinterpret_cast<int32_t*>(base + L.mcnt);
+  auto* rinv = reinterpret_cast<int32_t*>(base + L.rinv);
   auto* tw_v = reinterpret_cast<float2*>(base + L.tw_v);
   auto* tw_h = reinterpret_cast<float2*>(base + L.tw_h);
   auto* coil_cm = reinterpret_cast<float2*>(base + L.coil);
   auto* hyb = reinterpret_cast<float2*>(base + L.hyb);
   auto* img = reinterpret_cast<float2*>(base + L.img);
-  hipLaunchKernelGGL(k_noalloc_tables, dim3(nt + 1), dim3(256), 0, s, mask, rows, mcnt, tw_v, tw_h, nv, nh, nt);
+  hipLaunchKernelGGL(k_noalloc_tables, dim3(nt + 1), dim3(256), 0, s, mask, rows, mcnt, rinv, tw_v, tw_h, nv, nh,
+                     nt);
   CS_HIP(hipGetLastError());
   // coil maps [c][j][i] -> column-major [c][i][j]
   if ((st = launch_transpose(reinterpret_cast<const float2*>(coil), coil_cm, nc, nv, nh, s)) != CS_OK) return st;
@@ -151,8 +170,8 @@ extern "C" int cs_apply_AH_noalloc(const cs_plan_desc* desc, const cs_c64* coil,
     if ((st = launch_adjoint_rows_raw(yc, hyb, rows + (size_t)t0 * nv, mcnt + t0, fh, tw_h, nv, nh, f, nc, nv, rb,
                                       s)) != CS_OK)
       return st;
-    if ((st = launch_adjoint_vertical_raw(hyb, coil_cm, img, rows + (size_t)t0 * nv, mcnt + t0, fv, tw_v, nv, nh, f,
-                                          nc, nv, cw, s)) != CS_OK)
+    if ((st = launch_adjoint_vertical_raw(hyb, coil_cm, img, rows + (size_t)t0 * nv, mcnt + t0, rinv + (size_t)t0 * nv,
+                                          fv, tw_v, nv, nh, f, nc, nv, cw, s)) != CS_OK)
       return st;
     if ((st = launch_transpose(img, reinterpret_cast<float2*>(x) + (size_t)t0 * iframe, f, nh, nv, s)) != CS_OK)
       return st;

@@ -24,9 +24,12 @@ def _plan(case, mu=0.1, prior="tv"):
 
 
 # (nv, nh, nt, nc): radix-2/4 powers, radix-3 mixes, odd sizes (3^b), tiny and
-# ragged shapes that leave partial column tiles in the FFT kernels
+# ragged shapes that leave partial column tiles in the FFT kernels; nv = 256
+# and nh = 256 take the 16 x 16 register transforms (with fewer sampled rows
+# than one row tile, and with a ragged last tile of rows or columns)
 SHAPES = [(64, 64, 8, 4), (96, 128, 3, 2), (192, 96, 2, 3), (27, 12, 3, 2), (6, 4, 2, 1),
-          (256, 48, 2, 2), (128, 81, 2, 5), (512, 8, 2, 1), (8, 512, 2, 1)]
+          (256, 48, 2, 2), (128, 81, 2, 5), (512, 8, 2, 1), (8, 512, 2, 1), (48, 256, 3, 2),
+          (256, 256, 2, 3), (256, 18, 3, 2)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=[f"{a}x{b}x{c}x{d}" for a, b, c, d in SHAPES])
@@ -53,14 +56,15 @@ def test_forward_and_adjoint_match_oracle(shape):
     plan.close()
 
 
-def test_frame_without_samples_and_full_frames():
+@pytest.mark.parametrize("nv,nh", [(32, 16), (256, 256)], ids=str)
+def test_frame_without_samples_and_full_frames(nv, nh):
     from paper_1203_4587_amd.api import to_device
-    case = make_case(32, 16, 4, 3, accel=4, ncenter=2, seed=3)
+    case = make_case(nv, nh, 4, 3, accel=4, ncenter=2, seed=3)
     case.mask[1] = 0
     case.mask[2] = 1
     plan = _plan(case)
     rng = np.random.default_rng(1)
-    x = c64(rng.standard_normal((4, 32, 16)) + 1j * rng.standard_normal((4, 32, 16)))
+    x = c64(rng.standard_normal((4, nv, nh)) + 1j * rng.standard_normal((4, nv, nh)))
     y = plan.apply_A(to_device(x)).cpu().numpy()
     assert rel_l2(y, O.forward(x, case.coil, case.mask)) < 1e-5
     assert np.all(y[1] == 0)
