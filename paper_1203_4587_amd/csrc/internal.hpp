@@ -238,8 +238,10 @@ int launch_dft_adjoint(cs_plan* p, unsigned nblocks, const float2* bb, float2* d
 // the same solve (the temporal DFT step completes the previous deferred update)
 int run_iterations_cont(cs_plan* p, int32_t iters, float lambda, float mu, bool cont, hipStream_t s);
 int launch_adjoint_rows(cs_plan* p, const float2* y, hipStream_t s);  // y -> p->ktmp
-// sum |M_t F_v (s_c . x) - ktmp|^2, one FP64 partial per workgroup of an nblocks grid (x column-major)
-int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nblocks, hipStream_t s);
+// sum |M_t F_v (s_c . x) - ktmp|^2, one FP64 partial per workgroup of an nblocks grid (x column-major);
+// tv_lambda > 0 adds tv_lambda * sum_{t < nt-1} |x[t + 1] - x[t]| (the temporal-TV l1) to the partials
+int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nblocks, float tv_lambda,
+                            hipStream_t s);
 int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s);  // p->ktmp -> x
 // the two adjoint passes on explicit buffers (the plan launchers above call
 // these): hyb is [nt][nc][nh][m_max], rows [nt][m_max] padded with -1, mcnt

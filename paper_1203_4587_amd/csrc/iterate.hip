@@ -1694,8 +1694,11 @@ int launch_dft_adjoint(cs_plan* p, unsigned nblocks, const float2* bb, float2* d
 // hybrid (ky, i) space: F_h is unitary, so the data term equals
 // sum_{t,c,r,i} |(M_t F_v (s_c . x))[r, i] - (F_h' y)[r, i]|^2 over sampled
 // rows r.  l1 = sum |D_t x| (TV), sum |Psi x| (DFT) or, for the overcomplete
-// frame, sum |w| over the completed coefficients (moduli of complex values).  Partial sums are FP64 and reduced in a fixed order, so the value
-// is bit-reproducible run to run.
+// frame, sum |w| over the completed coefficients (moduli of complex values).
+// For TV the data-term pass adds lambda |D_t x| to its own partials (it holds
+// the image values anyway); the other priors have an l1 kernel of their own.
+// Partial sums are FP64 and reduced in a fixed order, so the value is
+// bit-reproducible run to run.
 constexpr int kJBlocks = 1024;
 constexpr int kJThreads = 256;
 
@@ -1708,18 +1711,6 @@ __device__ __forceinline__ void block_reduce_store(double v, double* out) {
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = red[0];
-}
-
-__global__ __launch_bounds__(kJThreads) void k_l1_tv_partial(const float2* __restrict__ x, int nt, size_t npix,
-                                                             double* __restrict__ part) {
-  const size_t total = (size_t)(nt - 1) * npix;
-  double acc = 0.0;
-  for (size_t q = (size_t)blockIdx.x * kJThreads + threadIdx.x; q < total; q += (size_t)kJBlocks * kJThreads) {
-    const float2 a = x[q + npix], b = x[q];
-    const double dx = (double)a.x - b.x, dy = (double)a.y - b.y;
-    acc += sqrt(dx * dx + dy * dy);
-  }
-  block_reduce_store(acc, part + blockIdx.x);
 }
 
 // l1 of the coefficients w themselves (overcomplete frame prior: 2 nt frames)
@@ -1789,18 +1780,20 @@ static int l1_dft_launch(cs_plan* p, const float2* x, double* part, hipStream_t 
   return CS_OK;
 }
 
-// J = lambda * l1 + data from the two halves of the partials: each of the
+// J = lambda * l1 + data from the two halves of the partials (l1_half: the
+// second half holds l1; otherwise the first holds all of J): each of the
 // kJThreads threads sums a fixed run of each half, then a fixed tree; the
 // order never changes, so J is reproducible
-__global__ __launch_bounds__(kJThreads) void k_j_final(const double* __restrict__ part, float lambda,
+__global__ __launch_bounds__(kJThreads) void k_j_final(const double* __restrict__ part, float lambda, int l1_half,
                                                        float* __restrict__ out) {
   constexpr int kRun = kJBlocks / kJThreads;
   static_assert(kJBlocks % kJThreads == 0, "partials split evenly over the threads");
   __shared__ double r0[kJThreads], r1[kJThreads];
   double a = 0.0, b = 0.0;
+#pragma unroll
   for (int q = 0; q < kRun; ++q) {
     a += part[threadIdx.x * kRun + q];
-    b += part[kJBlocks + threadIdx.x * kRun + q];
+    if (l1_half) b += part[kJBlocks + threadIdx.x * kRun + q];
   }
   r0[threadIdx.x] = a;
   r1[threadIdx.x] = b;
@@ -1819,16 +1812,15 @@ __global__ __launch_bounds__(kJThreads) void k_j_final(const double* __restrict_
 int launch_objective(cs_plan* p, const float2* x, float lambda, float* out, hipStream_t s) {
   const int nh = p->desc.nh, nt = p->desc.nt;
   const size_t npix = (size_t)p->desc.nv * nh;
-  int st = launch_forward_residual(p, x, p->jpart, kJBlocks, s);  // data term, fused with the vertical pass
+  const bool tv = p->desc.prior == CS_PRIOR_TEMPORAL_TV;
+  // data term, fused with the vertical pass (and, for TV, lambda |D_t x|)
+  int st = launch_forward_residual(p, x, p->jpart, kJBlocks, tv ? lambda : 0.f, s);
   if (st != CS_OK) return st;
-  if (p->desc.prior == CS_PRIOR_TEMPORAL_TV) {
-    hipLaunchKernelGGL(k_l1_tv_partial, dim3(kJBlocks), dim3(kJThreads), 0, s, x, nt, npix,
-                       p->jpart + kJBlocks);
-  } else if (p->desc.prior == CS_PRIOR_TEMPORAL_FRAME) {
+  if (p->desc.prior == CS_PRIOR_TEMPORAL_FRAME) {
     // J at the completed coefficients w (img_tmp); x = Psi' w for the data term
     hipLaunchKernelGGL(k_l1_abs_partial, dim3(kJBlocks), dim3(kJThreads), 0, s, p->img_tmp, 2 * (size_t)nt * npix,
                        p->jpart + kJBlocks);
-  } else {
+  } else if (!tv) {
     switch (dft_kp(nt)) {
       case 16: st = l1_dft_launch<16>(p, x, p->jpart + kJBlocks, s); break;
       case 32: st = l1_dft_launch<32>(p, x, p->jpart + kJBlocks, s); break;
@@ -1841,7 +1833,7 @@ int launch_objective(cs_plan* p, const float2* x, float lambda, float* out, hipS
     }
     if (st != CS_OK) return st;
   }
-  hipLaunchKernelGGL(k_j_final, dim3(1), dim3(kJThreads), 0, s, p->jpart, lambda, out);
+  hipLaunchKernelGGL(k_j_final, dim3(1), dim3(kJThreads), 0, s, p->jpart, lambda, tv ? 0 : 1, out);
   CS_HIP(hipGetLastError());
   return CS_OK;
 }

@@ -60,15 +60,37 @@ __device__ __forceinline__ ColGroup col_group(int u, int ngrp, int cw, int nv, i
 // MODE kFwdStore:    hyb[t][c][i][r] = (1/sqrt nv) (F_v (s_c . x_t))[rows[t][r], i]
 // MODE kFwdResidual: sum over (t, c, i, r < mcnt[t]) of |that value - ref[t][c][i][r]|^2,
 //                    one FP64 partial per workgroup (grid-stride over column
-//                    groups with a fixed grid, so the sum is reproducible)
+//                    groups with a fixed grid, so the sum is reproducible);
+//                    with tvl > 0 the partials also hold tvl * sum |x[t+1] - x[t]|
+//                    over the group's pixels (t < nt - 1), from the image values
+//                    the pass holds anyway
 constexpr int kFwdStore = 0, kFwdResidual = 1;
+
+// FP64 |a - b| of complex values
+__device__ __forceinline__ double cabs_diff(float2 a, float2 b) {
+  const double dx = (double)a.x - b.x, dy = (double)a.y - b.y;
+  return sqrt(dx * dx + dy * dy);
+}
+
+// one FP64 partial per workgroup: fixed tree over its threads
+template <int NT>
+__device__ __forceinline__ void store_block_partial(double v, double* __restrict__ part) {
+  __shared__ double red[NT];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
 
 template <int MODE, int WE>
 __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical(
     const float2* __restrict__ x, const float2* __restrict__ coil_cm, float2* __restrict__ hyb,
     const float2* __restrict__ ref, const int32_t* __restrict__ rows, const int32_t* __restrict__ mcnt,
     FftDesc fv, const float2* __restrict__ twv, int nv, int nh, int nt, int nc, int m_max, int cw, float scale,
-    double* __restrict__ part) {
+    float tvl, double* __restrict__ part) {
   constexpr int kVE = WE / 64;  // image values per lane of one column group
   extern __shared__ float2 lds[];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -78,7 +100,7 @@ __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical(
   __syncthreads();
   const int ngrp = (nh + cw - 1) / cw;
   const int units = nt * ngrp;
-  double acc = 0.0;
+  double acc = 0.0, l1 = 0.0;
   for (int u = blockIdx.x * kVWaves + wv; u < units; u += gridDim.x * kVWaves) {
     const ColGroup g = col_group(u, ngrp, cw, nv, nh);
     const float2* xs = x + ((size_t)g.t * nh + g.i0) * nv;
@@ -88,6 +110,14 @@ __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical(
       const int e = lane + 64 * q;
       xv[q] = e < g.tot ? xs[e] : make_float2(0.f, 0.f);
       cv[q] = e < g.tot ? coil_cm[(size_t)g.i0 * nv + e] : make_float2(0.f, 0.f);
+    }
+    if (MODE == kFwdResidual && tvl > 0.f && g.t + 1 < nt) {
+      const float2* xn = xs + (size_t)nh * nv;
+#pragma unroll
+      for (int q = 0; q < kVE; ++q) {
+        const int e = lane + 64 * q;
+        if (e < g.tot) l1 += cabs_diff(xn[e], xv[q]);
+      }
     }
     const int m = mcnt[g.t];
     const int32_t* rw = rows + (size_t)g.t * m_max;
@@ -125,16 +155,7 @@ __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical(
       __builtin_amdgcn_wave_barrier();  // the next coil overwrites buf
     }
   }
-  if constexpr (MODE == kFwdResidual) {
-    __shared__ double red[64 * kVWaves];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 32 * kVWaves; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-  }
+  if constexpr (MODE == kFwdResidual) store_block_partial<64 * kVWaves>(acc + (double)tvl * l1, part);
 }
 
 // y[t][c][rows[t][r]][:] = (1/sqrt nh) F_h hyb[t][c][:][r]
@@ -377,7 +398,8 @@ template <int MODE>
 __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical256(
     const float2* __restrict__ x, const float2* __restrict__ coil_cm, float2* __restrict__ hyb,
     const float2* __restrict__ ref, const int32_t* __restrict__ rinv, const int32_t* __restrict__ mcnt,
-    const float2* __restrict__ twv, int nh, int nt, int nc, int m_max, float scale, double* __restrict__ part) {
+    const float2* __restrict__ twv, int nh, int nt, int nc, int m_max, float scale, float tvl,
+    double* __restrict__ part) {
   extern __shared__ float2 lds[];
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -387,7 +409,7 @@ __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical256(
   stage_twiddles256(twl, twv);
   const int ngrp = (nh + kV256Cols - 1) / kV256Cols;
   const int units = nt * ngrp;
-  double acc = 0.0;
+  double acc = 0.0, l1 = 0.0;
   for (int u = blockIdx.x * kVWaves + wv; u < units; u += gridDim.x * kVWaves) {
     const int t = u / ngrp;
     const int i0 = (u - t * ngrp) * kV256Cols;  // first column of the group
@@ -403,6 +425,11 @@ __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical256(
     for (int n1 = 0; n1 < 16; ++n1) xv[n1] = active ? xs[16 * n1] : make_float2(0.f, 0.f);
 #pragma unroll
     for (int k2 = 0; k2 < 16; ++k2) ro[k2] = active ? rinv[(size_t)t * 256 + L.q + 16 * k2] : -1;
+    if (MODE == kFwdResidual && tvl > 0.f && active && t + 1 < nt) {
+      const float2* xn = xs + (size_t)nh * 256;
+#pragma unroll
+      for (int n1 = 0; n1 < 16; ++n1) l1 += cabs_diff(xn[16 * n1], xv[n1]);
+    }
     // coil c + 1's map values are requested before coil c is transformed
     const int ic = active ? i : 0;
     float2 sn[16];
@@ -439,16 +466,7 @@ __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical256(
       __builtin_amdgcn_wave_barrier();  // the next transform rewrites the buffer
     }
   }
-  if constexpr (MODE == kFwdResidual) {
-    __shared__ double red[64 * kVWaves];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int ww = 32 * kVWaves; ww > 0; ww >>= 1) {
-      if ((int)threadIdx.x < ww) red[threadIdx.x] += red[threadIdx.x + ww];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-  }
+  if constexpr (MODE == kFwdResidual) store_block_partial<64 * kVWaves>(acc + (double)tvl * l1, part);
 }
 
 // ---------------------------------------------------------------- length-256 horizontal passes
@@ -607,12 +625,13 @@ int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipS
     const float sv = 1.0f / std::sqrt((float)nv), sh = 1.0f / std::sqrt((float)nh);
     if (nv == 256) {
       hipLaunchKernelGGL(k_fwd_vertical256<kFwdStore>, dim3(grid256(nh, nt)), dim3(64 * kVWaves), kLds256, s, x,
-                         p->coil_cm, p->ftmp, nullptr, p->rinv, p->mcnt, p->tw_v, nh, nt, nc, p->m_max, sv, nullptr);
+                         p->coil_cm, p->ftmp, nullptr, p->rinv, p->mcnt, p->tw_v, nh, nt, nc, p->m_max, sv, 0.f,
+                         nullptr);
     } else {
       auto k = cw * nv <= 256 ? k_fwd_vertical<kFwdStore, 256> : k_fwd_vertical<kFwdStore, 512>;
       hipLaunchKernelGGL(k, dim3(vertical_grid(p, cw)), dim3(64 * kVWaves), vertical_lds(p, cw), s, x, p->coil_cm,
                          p->ftmp, nullptr, p->rows, p->mcnt, p->fft_v, p->tw_v, nv, nh, nt, nc, p->m_max, cw, sv,
-                         nullptr);
+                         0.f, nullptr);
     }
     CS_HIP(hipGetLastError());
     if (y && nh == 256) {
@@ -635,20 +654,21 @@ int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipS
   return CS_OK;
 }
 
-int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nblocks, hipStream_t s) {
+int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nblocks, float tv_lambda,
+                            hipStream_t s) {
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
   const int cw = fft_cols_per_group(p);
   if (nv == 256) {
     hipLaunchKernelGGL(k_fwd_vertical256<kFwdResidual>, dim3(nblocks), dim3(64 * kVWaves), kLds256, s, x,
                        p->coil_cm, nullptr, p->ktmp, p->rinv, p->mcnt, p->tw_v, nh, nt, nc, p->m_max, 1.0f / 16.0f,
-                       part);
+                       tv_lambda, part);
     CS_HIP(hipGetLastError());
     return CS_OK;
   }
   auto k = cw * nv <= 256 ? k_fwd_vertical<kFwdResidual, 256> : k_fwd_vertical<kFwdResidual, 512>;
   hipLaunchKernelGGL(k, dim3(nblocks), dim3(64 * kVWaves), vertical_lds(p, cw), s, x, p->coil_cm, nullptr,
                      p->ktmp, p->rows, p->mcnt, p->fft_v, p->tw_v, nv, nh, nt, nc, p->m_max, cw,
-                     1.0f / std::sqrt((float)nv), part);
+                     1.0f / std::sqrt((float)nv), tv_lambda, part);
   CS_HIP(hipGetLastError());
   return CS_OK;
 }
