@@ -281,26 +281,48 @@ def unrolled_throughput(reps: int) -> dict:
     return res
 
 
-def stream_context() -> dict:
-    """Rate of a plain torch device-to-device copy of 1 GiB (bytes read +
-    written), timed with torch events in the same run (mean of 5 after a
-    warm-up): context for the roofline fraction, which stays against the
-    published peak."""
+READ_STREAM_BLOCKS = (2048, 4096, 8192, 16384)
+
+
+def stream_context(achieved) -> dict:
+    """Context for the roofline fraction, which stays against the published
+    peak: the rate of a plain torch device-to-device copy of 1 GiB (bytes
+    read + written), and the library's pure read stream (cs_read_stream) over
+    2 GiB at each grid of READ_STREAM_BLOCKS, the best of which is the read
+    rate this chip sustains in practice.  Both are timed with torch events on
+    the current stream, mean of 5 launches after a warm-up."""
     import torch
+    from paper_1203_4587_amd.api import read_stream
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
     a = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    copy = 2 * a.numel() * 4 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
+    copy = 2 * a.numel() * 4 / timed(lambda: b.copy_(a)) / 1e9
     del a, b
+    buf = torch.zeros(2 ** 29, dtype=torch.float32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    nbytes = buf.numel() * 4
+    rates = {g: nbytes / timed(lambda: read_stream(buf, sink, blocks=g)) / 1e9 for g in READ_STREAM_BLOCKS}
+    del buf, sink
     torch.cuda.empty_cache()
-    return {"device_copy_GBps": round(copy, 1)}
+    best = max(rates, key=rates.get)
+    out = {"device_copy_GBps": round(copy, 1),
+           "read_stream_GBps": round(rates[best], 1),
+           "read_stream_blocks": best,
+           "read_stream_GBps_by_blocks": {str(g): round(r, 1) for g, r in rates.items()}}
+    if achieved:
+        out["frac_of_read_stream"] = round(achieved / rates[best], 4)
+    return out
 
 
 def step_rows(plan, problem, y, t_plan: float, prior: str) -> dict:
@@ -643,7 +665,7 @@ def main() -> int:
             "event_timed_iter_per_s": round(args.steps / elapsed_events, 2),
         },
     }
-    line["roofline"].update(stream_context())
+    line["roofline"].update(stream_context(achieved))
     if not args.no_rows:
         line["rows"] = step_rows(plan, problem, y, t_plan, wl["prior"])
     # the paper's stopping rule: iterate until Delta(k) < 1e-3 (checked every 5

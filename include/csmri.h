@@ -369,6 +369,18 @@ typedef struct {
 int cs_kernel_timing(cs_plan* plan, int enable);
 int cs_kernel_times(cs_plan* plan, cs_kernel_time* out, int max, int* count);
 
+/* Measurement aid, not part of the method: reads `bytes` of device memory at
+ * `buf` with a streaming kernel (each of `blocks` workgroups of 256 threads,
+ * 0 selecting 8192, reads contiguous 32 KB tiles with 16-byte non-temporal
+ * loads, eight in flight per thread) and writes nothing, except that *sink (device float) would receive
+ * the sum of the values read if it equalled one fixed improbable number.
+ * Timed around a launch it gives the HBM read rate the chip sustains for a
+ * pure read stream, the practical ceiling of the read-bound x-update.
+ * Asynchronous on `stream`.  Errors: CS_EINVAL (NULL pointer, bytes not a
+ * positive multiple of 16, buf not 16-byte aligned, blocks outside
+ * [0, 65535]). */
+int cs_read_stream(const void* buf, size_t bytes, int32_t blocks, float* sink, cs_stream stream);
+
 /* Static description of a status code. */
 const char* cs_status_string(int status);
 

@@ -59,6 +59,7 @@ EXPORTED = (
     "cs_admm_forward_ckpt",
     "cs_admm_backward",
     "cs_apply_AH_noalloc",
+    "cs_read_stream",
 )
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -152,6 +153,7 @@ def load() -> ctypes.CDLL:
     lib.cs_admm_forward_ckpt.argtypes = [vp, vp, f32, f32, vp, vp]
     lib.cs_admm_backward.argtypes = [vp, vp, vp, vp, vp]
     lib.cs_apply_AH_noalloc.argtypes = [ctypes.POINTER(CsPlanDesc), vp, vp, vp, vp, vp]
+    lib.cs_read_stream.argtypes = [vp, ctypes.c_size_t, i32, vp, vp]
     for name in EXPORTED:
         if name not in ("cs_status_string", "cs_last_error"):
             getattr(lib, name).restype = ctypes.c_int

@@ -447,6 +447,18 @@ class Batch:
         return outs
 
 
+def read_stream(buf: torch.Tensor, sink: torch.Tensor, blocks: int = 0, stream=None) -> None:
+    """Launch cs_read_stream over the bytes of the contiguous device tensor
+    `buf` (a measurement aid: a pure HBM read stream, nothing written in
+    practice; `sink` is a device float32 tensor of at least one element)."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous device tensor")
+    if not sink.is_cuda or sink.dtype != torch.float32 or sink.numel() < 1:
+        raise ValueError("sink must be a device float32 tensor with at least one element")
+    nbytes = buf.numel() * buf.element_size()
+    check(_lib.load().cs_read_stream(_ptr(buf), nbytes, int(blocks), _ptr(sink), _stream(stream)), "cs_read_stream")
+
+
 def to_device(a, device="cuda", dtype=None) -> torch.Tensor:
     """numpy -> contiguous torch tensor on the GPU (complex128 -> complex64)."""
     import numpy as np

@@ -208,3 +208,14 @@ def test_fft_tile_calls_reject_bad_arguments(lib):
     c, r = ctypes.c_int32(), ctypes.c_int32()
     assert lib.cs_plan_fft_tiles(None, ctypes.byref(c), ctypes.byref(r)) == _lib.CS_EINVAL
     assert lib.cs_plan_set_fft_tiles(None, 4, 4) == _lib.CS_EINVAL
+
+
+def test_read_stream_rejects_bad_arguments(lib):
+    sink = ctypes.c_void_p(0x2000)
+    assert lib.cs_read_stream(None, 1 << 20, 0, sink, None) == _lib.CS_EINVAL
+    assert lib.cs_read_stream(FAKE, 1 << 20, 0, None, None) == _lib.CS_EINVAL
+    assert lib.cs_read_stream(FAKE, 0, 0, sink, None) == _lib.CS_EINVAL
+    assert lib.cs_read_stream(FAKE, 24, 0, sink, None) == _lib.CS_EINVAL       # not a multiple of 16
+    assert lib.cs_read_stream(ctypes.c_void_p(0x1008), 32, 0, sink, None) == _lib.CS_EINVAL  # misaligned
+    assert lib.cs_read_stream(FAKE, 32, -1, sink, None) == _lib.CS_EINVAL
+    assert lib.cs_read_stream(FAKE, 32, 65536, sink, None) == _lib.CS_EINVAL
