@@ -981,13 +981,41 @@ struct cs_batch {
   std::vector<const void*> key;
 };
 
-static void batch_release(cs_batch* b) {
-  if (!b) return;
-  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+// the private recording streams and events (recreated by the next recording)
+static void batch_drop_streams(cs_batch* b) {
   for (hipEvent_t e : b->joins) (void)hipEventDestroy(e);
   if (b->fork) (void)hipEventDestroy(b->fork);
   for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
   if (b->capture) (void)hipStreamDestroy(b->capture);
+  b->joins.clear();
+  b->streams.clear();
+  b->fork = nullptr;
+  b->capture = nullptr;
+}
+
+// all of them or none: a failure part way leaves nothing behind
+static int batch_make_streams(cs_batch* b, size_t n) {
+  hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) b->streams.push_back(st);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) b->joins.push_back(ev);
+  }
+  if (e != hipSuccess) {
+    batch_drop_streams(b);
+    return hip_fail(e, "creating the batch's recording streams");
+  }
+  return CS_OK;
+}
+
+static void batch_release(cs_batch* b) {
+  if (!b) return;
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  batch_drop_streams(b);
   for (cs_plan* p : b->plans) (void)cs_plan_destroy(p);
   delete b;
 }
@@ -1081,16 +1109,8 @@ int cs_batch_solve(cs_batch* b, const cs_c64* const* y, const float* lambda, int
       b->graph = nullptr;
     }
     if (!b->capture) {
-      CS_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
-      CS_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
-      for (size_t i = 0; i < n; ++i) {
-        hipStream_t st;
-        hipEvent_t e;
-        CS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-        b->streams.push_back(st);
-        CS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        b->joins.push_back(e);
-      }
+      const int ms = batch_make_streams(b, n);
+      if (ms != CS_OK) return ms;
     }
     // record: fork every slice's stream off the capture stream, run each
     // slice's solve on its stream, join them back.  Slices are recorded in
@@ -1104,10 +1124,12 @@ int cs_batch_solve(cs_batch* b, const cs_c64* const* y, const float* lambda, int
     CS_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
     int st = CS_OK;
     hipError_t e = hipEventRecord(b->fork, b->capture);
+    std::vector<char> forked(n, 0);  // slice streams inside the capture and not yet joined back
     for (size_t oi = 0; oi < n && st == CS_OK && e == hipSuccess; ++oi) {
       const size_t i = order[oi];
       e = hipStreamWaitEvent(b->streams[i], b->fork, 0);
       if (e != hipSuccess) break;
+      forked[i] = 1;
       cs_plan* p = b->plans[i];
       const bool saved_timing = p->timing;
       const uint32_t saved_flags = p->desc.flags;
@@ -1119,11 +1141,20 @@ int cs_batch_solve(cs_batch* b, const cs_c64* const* y, const float* lambda, int
       p->desc.flags = saved_flags;
       if (st == CS_OK) e = hipEventRecord(b->joins[i], b->streams[i]);
       if (st == CS_OK && e == hipSuccess) e = hipStreamWaitEvent(b->capture, b->joins[i], 0);
+      if (st == CS_OK && e == hipSuccess) forked[i] = 0;
     }
+    // after a failure every forked stream is still joined back before the
+    // capture ends, so that no stream stays attached to an abandoned capture
+    for (size_t i = 0; i < n; ++i)
+      if (forked[i] && hipEventRecord(b->joins[i], b->streams[i]) == hipSuccess)
+        (void)hipStreamWaitEvent(b->capture, b->joins[i], 0);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->capture, &g);
     if (st != CS_OK || e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
+      // the recording streams are not reused after a failed recording
+      (void)hipGetLastError();
+      batch_drop_streams(b);
       if (st != CS_OK) return st;
       return hip_fail(e != hipSuccess ? e : e2, "recording the batch graph");
     }
