@@ -5,6 +5,7 @@
 // x-update is nv contiguous values and one pixel's time series is a stride-
 // (nv*nh) sequence read coalesced across neighbouring pixels.
 #include "internal.hpp"
+#include "tdft.hpp"
 
 namespace csmri {
 
@@ -637,6 +638,149 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ frag, float* 
   __builtin_amdgcn_wave_barrier();
 }
 
+// load / store at a wave-uniform base plus a 32-bit per-lane byte offset
+__device__ __forceinline__ float2 ld_off(const float2* __restrict__ base, uint32_t off) {
+  return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base) + off);
+}
+__device__ __forceinline__ void st_off(float2* __restrict__ base, uint32_t off, float2 v) {
+  *reinterpret_cast<float2*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
+// The same three modes as dft_tile, for nt = L N2 (tdft_lanes(nt) = L), with
+// Psi as the lane-group FFT of tdft.hpp: 64 / L pixels per wave, lane l on
+// pixel l / L and frames (l % L) + L n2, or frequencies k2 + N2 bitrev(l % L)
+// after the forward transform.  No LDS and no matrix cores.  Every lane of the
+// wave runs the transforms (the lane exchanges read the partner lanes).
+template <int L, int N2, int MODE>
+__device__ __forceinline__ void dft_fft_tile(const float2* __restrict__ in, float2* __restrict__ d,
+                                             float2* __restrict__ v, float2* __restrict__ out,
+                                             const float2* __restrict__ wgiven, size_t npix, size_t p0, int count,
+                                             float tau, int first, int lane, const GroupRoots<L, N2>& roots) {
+  constexpr float kScale = (float)cx_rsqrt(L * N2);  // 1 / sqrt(nt): Psi is unitary
+  const int col = lane / L, j = lane % L;
+  const int k1 = lane_bitrev<L>(j);
+  const bool pv = col < count;
+  // Addresses: a wave-uniform base per frame or frequency (from p0) plus one
+  // 32-bit byte offset per lane (8 nt npix < 2^32 for every supported size).
+  // Lanes past the tile's last pixel read that pixel (a group's lanes share
+  // their pixel, so its values never mix with a real pixel's) and store
+  // nothing.
+  const uint32_t cc = (uint32_t)min(col, count - 1);
+  const uint32_t offT = 8u * (cc + (uint32_t)(j * npix)), offF = 8u * (cc + (uint32_t)(N2 * k1 * npix));
+  const size_t strideT = (size_t)L * npix;
+  float2 x[N2];
+  // the step's dual and shrinkage operands of this lane's frequencies are
+  // requested first, so that their latency overlaps the transform
+  float2 dpre[N2], vpre[N2];
+  if (MODE == kDftStep) {
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+      const size_t bk = p0 + (size_t)k * npix;
+      dpre[k] = ld_off(d + bk, offF);
+      vpre[k] = first ? make_float2(0.f, 0.f) : ld_off(v + bk, offF);
+    }
+  }
+  if (MODE == kDftStep && wgiven) {
+#pragma unroll
+    for (int k = 0; k < N2; ++k) x[k] = ld_off(wgiven + p0 + (size_t)k * npix, offF);
+  } else if (MODE == kDftAdjoint) {
+#pragma unroll
+    for (int k = 0; k < N2; ++k) x[k] = ld_off(in + p0 + (size_t)k * npix, offF);
+  } else {
+#pragma unroll
+    for (int n = 0; n < N2; ++n) x[n] = ld_off(in + p0 + (size_t)n * strideT, offT);
+    group_fft_time_to_freq<L, N2, -1>(x, j, roots);
+#pragma unroll
+    for (int k = 0; k < N2; ++k) x[k] = cscale(x[k], kScale);
+  }
+  if (MODE == kDftForward) {
+    if (pv) {
+#pragma unroll
+      for (int k = 0; k < N2; ++k) {
+        const size_t bk = p0 + (size_t)k * npix;
+        st_off(out + bk, offF, x[k]);
+        if (d) {
+          const float2 vf = ld_off(v + bk, offF), df = ld_off(d + bk, offF);
+          st_off(d + bk, offF, make_float2(df.x - (x[k].x - vf.x), df.y - (x[k].y - vf.y)));
+        }
+      }
+    }
+    return;
+  }
+  if (MODE == kDftStep) {
+    // dual update, shrinkage and q = v + d, in place of w
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+      const float2 w = x[k];
+      float2 df = dpre[k];
+      if (!first) df = make_float2(df.x - (w.x - vpre[k].x), df.y - (w.y - vpre[k].y));
+      const float2 vf = soft_threshold(csub(w, df), tau);
+      if (pv) {
+        const size_t bk = p0 + (size_t)k * npix;
+        st_off(d + bk, offF, df);
+        st_off(v + bk, offF, vf);
+      }
+      x[k] = cadd(vf, df);
+    }
+  }
+  group_fft_freq_to_time<L, N2, +1>(x, j, roots);
+  if (pv) {
+#pragma unroll
+    for (int n = 0; n < N2; ++n) st_off(out + p0 + (size_t)n * strideT, offT, cscale(x[n], kScale));
+  }
+}
+
+// phase-kernel form of the group-FFT step: 4 waves per workgroup, one tile of
+// 64 / L pixels per wave in a grid-stride loop
+template <int L, int N2, int MODE>
+__global__ __launch_bounds__(256) void k_dft_fft(const float2* __restrict__ in, float2* __restrict__ d,
+                                                 float2* __restrict__ v, float2* __restrict__ out,
+                                                 const float2* __restrict__ wgiven, size_t npix, size_t pix0,
+                                                 size_t pix1, float tau, int first) {
+  constexpr int P = 64 / L;  // pixels per wave
+  // the wave index is uniform over the wave: said so, the tile's base
+  // addresses stay in scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  const size_t ntiles = (pix1 - pix0 + P - 1) / P;
+  const GroupRoots<L, N2> roots = group_roots<L, N2>(lane % L);
+  for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
+    const size_t p0 = pix0 + tl * P;
+    const int count = (int)std::min<size_t>(P, pix1 - p0);
+    dft_fft_tile<L, N2, MODE>(in, d, v, out, wgiven, npix, p0, count, tau, first, lane, roots);
+  }
+}
+
+// The DFT step of one 16-pixel tile by the group FFT when tdft_lanes(nt) is
+// not 0 (for a padded size KP: 8 lanes with N2 = KP / 16, or 4 lanes with an
+// odd N2 = KP / 8 - 1), else by the MFMA contraction.  The phase kernels
+// choose the same way, so every form computes the step with the same
+// arithmetic.  nt is uniform over the wave.
+template <int KP, int MODE>
+__device__ __forceinline__ void dft_tile_any(const float* __restrict__ frag, float* tile,
+                                             const float2* __restrict__ in, float2* __restrict__ d,
+                                             float2* __restrict__ v, float2* __restrict__ out,
+                                             const float2* __restrict__ wgiven, int nt, size_t npix, size_t p0,
+                                             int count, float tau, int first, int lane) {
+  constexpr int k8 = KP / 16, k4 = KP / 8 - 1;
+  if constexpr (tdft_len_ok(k8)) {
+    if (nt == 8 * k8 && tdft_lanes(nt) == 8) {  // two 8-pixel halves
+      const GroupRoots<8, k8> roots = group_roots<8, k8>(lane % 8);
+      dft_fft_tile<8, k8, MODE>(in, d, v, out, wgiven, npix, p0, std::min(count, 8), tau, first, lane, roots);
+      if (count > 8)
+        dft_fft_tile<8, k8, MODE>(in, d, v, out, wgiven, npix, p0 + 8, count - 8, tau, first, lane, roots);
+      return;
+    }
+  }
+  if constexpr (k4 % 2 == 1 && tdft_len_ok(k4)) {
+    if (nt == 4 * k4 && tdft_lanes(nt) == 4) {
+      dft_fft_tile<4, k4, MODE>(in, d, v, out, wgiven, npix, p0, count, tau, first, lane, group_roots<4, k4>(lane % 4));
+      return;
+    }
+  }
+  dft_tile<KP, MODE>(frag, tile, in, d, v, out, wgiven, nt, npix, p0, count, tau, first, lane);
+}
+
 // copy the fragment matrix into LDS (all threads of the workgroup)
 // (16-byte aligned on both sides; batches of loads in flight before their stores)
 template <int KP>
@@ -693,9 +837,32 @@ inline size_t dft_lds_bytes(int kp, int waves) {
   return ((size_t)(kp / 16) * (kp / 4) * 64 + (size_t)waves * kp * 16) * sizeof(float);
 }
 
+template <int L, int N2, int MODE>
+static int dft_fft_launch(cs_plan* p, const float2* in, float2* d, float2* v, float2* out, const float2* wgiven,
+                          float tau, int first, int i0, int i1, hipStream_t s) {
+  constexpr size_t P = 64 / L;
+  const size_t npix = (size_t)p->desc.nv * p->desc.nh;
+  const size_t pix0 = (size_t)i0 * p->desc.nv, pix1 = (size_t)i1 * p->desc.nv;
+  const size_t ntiles = (pix1 - pix0 + P - 1) / P;
+  // one tile per wave: the step is short and gains most from many waves in
+  // flight (fewer waves with several tiles each measured slower)
+  const unsigned grid = (unsigned)std::min<size_t>((ntiles + 3) / 4, 65535);
+  constexpr size_t kLdsPad = 0;
+  hipLaunchKernelGGL((k_dft_fft<L, N2, MODE>), dim3(grid), dim3(256), kLdsPad, s, in, d, v, out, wgiven, npix, pix0,
+                     pix1, tau, first);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
 template <int KP, int MODE>
 static int dft_tiles_launch(cs_plan* p, const float2* in, float2* d, float2* v, float2* out, const float2* wgiven,
                             float tau, int first, int i0, int i1, hipStream_t s) {
+  constexpr int k8 = KP / 16, k4 = KP / 8 - 1;  // the group-FFT lengths whose nt has this KP
+  const int nt = p->desc.nt, lanes = tdft_lanes(nt);
+  if constexpr (tdft_len_ok(k8))
+    if (lanes == 8 && nt == 8 * k8) return dft_fft_launch<8, k8, MODE>(p, in, d, v, out, wgiven, tau, first, i0, i1, s);
+  if constexpr (k4 % 2 == 1 && tdft_len_ok(k4))
+    if (lanes == 4 && nt == 4 * k4) return dft_fft_launch<4, k4, MODE>(p, in, d, v, out, wgiven, tau, first, i0, i1, s);
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
   const size_t pix0 = (size_t)i0 * p->desc.nv, pix1 = (size_t)i1 * p->desc.nv;
   const int waves = dft_waves(KP);
@@ -1205,9 +1372,9 @@ __global__ __launch_bounds__(512) void k_column_solve(ColumnSolveArgs a) {
                     std::min(16, n - 16 * tl), a.tau, a.rho, lane);
     } else {
       for (int tl = w; tl * 16 < n; tl += nwaves)
-        dft_tile<NT, kDftStep>(frags, reinterpret_cast<float*>(bsh), a.s2, a.s0, a.s1,
-                               a.s3, k == 0 ? a.wgiven : nullptr, a.nt, npix, (size_t)i * n + 16 * tl,
-                               std::min(16, n - 16 * tl), a.tau, k == 0, lane);
+        dft_tile_any<NT, kDftStep>(frags, reinterpret_cast<float*>(bsh), a.s2, a.s0, a.s1, a.s3,
+                                   k == 0 ? a.wgiven : nullptr, a.nt, npix, (size_t)i * n + 16 * tl,
+                                   std::min(16, n - 16 * tl), a.tau, k == 0, lane);
     }
     __syncthreads();
     // x-update: wave w solves the blocks (t, i), t = w, w + nwaves, ...; no
@@ -1657,10 +1824,127 @@ __global__ __launch_bounds__(256) void k_dft_adjoint(const float* __restrict__ f
   }
 }
 
+// k_dft_adjoint with Psi as the lane-group FFT (nt = L N2): the same three
+// transforms and the same per-frequency and per-frame lines, 64 / L pixels
+// per wave (lane l on pixel l / L).  w_{k-1} = Psi z_{k-1} is formed by the
+// forward step's own transform and scaling, so every |a| > tau decision is
+// the forward's.
+template <int L, int N2>
+__global__ __launch_bounds__(256) void k_dft_adjoint_fft(const float2* __restrict__ bb, float2* __restrict__ db,
+                                                         float2* __restrict__ zb, float2* __restrict__ hyb,
+                                                         const float2* __restrict__ zprev,
+                                                         const float2* __restrict__ dprev,
+                                                         const float2* __restrict__ u, const float2* __restrict__ z,
+                                                         double* __restrict__ partial, size_t npix, float tau,
+                                                         float mu, int last) {
+  constexpr float kScale = (float)cx_rsqrt(L * N2);
+  constexpr int P = 64 / L;  // pixels per wave
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane / L, j = lane % L;
+  const int k1 = lane_bitrev<L>(j);
+  const int nw = blockDim.x >> 6;
+  const size_t ntiles = (npix + P - 1) / P;
+  const GroupRoots<L, N2> roots = group_roots<L, N2>(j);
+  double tsum = 0.0, msum = 0.0;
+  for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
+    const size_t p0 = tl * P;
+    const int count = (int)std::min<size_t>(P, npix - p0);
+    const bool pv = col < count;
+    const size_t p = p0 + col;
+    // s = Psi (mu bb) and w_{k-1} = Psi z_{k-1}
+    float2 S[N2], A[N2];
+#pragma unroll
+    for (int n = 0; n < N2; ++n) {
+      const size_t o = (size_t)(j + L * n) * npix + p;
+      S[n] = pv ? cscale(bb[o], mu) : make_float2(0.f, 0.f);
+      A[n] = pv ? zprev[o] : make_float2(0.f, 0.f);
+    }
+    group_fft_time_to_freq<L, N2, -1>(S, j, roots);
+    group_fft_time_to_freq<L, N2, -1>(A, j, roots);
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+      S[k] = cscale(S[k], kScale);
+      A[k] = cscale(A[k], kScale);
+    }
+    float2 Q[N2];
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+      float2 q = make_float2(0.f, 0.f);
+      if (pv) {
+        const size_t o = (size_t)(k + N2 * k1) * npix + p;
+        const float2 dk = db[o];
+        const float2 a = csub(A[k], dprev[o]);
+        const float2 vb = cadd(dk, S[k]);
+        float2 ab = make_float2(0.f, 0.f);
+        const float mag = sqrtf(fmaf(a.x, a.x, a.y * a.y));
+        if (mag > tau) {
+          const float sdot = fmaf(a.x, vb.x, a.y * vb.y) / mag;  // Re(conj(a/|a|) vb)
+          const float kk = tau / mag;
+          const float ks = kk * sdot / mag;
+          ab = make_float2(fmaf(1.f - kk, vb.x, ks * a.x), fmaf(1.f - kk, vb.y, ks * a.y));
+          tsum -= (double)sdot;
+        }
+        const float2 dn = csub(vb, ab);
+        db[o] = dn;
+        q = last ? ab : csub(ab, dn);
+      }
+      Q[k] = q;
+    }
+    group_fft_freq_to_time<L, N2, +1>(Q, j, roots);  // Psi'(wb - db), or Psi' wb for the first iteration
+    if (pv) {
+#pragma unroll
+      for (int n = 0; n < N2; ++n) {
+        const size_t o = (size_t)(j + L * n) * npix + p;
+        const float2 r = cscale(Q[n], kScale);
+        const float2 b = bb[o], uu = u[o], zz = z[o];
+        msum += (double)b.x * ((double)uu.x - zz.x) + (double)b.y * ((double)uu.y - zz.y);
+        float2 hv = cadd(hyb[o], b);
+        if (last) hv = cadd(hv, r);
+        else zb[o] = r;
+        hyb[o] = hv;
+      }
+    }
+  }
+  __shared__ double red[2][256];
+  red[0][threadIdx.x] = tsum;
+  red[1][threadIdx.x] = msum;
+  __syncthreads();
+  for (int k = (int)blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + k];
+      red[1][threadIdx.x] += red[1][threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] += red[0][0];
+    partial[2 * blockIdx.x + 1] += red[1][0];
+  }
+}
+
+template <int L, int N2>
+static int dft_adjoint_fft_launch(cs_plan* p, unsigned nblocks, const float2* bb, float2* db, float2* zb,
+                                  float2* hyb, const float2* zprev, const float2* dprev, const float2* u,
+                                  const float2* z, double* partial, float tau, float mu, int last, hipStream_t s) {
+  const size_t npix = (size_t)p->desc.nv * p->desc.nh;
+  hipLaunchKernelGGL((k_dft_adjoint_fft<L, N2>), dim3(nblocks), dim3(256), 0, s, bb, db, zb, hyb, zprev, dprev, u, z,
+                     partial, npix, tau, mu, last);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
 template <int KP>
 static int dft_adjoint_launch(cs_plan* p, unsigned nblocks, const float2* bb, float2* db, float2* zb, float2* hyb,
                               const float2* zprev, const float2* dprev, const float2* u, const float2* z,
                               double* partial, float tau, float mu, int last, hipStream_t s) {
+  constexpr int k8 = KP / 16, k4 = KP / 8 - 1;  // the group-FFT lengths whose nt has this KP
+  const int nt = p->desc.nt, lanes = tdft_lanes(nt);
+  if constexpr (tdft_len_ok(k8))
+    if (lanes == 8 && nt == 8 * k8)
+      return dft_adjoint_fft_launch<8, k8>(p, nblocks, bb, db, zb, hyb, zprev, dprev, u, z, partial, tau, mu, last, s);
+  if constexpr (k4 % 2 == 1 && tdft_len_ok(k4))
+    if (lanes == 4 && nt == 4 * k4)
+      return dft_adjoint_fft_launch<4, k4>(p, nblocks, bb, db, zb, hyb, zprev, dprev, u, z, partial, tau, mu, last, s);
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
   const int waves = dft_waves(KP);
   const size_t lds = dft_lds_bytes(KP, waves);
