@@ -1100,7 +1100,8 @@ int launch_tv_step(cs_plan* p, float lambda, float mu, hipStream_t s) {
 // q = Psi H'y + mu (v + d); and Psi' w = x~.  So one iteration is one
 // per-pixel pass (finish the previous iteration's w and d, shrink, form u)
 // plus the x-update with right-hand side H'y + mu u.  Both transforms of a
-// pass run on the MFMA DFT tiles; the identity part needs no arithmetic.
+// pass run on the group FFT where it applies (else on the MFMA DFT tiles); the
+// identity part needs no arithmetic.
 //   kFrameFirst:   v = soft(w - d, tau), u = Psi'(v + d) from the given w (d kept)
 //   kFrameStep:    w = v + d + Psi(x~ - u); d <- d - (w - v); v = soft(w - d, tau);
 //                  u = Psi'(v + d)
@@ -1242,6 +1243,150 @@ __device__ __forceinline__ void frame_tile(const float* __restrict__ frag, float
   __builtin_amdgcn_wave_barrier();
 }
 
+// frame_tile with F as the lane-group FFT (nt = L N2, tdft_lanes(nt) = L):
+// 64 / L pixels per wave.  The identity part of the coefficients is handled
+// in the frame layout (lane j: frames j + L n2), the DFT part in the
+// frequency layout (lane j: k2 + N2 bitrev(j)); each coefficient is updated
+// on its own, so only the sum u = (q_I + F' q_F) / sqrt(2) combines them.
+template <int L, int N2, int MODE>
+__device__ __forceinline__ void frame_fft_tile(const float2* __restrict__ xt, float2* __restrict__ u,
+                                               float2* __restrict__ v, float2* __restrict__ d,
+                                               float2* __restrict__ w, int nt, size_t npix, size_t p0, int count,
+                                               float tau, int lane, const GroupRoots<L, N2>& roots) {
+  constexpr float kScale = (float)cx_rsqrt(L * N2);
+  const int col = lane / L, j = lane % L;
+  const int k1 = lane_bitrev<L>(j);
+  const bool pv = col < count;
+  const uint32_t cc = (uint32_t)min(col, count - 1);
+  const uint32_t offT = 8u * (cc + (uint32_t)(j * npix)), offF = 8u * (cc + (uint32_t)(N2 * k1 * npix));
+  const size_t strideT = (size_t)L * npix;
+  const size_t partF = (size_t)nt * npix;  // the DFT part's first coefficient frame
+  float2 xI[N2], xF[N2];  // frame layout, frequency layout
+  if (MODE == kFrameForward) {
+#pragma unroll
+    for (int n = 0; n < N2; ++n) xI[n] = ld_off(xt + p0 + (size_t)n * strideT, offT);
+#pragma unroll
+    for (int n = 0; n < N2; ++n) xF[n] = xI[n];
+    group_fft_time_to_freq<L, N2, -1>(xF, j, roots);
+    if (pv) {
+#pragma unroll
+      for (int n = 0; n < N2; ++n) st_off(w + p0 + (size_t)n * strideT, offT, cscale(xI[n], kInvSqrt2));
+#pragma unroll
+      for (int k = 0; k < N2; ++k)
+        st_off(w + partF + p0 + (size_t)k * npix, offF, cscale(cscale(xF[k], kScale), kInvSqrt2));
+    }
+    return;
+  }
+  if (MODE == kFrameAdjoint) {
+#pragma unroll
+    for (int n = 0; n < N2; ++n) xI[n] = ld_off(w + p0 + (size_t)n * strideT, offT);
+#pragma unroll
+    for (int k = 0; k < N2; ++k) xF[k] = ld_off(w + partF + p0 + (size_t)k * npix, offF);
+  } else {
+    // every operand is requested before the transform: the identity part's
+    // (frame layout) and the DFT part's (frequency layout) d and v, and w or
+    // the x~ and u of e = x~ - u
+    float2 dI[N2], dF[N2], vI[N2], vF[N2], peI[N2], peF[N2];
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+      const size_t bI = p0 + (size_t)k * strideT, bF = partF + p0 + (size_t)k * npix;
+      dI[k] = ld_off(d + bI, offT);
+      dF[k] = ld_off(d + bF, offF);
+      if (MODE == kFrameFirst) {  // v <- soft(w - d): w in place of v
+        vI[k] = ld_off(w + bI, offT);
+        vF[k] = ld_off(w + bF, offF);
+      } else {
+        vI[k] = ld_off(v + bI, offT);
+        vF[k] = ld_off(v + bF, offF);
+        peI[k] = csub(ld_off(xt + bI, offT), ld_off(u + bI, offT));
+      }
+    }
+    // Psi (x~ - u): the identity part e / sqrt(2), the DFT part F e / sqrt(2)
+    if (MODE != kFrameFirst) {
+#pragma unroll
+      for (int n = 0; n < N2; ++n) peF[n] = peI[n];
+      group_fft_time_to_freq<L, N2, -1>(peF, j, roots);
+#pragma unroll
+      for (int k = 0; k < N2; ++k) {
+        peF[k] = cscale(cscale(peF[k], kScale), kInvSqrt2);
+        peI[k] = cscale(peI[k], kInvSqrt2);
+      }
+    }
+    // coefficient updates: part 0 the identity (frame layout), part 1 the DFT
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+#pragma unroll
+      for (int k = 0; k < N2; ++k) {
+        const size_t b = part ? partF + p0 + (size_t)k * npix : p0 + (size_t)k * strideT;
+        const uint32_t off = part ? offF : offT;
+        float2 dv = part ? dF[k] : dI[k], q;
+        if (MODE == kFrameFirst) {
+          const float2 vn = soft_threshold(csub(part ? vF[k] : vI[k], dv), tau);
+          if (pv) st_off(v + b, off, vn);
+          q = cadd(vn, dv);
+        } else {
+          const float2 vv = part ? vF[k] : vI[k];
+          const float2 wv = cadd(cadd(vv, dv), part ? peF[k] : peI[k]);
+          dv = csub(dv, csub(wv, vv));
+          if (MODE == kFrameFinish) {
+            if (pv) {
+              st_off(w + b, off, wv);
+              st_off(d + b, off, dv);
+            }
+            q = make_float2(0.f, 0.f);
+          } else {
+            const float2 vn = soft_threshold(csub(wv, dv), tau);
+            if (pv) {
+              st_off(v + b, off, vn);
+              st_off(d + b, off, dv);
+            }
+            q = cadd(vn, dv);
+          }
+        }
+        if (part) xF[k] = q;
+        else xI[k] = q;
+      }
+    }
+    if (MODE == kFrameFinish) return;
+  }
+  // u = Psi' q = (q_identity + F' q_dft) / sqrt(2)  (x for kFrameAdjoint)
+  group_fft_freq_to_time<L, N2, +1>(xF, j, roots);
+  float2* out = MODE == kFrameAdjoint ? const_cast<float2*>(xt) : u;
+  if (pv) {
+#pragma unroll
+    for (int n = 0; n < N2; ++n)
+      st_off(out + p0 + (size_t)n * strideT, offT, cscale(cadd(cscale(xF[n], kScale), xI[n]), kInvSqrt2));
+  }
+}
+
+template <int L, int N2, int MODE>
+__global__ __launch_bounds__(256) void k_frame_fft(const float2* xt, float2* __restrict__ u, float2* __restrict__ v,
+                                                   float2* __restrict__ d, float2* __restrict__ w, int nt,
+                                                   size_t npix, float tau) {
+  constexpr int P = 64 / L;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  const size_t ntiles = (npix + P - 1) / P;
+  const GroupRoots<L, N2> roots = group_roots<L, N2>(lane % L);
+  for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
+    const size_t p0 = tl * P;
+    const int count = (int)std::min<size_t>(P, npix - p0);
+    frame_fft_tile<L, N2, MODE>(xt, u, v, d, w, nt, npix, p0, count, tau, lane, roots);
+  }
+}
+
+template <int L, int N2, int MODE>
+static int frame_fft_launch(cs_plan* p, const float2* xt, float2* u, float2* v, float2* d, float2* w, float tau,
+                            hipStream_t s) {
+  constexpr size_t P = 64 / L;
+  const size_t npix = (size_t)p->desc.nv * p->desc.nh;
+  const size_t ntiles = (npix + P - 1) / P;
+  const unsigned grid = (unsigned)std::min<size_t>((ntiles + 3) / 4, 65535);
+  hipLaunchKernelGGL((k_frame_fft<L, N2, MODE>), dim3(grid), dim3(256), 0, s, xt, u, v, d, w, p->desc.nt, npix, tau);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
 template <int KP, int MODE>
 __global__ __launch_bounds__(256) void k_frame_tiles(const float* __restrict__ frags, const float2* xt,
                                                      float2* __restrict__ u, float2* __restrict__ v,
@@ -1264,6 +1409,12 @@ __global__ __launch_bounds__(256) void k_frame_tiles(const float* __restrict__ f
 template <int KP, int MODE>
 static int frame_tiles_launch(cs_plan* p, const float2* xt, float2* u, float2* v, float2* d, float2* w, float tau,
                               hipStream_t s) {
+  constexpr int k8 = KP / 16, k4 = KP / 8 - 1;  // the group-FFT lengths whose nt has this KP
+  const int nt = p->desc.nt, lanes = tdft_lanes(nt);
+  if constexpr (tdft_len_ok(k8))
+    if (lanes == 8 && nt == 8 * k8) return frame_fft_launch<8, k8, MODE>(p, xt, u, v, d, w, tau, s);
+  if constexpr (k4 % 2 == 1 && tdft_len_ok(k4))
+    if (lanes == 4 && nt == 4 * k4) return frame_fft_launch<4, k4, MODE>(p, xt, u, v, d, w, tau, s);
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
   const int waves = dft_waves(KP);
   const size_t lds = dft_lds_bytes(KP, waves);
