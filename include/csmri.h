@@ -230,9 +230,10 @@ int cs_plan_set_flags(cs_plan* plan, uint32_t flags);
  * them.  0 selects the default: as many columns as fit 256 values (one when
  * nv > 256) and as many rows as fit 4096 values.  Larger values are clipped to
  * 512 values per column group and 4096 per row group.  Results do not depend
- * on them.  At nv = 256 the vertical passes, and at nh = 256 the horizontal
- * ones, run length-256 register transforms with fixed tiles (4 columns per
- * wave, 16 rows per workgroup) and ignore the corresponding value. */
+ * on them.  At n_v = 16 M (M = 4, 6, 8, 9, 12, 16: 64 ... 256) the vertical
+ * passes, and at n_h = 16 M the horizontal ones, run register transforms with
+ * fixed tiles (4 columns per wave, 16 rows per workgroup) and ignore the
+ * corresponding value. */
 int cs_plan_fft_tiles(const cs_plan* plan, int32_t* cols, int32_t* rows);
 int cs_plan_set_fft_tiles(cs_plan* plan, int32_t cols, int32_t rows);
 

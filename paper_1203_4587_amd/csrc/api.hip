@@ -833,7 +833,7 @@ int cs_plan_set_fft_tiles(cs_plan* p, int32_t cols, int32_t rows) {
 // workgroup) pair from the largest down to 1/16 (columns) and 1/4 (rows) of
 // it is timed on H'y of y (the adjoint passes) followed by the vertical
 // forward pass, which the objective uses; the fastest is kept in the plan.
-// The length-256 passes have fixed tiles, so a knob they ignore is not swept.
+// The register passes (n = 16 M) have fixed tiles, so a knob they ignore is not swept.
 static int tune_fft_tiles(cs_plan* p, const cs_c64* y, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int save_cw = p->fft_cw, save_rb = p->fft_rb;
   p->fft_cw = 0;
@@ -841,7 +841,7 @@ static int tune_fft_tiles(cs_plan* p, const cs_c64* y, hipStream_t s, hipEvent_t
   const int cw_default = fft_cols_per_group(p);
   const int cw_full = fft_cols_limit(p), rb_full = fft_rows_per_group(p);
   std::vector<int> cws, rbs;
-  const int cw_div = p->desc.nv == 256 ? 1 : 16, rb_div = p->desc.nh == 256 ? 1 : 4;
+  const int cw_div = reg16_size(p->desc.nv) ? 1 : 16, rb_div = reg16_size(p->desc.nh) ? 1 : 4;
   for (int d = 1; d <= cw_div; d *= 2)
     if (cw_full / d >= 1 && (cws.empty() || cws.back() != cw_full / d)) cws.push_back(cw_full / d);
   for (int d = 1; d <= rb_div; d *= 2)

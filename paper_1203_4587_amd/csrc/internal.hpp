@@ -259,6 +259,8 @@ int check_finite_kspace(cs_plan* p, const float2* y, hipStream_t s, const char* 
 int check_finite_values(cs_plan* p, const float2* x, size_t n, hipStream_t s, const char* what);
 int fft_cols_per_group(const cs_plan* p);
 int fft_cols_limit(const cs_plan* p);
+// sizes (n_v or n_h) that take the 16 x M register passes (fixed tiles)
+bool reg16_size(int n);
 int fft_rows_per_group(const cs_plan* p);
 
 // factor.hip

@@ -17,6 +17,7 @@
 // column are contiguous for the vertical passes.  The row-major [t][j][i]
 // layout of the boundary goes through a tiled transpose.
 #include "fft.hpp"
+#include "tdft.hpp"
 
 namespace csmri {
 
@@ -285,74 +286,93 @@ __global__ __launch_bounds__(64 * kVWaves) void k_adj_vertical(
   }
 }
 
-// ---------------------------------------------------------------- length-256 vertical passes
+// ---------------------------------------------------------------- register passes, n = 16 M
 //
-// nv = 256 = 16 x 16: row j (or ky) = 16 n1 + n2 on input, 16 k2 + k1 on
-// output.  A wave works on 4 readout columns at once, lane l on column
-// l / 16 with q = l % 16: it holds the 16 values of rows 16 n1 + q, runs the
-// length-16 DFT over n1 in registers, multiplies by exp(SIGN 2 pi i q k1 /
-// 256) (a per-lane table read once per kernel), and after one transpose
-// through LDS (rows padded to 17 values) holds the 16 values of rows
-// q + 16 k2, which the second length-16 DFT transforms into the outputs
-// q + 16 k2.  The sampled rows move between hybrid storage and the lanes
-// through the frame's row index rinv[t][ky] (r, or -1 for an unsampled ky),
-// so no zero-filled buffer is built.  Results agree with the generic
+// n = 16 M (M <= 16 a product of 2, 3 and 5; n_v for the vertical passes, n_h
+// for the horizontal ones): input index 16 n1 + q (q < 16, n1 < M), output
+// index k1 + M k2 (k1 < M, k2 < 16).  Lane q of a 16-lane line holds the M
+// inputs 16 n1 + q, runs the length-M DFT over n1 in registers, multiplies
+// by exp(SIGN 2 pi i q k1 / n) (the workgroup's LDS copy of the table), and
+// after one transpose through LDS (rows padded to 17 values) lane k1 < M holds
+// the 16 values of k1 over q, which a length-16 DFT transforms into the
+// outputs k1 + M k2 (lanes k1 >= M carry no output).  A wave holds 4 lines.
+// For the vertical passes the sampled rows move between hybrid storage and the
+// lanes through the frame's row index rinv[t][ky] (r, or -1 for an unsampled
+// ky), so no zero-filled buffer is built.  Results agree with the generic
 // mixed-radix passes to rounding (not bit for bit: another butterfly order).
-constexpr int kV256Cols = 4;                      // readout columns per wave
-constexpr int kV256Lds = kV256Cols * 16 * 17;     // transpose buffer values per wave
+constexpr int kV256Cols = 4;                   // lines (readout columns or sampled rows) per wave
+constexpr int kV256Lds = kV256Cols * 16 * 17;  // transpose buffer values per wave
+
+constexpr bool reg16_ok(int n) { return n % 16 == 0 && tdft_len_ok(n / 16); }
 
 struct Lane256 {
   int b, q;
 };
 __device__ __forceinline__ Lane256 lane256(int lane) { return Lane256{lane >> 4, lane & 15}; }
 
-// the workgroup's copy of the table exp(-2 pi i m / 256), m < 256, at the
-// start of its LDS (all threads; ends with a barrier)
-__device__ __forceinline__ void stage_twiddles256(float2* twl, const float2* __restrict__ twv) {
-  for (int m = threadIdx.x; m < 256; m += blockDim.x) twl[m] = twv[m];
+// the workgroup's copy of the table exp(-2 pi i m / n), m < n, at the start
+// of its LDS (all threads; ends with a barrier)
+__device__ __forceinline__ void stage_twiddles(float2* twl, const float2* __restrict__ tw, int n) {
+  for (int m = threadIdx.x; m < n; m += blockDim.x) twl[m] = tw[m];
   __syncthreads();
 }
 
-// v: rows 16 n1 + q in, rows q + 16 k2 of the transform out (unnormalised);
-// the twiddles exp(SIGN 2 pi i q k1 / 256) come from the LDS table
-template <int SIGN>
-__device__ __forceinline__ void fft256_lanes(float2 (&v)[16], const float2* twl, float2* tbuf, Lane256 L) {
-  dft16_regs<SIGN>(v);
+// v[n1] (n1 < M): inputs 16 n1 + q in; v[k2] (k2 < 16) on lanes q < M: the
+// outputs q + M k2 of the transform (unnormalised); the twiddles exp(SIGN 2
+// pi i q k1 / 16 M) come from the LDS table.  Every lane of the wave takes
+// part (lanes q >= M read a real lane's buffer row and hold no output).
+template <int M, int SIGN>
+__device__ __forceinline__ void fft16m_lanes(float2 (&v)[16], const float2* twl, float2* tbuf, Lane256 L) {
+  if constexpr (M == 16) {
+    dft16_regs<SIGN>(v);
+  } else {
+    float2 a[M];
 #pragma unroll
-  for (int k1 = 1; k1 < 16; ++k1) {
-    const float2 t = twl[(L.q * k1) & 255];
+    for (int n = 0; n < M; ++n) a[n] = v[n];
+    dft_reg<M, SIGN>(a);
+#pragma unroll
+    for (int n = 0; n < M; ++n) v[n] = a[n];
+  }
+#pragma unroll
+  for (int k1 = 1; k1 < M; ++k1) {
+    const float2 t = twl[L.q * k1];  // q k1 < 16 M
     v[k1] = SIGN < 0 ? cmul(v[k1], t) : cmulc(t, v[k1]);
   }
   float2* tb = tbuf + L.b * (16 * 17);
 #pragma unroll
-  for (int k1 = 0; k1 < 16; ++k1) tb[k1 * 17 + L.q] = v[k1];
+  for (int k1 = 0; k1 < M; ++k1) tb[k1 * 17 + L.q] = v[k1];
   __builtin_amdgcn_wave_barrier();
+  const int r = min(L.q, M - 1);
 #pragma unroll
-  for (int n2 = 0; n2 < 16; ++n2) v[n2] = tb[L.q * 17 + n2];
+  for (int n2 = 0; n2 < 16; ++n2) v[n2] = tb[r * 17 + n2];
   __builtin_amdgcn_wave_barrier();  // the buffer is rewritten by the next transform
   dft16_regs<SIGN>(v);
 }
 
-// adjoint vertical pass at nv = 256 (as k_adj_vertical)
-__global__ __launch_bounds__(64 * kVWaves) void k_adj_vertical256(
+// adjoint vertical pass at n_v = 16 M (as k_adj_vertical)
+template <int M>
+__global__ __launch_bounds__(64 * kVWaves) void k_adj_vertical16m(
     const float2* __restrict__ hyb, const float2* __restrict__ coil_cm, float2* __restrict__ x,
     const int32_t* __restrict__ rinv, const float2* __restrict__ twv, int nh, int nt, int nc, int m_max,
     float scale) {
+  constexpr int NV = 16 * M;
   extern __shared__ float2 lds[];
   const int wv = threadIdx.x >> 6;
   const Lane256 L = lane256(threadIdx.x & 63);
+  const bool owner = L.q < M;        // the lane holds output rows L.q + M k2
+  const int qo = min(L.q, M - 1);    // a valid row for the lanes that hold none
   float2* twl = lds;
-  float2* tbuf = lds + 256 + (size_t)wv * kV256Lds;
-  stage_twiddles256(twl, twv);
+  float2* tbuf = lds + NV + (size_t)wv * kV256Lds;
+  stage_twiddles(twl, twv, NV);
   const int ngrp = (nh + kV256Cols - 1) / kV256Cols;
   const int units = nt * ngrp;
   for (int u = blockIdx.x * kVWaves + wv; u < units; u += gridDim.x * kVWaves) {
     const int t = u / ngrp;
     const int i = (u - t * ngrp) * kV256Cols + L.b;
     const bool active = i < nh;
-    int rr[16];
+    int rr[M];
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) rr[n1] = active ? rinv[(size_t)t * 256 + 16 * n1 + L.q] : -1;
+    for (int n1 = 0; n1 < M; ++n1) rr[n1] = active ? rinv[(size_t)t * NV + 16 * n1 + L.q] : -1;
     float2 acc[16];
 #pragma unroll
     for (int k2 = 0; k2 < 16; ++k2) acc[k2] = make_float2(0.f, 0.f);
@@ -361,52 +381,54 @@ __global__ __launch_bounds__(64 * kVWaves) void k_adj_vertical256(
     // latency hides behind the transform (two waves per SIMD cannot hide it
     // otherwise)
     const int ic = active ? i : 0;
-    float2 hn[16];
+    float2 hn[M];
     auto fetch_rows = [&](int c) {
       const float2* src = hyb + (((size_t)t * nc + c) * nh + ic) * m_max;
 #pragma unroll
-      for (int n = 0; n < 16; ++n) hn[n] = rr[n] >= 0 ? src[rr[n]] : make_float2(0.f, 0.f);
+      for (int n = 0; n < M; ++n) hn[n] = rr[n] >= 0 ? src[rr[n]] : make_float2(0.f, 0.f);
     };
     fetch_rows(0);
     for (int c = 0; c < nc; ++c) {
       float2 v[16], sv[16];
 #pragma unroll
-      for (int n = 0; n < 16; ++n) v[n] = hn[n];
+      for (int n = 0; n < M; ++n) v[n] = hn[n];
       if (c + 1 < nc) fetch_rows(c + 1);
-      const float2* cs = coil_cm + ((size_t)c * nh + ic) * 256 + L.q;
+      const float2* cs = coil_cm + ((size_t)c * nh + ic) * NV + qo;
 #pragma unroll
-      for (int k2 = 0; k2 < 16; ++k2) sv[k2] = active ? cs[16 * k2] : make_float2(0.f, 0.f);
-      fft256_lanes<+1>(v, twl, tbuf, L);
+      for (int k2 = 0; k2 < 16; ++k2) sv[k2] = active ? cs[M * k2] : make_float2(0.f, 0.f);
+      fft16m_lanes<M, +1>(v, twl, tbuf, L);
 #pragma unroll
       for (int k2 = 0; k2 < 16; ++k2) acc[k2] = cfmac(sv[k2], v[k2], acc[k2]);
     }
-    if (active) {
-      float2* xs = x + ((size_t)t * nh + i) * 256 + L.q;
+    if (active && owner) {
+      float2* xs = x + ((size_t)t * nh + i) * NV + L.q;
 #pragma unroll
-      for (int k2 = 0; k2 < 16; ++k2) xs[16 * k2] = cscale(acc[k2], scale);
+      for (int k2 = 0; k2 < 16; ++k2) xs[M * k2] = cscale(acc[k2], scale);
     }
   }
 }
 
-// forward vertical pass at nv = 256 (as k_fwd_vertical, both modes).  After
+// forward vertical pass at n_v = 16 M (as k_fwd_vertical, both modes).  After
 // each transform the lanes drop their sampled outputs into the (then free)
 // transpose buffer at slot r of their column, and the wave walks the m
 // sampled values of its columns in r order: hybrid rows are stored (or
 // compared with the reference rows) contiguously, and the FP64 residual is
 // formed for the sampled values only.
-template <int MODE>
-__global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical256(
+template <int M, int MODE>
+__global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical16m(
     const float2* __restrict__ x, const float2* __restrict__ coil_cm, float2* __restrict__ hyb,
     const float2* __restrict__ ref, const int32_t* __restrict__ rinv, const int32_t* __restrict__ mcnt,
     const float2* __restrict__ twv, int nh, int nt, int nc, int m_max, float scale, float tvl,
     double* __restrict__ part) {
+  constexpr int NV = 16 * M;
   extern __shared__ float2 lds[];
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const Lane256 L = lane256(lane);
+  const bool owner = L.q < M;  // the lane holds output rows L.q + M k2
   float2* twl = lds;
-  float2* tbuf = lds + 256 + (size_t)wv * kV256Lds;
-  stage_twiddles256(twl, twv);
+  float2* tbuf = lds + NV + (size_t)wv * kV256Lds;
+  stage_twiddles(twl, twv, NV);
   const int ngrp = (nh + kV256Cols - 1) / kV256Cols;
   const int units = nt * ngrp;
   double acc = 0.0, l1 = 0.0;
@@ -417,34 +439,34 @@ __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical256(
     const bool active = i < nh;
     const int m = mcnt[t];
     const int ncol = min(kV256Cols, nh - i0);
-    // image rows 16 n1 + q of column i; hybrid row index of the output rows q + 16 k2
-    float2 xv[16];
+    // image rows 16 n1 + q of column i; hybrid row index of the output rows q + M k2
+    float2 xv[M];
     int ro[16];
-    const float2* xs = x + ((size_t)t * nh + (active ? i : 0)) * 256 + L.q;
+    const float2* xs = x + ((size_t)t * nh + (active ? i : 0)) * NV + L.q;
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) xv[n1] = active ? xs[16 * n1] : make_float2(0.f, 0.f);
+    for (int n1 = 0; n1 < M; ++n1) xv[n1] = active ? xs[16 * n1] : make_float2(0.f, 0.f);
 #pragma unroll
-    for (int k2 = 0; k2 < 16; ++k2) ro[k2] = active ? rinv[(size_t)t * 256 + L.q + 16 * k2] : -1;
+    for (int k2 = 0; k2 < 16; ++k2) ro[k2] = (active && owner) ? rinv[(size_t)t * NV + L.q + M * k2] : -1;
     if (MODE == kFwdResidual && tvl > 0.f && active && t + 1 < nt) {
-      const float2* xn = xs + (size_t)nh * 256;
+      const float2* xn = xs + (size_t)nh * NV;
 #pragma unroll
-      for (int n1 = 0; n1 < 16; ++n1) l1 += cabs_diff(xn[16 * n1], xv[n1]);
+      for (int n1 = 0; n1 < M; ++n1) l1 += cabs_diff(xn[16 * n1], xv[n1]);
     }
     // coil c + 1's map values are requested before coil c is transformed
     const int ic = active ? i : 0;
-    float2 sn[16];
+    float2 sn[M];
     auto fetch_coil = [&](int c) {
-      const float2* cs = coil_cm + ((size_t)c * nh + ic) * 256 + L.q;
+      const float2* cs = coil_cm + ((size_t)c * nh + ic) * NV + L.q;
 #pragma unroll
-      for (int n = 0; n < 16; ++n) sn[n] = active ? cs[16 * n] : make_float2(0.f, 0.f);
+      for (int n = 0; n < M; ++n) sn[n] = active ? cs[16 * n] : make_float2(0.f, 0.f);
     };
     fetch_coil(0);
     for (int c = 0; c < nc; ++c) {
       float2 v[16];
 #pragma unroll
-      for (int n = 0; n < 16; ++n) v[n] = cmul(sn[n], xv[n]);
+      for (int n = 0; n < M; ++n) v[n] = cmul(sn[n], xv[n]);
       if (c + 1 < nc) fetch_coil(c + 1);
-      fft256_lanes<-1>(v, twl, tbuf, L);
+      fft16m_lanes<M, -1>(v, twl, tbuf, L);
       float2* slots = tbuf + L.b * (16 * 17);
 #pragma unroll
       for (int k2 = 0; k2 < 16; ++k2)
@@ -469,22 +491,20 @@ __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical256(
   if constexpr (MODE == kFwdResidual) store_block_partial<64 * kVWaves>(acc + (double)tvl * l1, part);
 }
 
-// ---------------------------------------------------------------- length-256 horizontal passes
-//
-// nh = 256: a workgroup of 4 waves owns 16 sampled rows of one (frame, coil);
-// lane (b, q) of wave w holds row 4 w + b with the same 16 x 16 split as the
-// vertical passes.  The hybrid side [i][r] goes through a workgroup LDS tile
-// of 16 rows x 257 values (rows padded by one value), so hybrid rows move as
-// 16 contiguous values per readout column.
-constexpr int kH256Rows = 16;                        // sampled rows per workgroup
-constexpr int kH256Stride = 257;                     // LDS tile row stride (values)
-constexpr size_t kLdsH256 = (256 + (size_t)kVWaves * kV256Lds) * sizeof(float2);
-static_assert(kH256Rows * kH256Stride <= kVWaves * kV256Lds, "the row tile reuses the transform buffers");
+// Horizontal passes at n_h = 16 M: a workgroup of 4 waves owns 16 sampled rows
+// of one (frame, coil); lane (b, q) of wave w holds row 4 w + b.  The hybrid
+// side [i][r] goes through a workgroup LDS tile of 16 rows x (n_h + 1) values,
+// so hybrid rows move as 16 contiguous values per readout column.
+constexpr int kH256Rows = 16;  // sampled rows per workgroup
+constexpr size_t kLds16m = (256 + (size_t)kVWaves * kV256Lds) * sizeof(float2);  // any M <= 16
+static_assert(kH256Rows * 257 <= kVWaves * kV256Lds, "the row tile reuses the transform buffers");
 
-// hyb[t][c][i][r] = (1/16) F_h' y[t][c][rows[t][r]][i]
-__global__ __launch_bounds__(64 * kVWaves) void k_adj_horizontal256(
+// hyb[t][c][i][r] = (1/sqrt nh) F_h' y[t][c][rows[t][r]][i]
+template <int M>
+__global__ __launch_bounds__(64 * kVWaves) void k_adj_horizontal16m(
     const float2* __restrict__ y, float2* __restrict__ hyb, const int32_t* __restrict__ rows,
     const int32_t* __restrict__ mcnt, const float2* __restrict__ twh, int nv, int nc, int m_max, float scale) {
+  constexpr int NH = 16 * M, STRIDE = NH + 1;
   extern __shared__ float2 lds[];
   const int r0 = blockIdx.x * kH256Rows, t = blockIdx.y, c = blockIdx.z;
   const int m = mcnt[t];
@@ -492,35 +512,39 @@ __global__ __launch_bounds__(64 * kVWaves) void k_adj_horizontal256(
   const int wv = threadIdx.x >> 6;
   const Lane256 L = lane256(threadIdx.x & 63);
   float2* twl = lds;
-  float2* tiles = lds + 256;
+  float2* tiles = lds + NH;
   float2* tbuf = tiles + (size_t)wv * kV256Lds;
-  stage_twiddles256(twl, twh);
+  stage_twiddles(twl, twh, NH);
   const int R = 4 * wv + L.b;  // row of the tile
   const bool active = r0 + R < m;
   float2 v[16];
   {
     const int ky = active ? rows[(size_t)t * m_max + r0 + R] : 0;
-    const float2* src = y + ((size_t)(t * nc + c) * nv + ky) * 256 + L.q;
+    const float2* src = y + ((size_t)(t * nc + c) * nv + ky) * NH + L.q;
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) v[n1] = active ? src[16 * n1] : make_float2(0.f, 0.f);
+    for (int n1 = 0; n1 < M; ++n1) v[n1] = active ? src[16 * n1] : make_float2(0.f, 0.f);
   }
-  fft256_lanes<+1>(v, twl, tbuf, L);
+  fft16m_lanes<M, +1>(v, twl, tbuf, L);
   __syncthreads();  // every wave is done with its transform buffer
+  if (L.q < M) {
 #pragma unroll
-  for (int k2 = 0; k2 < 16; ++k2) tiles[R * kH256Stride + L.q + 16 * k2] = cscale(v[k2], scale);
+    for (int k2 = 0; k2 < 16; ++k2) tiles[R * STRIDE + L.q + M * k2] = cscale(v[k2], scale);
+  }
   __syncthreads();
   const int nrow = min(kH256Rows, m - r0);
-  float2* dst = hyb + ((size_t)(t * nc + c) * 256) * m_max + r0;
-  for (int e = threadIdx.x; e < 256 * kH256Rows; e += 64 * kVWaves) {
+  float2* dst = hyb + ((size_t)(t * nc + c) * NH) * m_max + r0;
+  for (int e = threadIdx.x; e < NH * kH256Rows; e += 64 * kVWaves) {
     const int rr = e & (kH256Rows - 1), i = e >> 4;
-    if (rr < nrow) dst[(size_t)i * m_max + rr] = tiles[rr * kH256Stride + i];
+    if (rr < nrow) dst[(size_t)i * m_max + rr] = tiles[rr * STRIDE + i];
   }
 }
 
-// y[t][c][rows[t][r]][:] = (1/16) F_h hyb[t][c][:][r]
-__global__ __launch_bounds__(64 * kVWaves) void k_fwd_horizontal256(
+// y[t][c][rows[t][r]][:] = (1/sqrt nh) F_h hyb[t][c][:][r]
+template <int M>
+__global__ __launch_bounds__(64 * kVWaves) void k_fwd_horizontal16m(
     const float2* __restrict__ hyb, float2* __restrict__ y, const int32_t* __restrict__ rows,
     const int32_t* __restrict__ mcnt, const float2* __restrict__ twh, int nv, int nc, int m_max, float scale) {
+  constexpr int NH = 16 * M, STRIDE = NH + 1;
   extern __shared__ float2 lds[];
   const int r0 = blockIdx.x * kH256Rows, t = blockIdx.y, c = blockIdx.z;
   const int m = mcnt[t];
@@ -528,26 +552,26 @@ __global__ __launch_bounds__(64 * kVWaves) void k_fwd_horizontal256(
   const int wv = threadIdx.x >> 6;
   const Lane256 L = lane256(threadIdx.x & 63);
   float2* twl = lds;
-  float2* tiles = lds + 256;
+  float2* tiles = lds + NH;
   float2* tbuf = tiles + (size_t)wv * kV256Lds;
-  for (int q = threadIdx.x; q < 256; q += blockDim.x) twl[q] = twh[q];
+  for (int q = threadIdx.x; q < NH; q += blockDim.x) twl[q] = twh[q];
   const int nrow = min(kH256Rows, m - r0);
-  const float2* src = hyb + ((size_t)(t * nc + c) * 256) * m_max + r0;
-  for (int e = threadIdx.x; e < 256 * kH256Rows; e += 64 * kVWaves) {
+  const float2* src = hyb + ((size_t)(t * nc + c) * NH) * m_max + r0;
+  for (int e = threadIdx.x; e < NH * kH256Rows; e += 64 * kVWaves) {
     const int rr = e & (kH256Rows - 1), i = e >> 4;
-    tiles[rr * kH256Stride + i] = rr < nrow ? src[(size_t)i * m_max + rr] : make_float2(0.f, 0.f);
+    tiles[rr * STRIDE + i] = rr < nrow ? src[(size_t)i * m_max + rr] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   const int R = 4 * wv + L.b;
   float2 v[16];
 #pragma unroll
-  for (int n1 = 0; n1 < 16; ++n1) v[n1] = tiles[R * kH256Stride + 16 * n1 + L.q];
+  for (int n1 = 0; n1 < M; ++n1) v[n1] = tiles[R * STRIDE + 16 * n1 + L.q];
   __syncthreads();  // the transform buffers overlay the tile
-  fft256_lanes<-1>(v, twl, tbuf, L);
-  if (R < nrow) {
-    float2* dst = y + ((size_t)(t * nc + c) * nv + rows[(size_t)t * m_max + r0 + R]) * 256 + L.q;
+  fft16m_lanes<M, -1>(v, twl, tbuf, L);
+  if (R < nrow && L.q < M) {
+    float2* dst = y + ((size_t)(t * nc + c) * nv + rows[(size_t)t * m_max + r0 + R]) * NH + L.q;
 #pragma unroll
-    for (int k2 = 0; k2 < 16; ++k2) dst[16 * k2] = cscale(v[k2], scale);
+    for (int k2 = 0; k2 < 16; ++k2) dst[M * k2] = cscale(v[k2], scale);
   }
 }
 
@@ -605,13 +629,32 @@ static unsigned vertical_grid(const cs_plan* p, int cw) {
   return (unsigned)std::min<size_t>((units + kVWaves - 1) / kVWaves, 65535);
 }
 
-// nv = 256: blocks of kVWaves waves, one wave per group of kV256Cols columns
-// of one frame (at most 65535 blocks; the kernels loop over further groups)
-static unsigned grid256(int nh, int nt) {
+// register passes (n = 16 M): blocks of kVWaves waves, one wave per group of
+// kV256Cols columns of one frame (at most 65535 blocks; the kernels loop over
+// further groups)
+static unsigned grid16m(int nh, int nt) {
   const size_t units = (size_t)nt * ((nh + kV256Cols - 1) / kV256Cols);
   return (unsigned)std::min<size_t>((units + kVWaves - 1) / kVWaves, 65535);
 }
-static constexpr size_t kLds256 = (256 + (size_t)kVWaves * kV256Lds) * sizeof(float2);
+
+// the sizes that take the register passes: n = 16 M for M = 4, 6, 8, 9, 12,
+// 16 (n = 64 ... 256 among the supported sizes; smaller M would leave most
+// lanes of the second transform idle)
+bool reg16_size(int n) {
+  const int m = n / 16;
+  return n % 16 == 0 && (m == 4 || m == 6 || m == 8 || m == 9 || m == 12 || m == 16);
+}
+template <class F>
+static void reg16_switch(int n, F&& f) {
+  switch (n / 16) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 9: f(std::integral_constant<int, 9>{}); break;
+    case 12: f(std::integral_constant<int, 12>{}); break;
+    default: f(std::integral_constant<int, 16>{}); break;
+  }
+}
 
 int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipStream_t s) {
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
@@ -623,10 +666,13 @@ int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipS
     }
     const int cw = fft_cols_per_group(p);
     const float sv = 1.0f / std::sqrt((float)nv), sh = 1.0f / std::sqrt((float)nh);
-    if (nv == 256) {
-      hipLaunchKernelGGL(k_fwd_vertical256<kFwdStore>, dim3(grid256(nh, nt)), dim3(64 * kVWaves), kLds256, s, x,
-                         p->coil_cm, p->ftmp, nullptr, p->rinv, p->mcnt, p->tw_v, nh, nt, nc, p->m_max, sv, 0.f,
-                         nullptr);
+    if (reg16_size(nv)) {
+      reg16_switch(nv, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        hipLaunchKernelGGL((k_fwd_vertical16m<M, kFwdStore>), dim3(grid16m(nh, nt)), dim3(64 * kVWaves), kLds16m, s,
+                           x, p->coil_cm, p->ftmp, nullptr, p->rinv, p->mcnt, p->tw_v, nh, nt, nc, p->m_max, sv, 0.f,
+                           nullptr);
+      });
     } else {
       auto k = cw * nv <= 256 ? k_fwd_vertical<kFwdStore, 256> : k_fwd_vertical<kFwdStore, 512>;
       hipLaunchKernelGGL(k, dim3(vertical_grid(p, cw)), dim3(64 * kVWaves), vertical_lds(p, cw), s, x, p->coil_cm,
@@ -634,9 +680,12 @@ int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipS
                          0.f, nullptr);
     }
     CS_HIP(hipGetLastError());
-    if (y && nh == 256) {
-      hipLaunchKernelGGL(k_fwd_horizontal256, dim3(ceil_div(p->m_max, kH256Rows), nt, nc), dim3(64 * kVWaves),
-                         kLdsH256, s, p->ftmp, y, p->rows, p->mcnt, p->tw_h, nv, nc, p->m_max, sh);
+    if (y && reg16_size(nh)) {
+      reg16_switch(nh, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        hipLaunchKernelGGL((k_fwd_horizontal16m<M>), dim3(ceil_div(p->m_max, kH256Rows), nt, nc), dim3(64 * kVWaves),
+                           kLds16m, s, p->ftmp, y, p->rows, p->mcnt, p->tw_h, nv, nc, p->m_max, sh);
+      });
       CS_HIP(hipGetLastError());
     } else if (y) {
       const int rb = fft_rows_per_group(p);
@@ -658,10 +707,13 @@ int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nbloc
                             hipStream_t s) {
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt, nc = p->desc.nc;
   const int cw = fft_cols_per_group(p);
-  if (nv == 256) {
-    hipLaunchKernelGGL(k_fwd_vertical256<kFwdResidual>, dim3(nblocks), dim3(64 * kVWaves), kLds256, s, x,
-                       p->coil_cm, nullptr, p->ktmp, p->rinv, p->mcnt, p->tw_v, nh, nt, nc, p->m_max, 1.0f / 16.0f,
-                       tv_lambda, part);
+  if (reg16_size(nv)) {
+    reg16_switch(nv, [&](auto mc) {
+      constexpr int M = decltype(mc)::value;
+      hipLaunchKernelGGL((k_fwd_vertical16m<M, kFwdResidual>), dim3(nblocks), dim3(64 * kVWaves), kLds16m, s, x,
+                         p->coil_cm, nullptr, p->ktmp, p->rinv, p->mcnt, p->tw_v, nh, nt, nc, p->m_max,
+                         1.0f / std::sqrt((float)nv), tv_lambda, part);
+    });
     CS_HIP(hipGetLastError());
     return CS_OK;
   }
@@ -675,9 +727,12 @@ int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nbloc
 
 int launch_adjoint_rows_raw(const float2* y, float2* hyb, const int32_t* rows, const int32_t* mcnt, const FftDesc& fh,
                             const float2* twh, int nv, int nh, int nt, int nc, int m_max, int rb, hipStream_t s) {
-  if (nh == 256) {
-    hipLaunchKernelGGL(k_adj_horizontal256, dim3(ceil_div(m_max, kH256Rows), nt, nc), dim3(64 * kVWaves), kLdsH256,
-                       s, y, hyb, rows, mcnt, twh, nv, nc, m_max, 1.0f / 16.0f);
+  if (reg16_size(nh)) {
+    reg16_switch(nh, [&](auto mc) {
+      constexpr int M = decltype(mc)::value;
+      hipLaunchKernelGGL((k_adj_horizontal16m<M>), dim3(ceil_div(m_max, kH256Rows), nt, nc), dim3(64 * kVWaves),
+                         kLds16m, s, y, hyb, rows, mcnt, twh, nv, nc, m_max, 1.0f / std::sqrt((float)nh));
+    });
     CS_HIP(hipGetLastError());
     return CS_OK;
   }
@@ -692,9 +747,12 @@ int launch_adjoint_rows_raw(const float2* y, float2* hyb, const int32_t* rows, c
 int launch_adjoint_vertical_raw(const float2* hyb, const float2* coil_cm, float2* x, const int32_t* rows,
                                 const int32_t* mcnt, const int32_t* rinv, const FftDesc& fv, const float2* twv,
                                 int nv, int nh, int nt, int nc, int m_max, int cw, hipStream_t s) {
-  if (nv == 256) {
-    hipLaunchKernelGGL(k_adj_vertical256, dim3(grid256(nh, nt)), dim3(64 * kVWaves), kLds256, s, hyb, coil_cm, x,
-                       rinv, twv, nh, nt, nc, m_max, 1.0f / 16.0f);
+  if (reg16_size(nv)) {
+    reg16_switch(nv, [&](auto mc) {
+      constexpr int M = decltype(mc)::value;
+      hipLaunchKernelGGL((k_adj_vertical16m<M>), dim3(grid16m(nh, nt)), dim3(64 * kVWaves), kLds16m, s, hyb, coil_cm,
+                         x, rinv, twv, nh, nt, nc, m_max, 1.0f / std::sqrt((float)nv));
+    });
     CS_HIP(hipGetLastError());
     return CS_OK;
   }
