@@ -2203,9 +2203,63 @@ __global__ __launch_bounds__(256) void k_l1_dft_tiles(const float* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// the same sum with Psi as the lane-group FFT (nt = L N2): 64 / L pixels per
+// wave, the forward step's own transform and scaling
+template <int L, int N2>
+__global__ __launch_bounds__(256) void k_l1_dft_fft(const float2* __restrict__ x, size_t npix,
+                                                    double* __restrict__ part) {
+  constexpr float kScale = (float)cx_rsqrt(L * N2);
+  constexpr int P = 64 / L;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int col = lane / L, j = lane % L;
+  const int nw = blockDim.x >> 6;
+  const size_t ntiles = (npix + P - 1) / P;
+  const GroupRoots<L, N2> roots = group_roots<L, N2>(j);
+  double acc = 0.0;
+  for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
+    const size_t p0 = tl * P;
+    const int count = (int)std::min<size_t>(P, npix - p0);
+    const uint32_t cc = (uint32_t)min(col, count - 1);
+    const uint32_t offT = 8u * (cc + (uint32_t)(j * npix));
+    float2 w[N2];
+#pragma unroll
+    for (int n = 0; n < N2; ++n) w[n] = ld_off(x + p0 + (size_t)n * L * npix, offT);
+    group_fft_time_to_freq<L, N2, -1>(w, j, roots);
+    if (col < count) {
+#pragma unroll
+      for (int k = 0; k < N2; ++k) {
+        const double a = cscale(w[k], kScale).x, b = cscale(w[k], kScale).y;
+        acc += sqrt(a * a + b * b);
+      }
+    }
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int k = (int)blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 template <int KP>
 static int l1_dft_launch(cs_plan* p, const float2* x, double* part, hipStream_t s) {
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
+  constexpr int k8 = KP / 16, k4 = KP / 8 - 1;  // the group-FFT lengths whose nt has this KP
+  const int nt = p->desc.nt, lanes = tdft_lanes(nt);
+  if constexpr (tdft_len_ok(k8))
+    if (lanes == 8 && nt == 8 * k8) {
+      hipLaunchKernelGGL((k_l1_dft_fft<8, k8>), dim3(kJBlocks), dim3(256), 0, s, x, npix, part);
+      CS_HIP(hipGetLastError());
+      return CS_OK;
+    }
+  if constexpr (k4 % 2 == 1 && tdft_len_ok(k4))
+    if (lanes == 4 && nt == 4 * k4) {
+      hipLaunchKernelGGL((k_l1_dft_fft<4, k4>), dim3(kJBlocks), dim3(256), 0, s, x, npix, part);
+      CS_HIP(hipGetLastError());
+      return CS_OK;
+    }
   const int waves = dft_waves(KP);
   const size_t lds = dft_lds_bytes(KP, waves);
   CS_HIP_STATUS(ensure_dynamic_lds((const void*)k_l1_dft_tiles<KP>, lds));
