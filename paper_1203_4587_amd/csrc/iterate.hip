@@ -5,7 +5,6 @@
 // x-update is nv contiguous values and one pixel's time series is a stride-
 // (nv*nh) sequence read coalesced across neighbouring pixels.
 #include "internal.hpp"
-#include "tdft.hpp"
 
 namespace csmri {
 
@@ -469,6 +468,10 @@ int launch_block_solve(cs_plan* p, int mode, const float2* hy, const float2* m, 
 
 // ---------------------------------------------------------------- TV step
 // (defined after the MFMA tile helpers of the temporal DFT, which it shares)
+
+}  // namespace csmri
+#include "tdft.hpp"  // the temporal DFT as a register FFT over lane groups
+namespace csmri {
 
 // ---------------------------------------------------------------- temporal DFT on MFMA
 //
