@@ -492,13 +492,6 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
   };
   std::vector<float2> htwv = twiddles(nv), htwh = twiddles(nh);
   // unitary temporal DFT: Psi[f][t] = exp(-2 pi i f t / nt) / sqrt(nt)
-  std::vector<float2> hpsi((size_t)nt * nt);
-  for (int f = 0; f < nt; ++f)
-    for (int t = 0; t < nt; ++t) {
-      const double ang = -2.0 * M_PI * (double)((f * t) % nt) / nt;
-      hpsi[(size_t)f * nt + t] =
-          make_float2((float)(std::cos(ang) / std::sqrt((double)nt)), (float)(std::sin(ang) / std::sqrt((double)nt)));
-    }
   // MFMA fragments of the real 2x2-block embedding of Psi (and of Psi'):
   // Psihat[2f + a][2t + b] = [[Re P, -Im P], [Im P, Re P]], P = Psi[f][t],
   // padded to KP = 2 nt rounded up to 16; Psihat' is its transpose.  Lane l of
@@ -565,7 +558,6 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
       (st = plan_alloc(p, &p->pcol, hp.size(), "pcol")) ||
       (st = plan_alloc(p, &p->tw_v, (size_t)nv, "tw_v")) ||
       (st = plan_alloc(p, &p->tw_h, (size_t)nh, "tw_h")) ||
-      (st = plan_alloc(p, &p->psi_t, hpsi.size(), "psi")) ||
       (st = plan_alloc(p, &p->dft_frags, hfrag.size(), "psi fragments")) ||
       (st = plan_alloc(p, &p->tv_frags, htfrag.size(), "tv fragments")) ||
       (st = plan_alloc(p, &p->coil_cm, npix * nc, "coil")) ||
@@ -595,7 +587,6 @@ int cs_plan_create(const cs_plan_desc* desc, const cs_c64* coil, const uint8_t* 
   UP(p->pcol, hp.data(), hp.size() * sizeof(double2));
   UP(p->tw_v, htwv.data(), htwv.size() * sizeof(float2));
   UP(p->tw_h, htwh.data(), htwh.size() * sizeof(float2));
-  UP(p->psi_t, hpsi.data(), hpsi.size() * sizeof(float2));
   UP(p->dft_frags, hfrag.data(), hfrag.size() * sizeof(float));
   UP(p->tv_frags, htfrag.data(), htfrag.size() * sizeof(float));
 #undef UP

@@ -173,7 +173,6 @@ struct cs_plan {
   csmri::FftDesc fft_v{}, fft_h{};
   float2* tw_v = nullptr;       // exp(-2 pi i q / nv), q < nv
   float2* tw_h = nullptr;
-  float2* psi_t = nullptr;      // [nt][nt] unitary temporal DFT matrix (DFT prior)
   float* dft_frags = nullptr;   // MFMA A-operand fragments of the embedded Psi and Psi' (DFT prior)
   float* tv_frags = nullptr;    // MFMA A-operand fragments of (rho I + D'D)^{-1}, padded to 16 (TV step)
 
