@@ -39,6 +39,8 @@ def _oracle(case, iters, cols=None):
     ((32, 8, 1, 2), 10),        # one frame: Psi = [1; 1] / sqrt(2)
     ((96, 12, 40, 3), 15),      # 80-wide embedding
     ((16, 8, 64, 2), 8),        # maximum frame count
+    ((16, 8, 36, 2), 8),        # register FFT with 4 lanes per pixel (odd per-lane length)
+    ((24, 6, 20, 2), 10),
 ], ids=str)
 def test_frame_solves_match_oracle(shape, iters):
     from paper_1203_4587_amd.api import Plan

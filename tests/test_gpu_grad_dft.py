@@ -60,7 +60,9 @@ def test_forward_ckpt_equals_plain_solve(every):
                                                ((27, 12, 5, 2), 8, 5),     # odd nv: row x-update
                                                ((32, 8, 1, 2), 5, 2),      # one frame: Psi = 1
                                                ((96, 12, 40, 3), 4, 3),    # 80-wide embedding
-                                               ((16, 8, 64, 2), 3, 2)],    # maximum frame count
+                                               ((16, 8, 64, 2), 3, 2),     # maximum frame count
+                                               ((16, 8, 36, 2), 3, 2),     # register FFT, 4 lanes per pixel
+                                               ((24, 8, 20, 2), 3, 2)],
                          ids=str)
 def test_gradient_matches_oracle_reference(shape, iters, every):
     """dL/dy, dL/dlambda, dL/dmu of L = Re<g, x_K> against the FP64 reverse sweep."""

@@ -56,6 +56,13 @@ def test_tv_small_workload_matches_oracle():
     ((512, 4, 6, 2), "tv", 10),      # maximum nv: four row pairs per lane
     ((384, 4, 5, 2), "dft", 10),     # three row pairs per lane (last group partly idle)
     ((6, 512, 4, 2), "tv", 10),      # maximum nh
+    # frame counts of the register FFT of Psi: 8 lanes per pixel (16, 48 frames),
+    # 4 lanes per pixel with an odd per-lane length (4, 36, 60 frames)
+    ((24, 8, 4, 2), "dft", 10),
+    ((16, 8, 16, 2), "dft", 10),
+    ((24, 8, 48, 2), "dft", 10),
+    ((16, 8, 36, 2), "dft", 10),
+    ((16, 6, 60, 2), "dft", 8),
 ], ids=lambda v: str(v))
 def test_solves_match_oracle(shape, prior, iters):
     nv, nh, nt, nc = shape
@@ -203,7 +210,7 @@ FORM_CASES = [((64, 32, 10, 4), "tv"), ((64, 32, 10, 4), "dft"), ((96, 24, 40, 3
               ((96, 24, 40, 3), "tv"), ((192, 16, 32, 4), "dft"), ((192, 16, 24, 4), "tv"),
               ((144, 12, 20, 3), "dft"), ((144, 12, 20, 3), "tv"), ((128, 16, 48, 2), "tv"),
               ((64, 8, 64, 2), "dft"), ((2, 8, 6, 2), "tv"), ((6, 12, 5, 2), "dft"),
-              ((512, 4, 6, 2), "tv"), ((384, 4, 5, 2), "dft")]
+              ((512, 4, 6, 2), "tv"), ((384, 4, 5, 2), "dft"), ((64, 8, 36, 2), "dft"), ((64, 8, 48, 2), "dft")]
 
 
 @pytest.mark.parametrize("shape,prior", FORM_CASES, ids=[f"{s}-{p}" for s, p in FORM_CASES])
