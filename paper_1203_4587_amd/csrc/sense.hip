@@ -15,7 +15,9 @@
 // before its single store).  Between the two passes the sampled rows live in
 // hybrid (ky, i) space as [t][c][i][r] (r < m_max fastest), so the rows of one
 // column are contiguous for the vertical passes.  The row-major [t][j][i]
-// layout of the boundary goes through a tiled transpose.
+// layout of the boundary goes through a tiled transpose.  Lengths n = 16 M
+// (M = 4, 6, 8, 9, 12, 16) take register passes instead of the LDS Stockham
+// FFT: a length-M and a length-16 DFT in registers around one LDS transpose.
 #include "fft.hpp"
 #include "tdft.hpp"
 
