@@ -40,6 +40,8 @@ WORKLOADS = {
     "dft192": dict(name="dft-192x192x40-12c", prior="dft"),
     "tv64": dict(name="tv-64x64x8-4c", prior="tv"),
     "frame192": dict(name="frame-192x192x40-12c", prior="frame", config="dft192"),
+    "paper128tv": dict(name="paper-tv-128x128x22-32c", prior="tv"),
+    "paper128dft": dict(name="paper-dft-128x128x22-32c", prior="dft"),
 }
 
 

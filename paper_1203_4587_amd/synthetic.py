@@ -270,6 +270,17 @@ def _cfg5():
                         sigma=0.005, iters=20, period=12.0, name="tv-192x192x24-12c-unrolled")
 
 
+def _paper(prior: str):
+    """The shape of the paper's own experiment (Sec. V): 128x128 pixels, 22
+    frames, 32 coils, R = 8 variable-density random lines per frame, with the
+    paper's lambda = 0.002 and mu (= mu2) = 0.06, mu2 / mu1 = 0.5, 200
+    iterations; a synthetic phantom stands in for its cardiac cine data."""
+    fam = "cardiac" if prior == "tv" else "periodic"
+    return make_problem(128, 128, 22, 32, 8, 8, prior, fam, 1006 if prior == "tv" else 1007,
+                        lam=0.002, mu=0.06, rho=0.5, sigma=0.005, iters=200, period=11.0,
+                        name=f"paper-{prior}-128x128x22-32c")
+
+
 def batch_slice(s: int):
     """The seeded problem of slice s (0..23) of the 24-slice uneven batch."""
     sp = batch_slice_spec(s)
@@ -284,4 +295,6 @@ CONFIGS = {
     "tv256": _cfg2,
     "dft192": _cfg3,
     "tv192_unrolled": _cfg5,
+    "paper128tv": lambda: _paper("tv"),
+    "paper128dft": lambda: _paper("dft"),
 }

@@ -194,6 +194,21 @@ def _tuned_equals(plan, y, p, x):
         assert torch.equal(plan.solve(y, p.lam, p.iters), x)
 
 
+@pytest.mark.parametrize("name,prior", [("paper128tv", "tv"), ("paper128dft", "dft")])
+def test_paper_shape_128x128x22_32c_sampled_columns(name, prior):
+    """The shape of the paper's experiment (128x128, 22 frames, 32 coils, R=8,
+    lambda 0.002, mu 0.06, 200 iterations) at full size; the oracle recomputes
+    five columns exactly."""
+    case = Case(S.CONFIGS[name]())
+    p = case.p
+    plan, y, x = _run(case, prior, p.lam, p.mu, p.rho, p.iters)
+    cols = _sampled_columns(p.x_true.shape[2])
+    ref = _oracle(case, prior, p.lam, p.mu, p.rho, p.iters, cols=cols)
+    err = rel_l2(x.cpu().numpy()[:, :, cols], ref["x"])
+    print(name, "sampled rel_l2", err)
+    assert err < TOL
+
+
 def test_full_size_dft_192x192x40_12c_sampled_columns():
     case = Case(S.CONFIGS["dft192"]())
     p = case.p
