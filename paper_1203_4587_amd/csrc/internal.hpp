@@ -247,10 +247,13 @@ int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s);
 // [nt] (rows r >= mcnt[t] are neither written nor read), x column-major
 int launch_adjoint_rows_raw(const float2* y, float2* hyb, const int32_t* rows, const int32_t* mcnt, const FftDesc& fh,
                             const float2* twh, int nv, int nh, int nt, int nc, int m_max, int rb, hipStream_t s);
-// rinv [nt][nv]: r of each sampled ky (-1 for the others), read by the nv = 256 kernels
+// rinv [nt][nv]: r of each sampled ky (-1 for the others), read by the nv = 16 M kernels;
+// csplit (1, 2 or 4): coil ranges per column group of those kernels, from
+// coil_split16 of the whole series' shape (frame chunks keep the series' split)
 int launch_adjoint_vertical_raw(const float2* hyb, const float2* coil_cm, float2* x, const int32_t* rows,
                                 const int32_t* mcnt, const int32_t* rinv, const FftDesc& fv, const float2* twv,
-                                int nv, int nh, int nt, int nc, int m_max, int cw, hipStream_t s);
+                                int nv, int nh, int nt, int nc, int m_max, int cw, int csplit, hipStream_t s);
+int coil_split16(int nh, int nt, int nc);
 int launch_transpose(const float2* in, float2* out, int frames, int rows, int cols, hipStream_t s);
 // CS_FLAG_CHECK_FINITE (no-ops without it): CS_EINVAL if the sampled rows of
 // k-space y, or the n values at x, hold a NaN or an infinity; synchronise s

@@ -171,7 +171,7 @@ extern "C" int cs_apply_AH_noalloc(const cs_plan_desc* desc, const cs_c64* coil,
                                       s)) != CS_OK)
       return st;
     if ((st = launch_adjoint_vertical_raw(hyb, coil_cm, img, rows + (size_t)t0 * nv, mcnt + t0, rinv + (size_t)t0 * nv,
-                                          fv, tw_v, nv, nh, f, nc, nv, cw, s)) != CS_OK)
+                                          fv, tw_v, nv, nh, f, nc, nv, cw, coil_split16(nh, nt, nc), s)) != CS_OK)
       return st;
     if ((st = launch_transpose(img, reinterpret_cast<float2*>(x) + (size_t)t0 * iframe, f, nh, nv, s)) != CS_OK)
       return st;

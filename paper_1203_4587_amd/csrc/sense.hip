@@ -351,27 +351,35 @@ __device__ __forceinline__ void fft16m_lanes(float2 (&v)[16], const float2* twl,
   dft16_regs<SIGN>(v);
 }
 
-// adjoint vertical pass at n_v = 16 M (as k_adj_vertical)
+// adjoint vertical pass at n_v = 16 M (as k_adj_vertical).  With csplit > 1
+// (1, 2 or 4) the csplit waves of a workgroup slot share one column group and
+// take contiguous coil ranges each; their sums meet in LDS and are added in
+// wave order, so the result depends on csplit but not on the launch.
 template <int M>
 __global__ __launch_bounds__(64 * kVWaves) void k_adj_vertical16m(
     const float2* __restrict__ hyb, const float2* __restrict__ coil_cm, float2* __restrict__ x,
     const int32_t* __restrict__ rinv, const float2* __restrict__ twv, int nh, int nt, int nc, int m_max,
-    float scale) {
+    int csplit, float scale) {
   constexpr int NV = 16 * M;
   extern __shared__ float2 lds[];
-  const int wv = threadIdx.x >> 6;
-  const Lane256 L = lane256(threadIdx.x & 63);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const Lane256 L = lane256(lane);
   const bool owner = L.q < M;        // the lane holds output rows L.q + M k2
   const int qo = min(L.q, M - 1);    // a valid row for the lanes that hold none
   float2* twl = lds;
   float2* tbuf = lds + NV + (size_t)wv * kV256Lds;
   stage_twiddles(twl, twv, NV);
+  const int upb = kVWaves / csplit;  // column groups per workgroup pass
+  const int slot = wv / csplit, part = wv - slot * csplit;
+  const int c0 = part * nc / csplit, c1 = (part + 1) * nc / csplit;
   const int ngrp = (nh + kV256Cols - 1) / kV256Cols;
   const int units = nt * ngrp;
-  for (int u = blockIdx.x * kVWaves + wv; u < units; u += gridDim.x * kVWaves) {
-    const int t = u / ngrp;
+  // the trip count is uniform over the workgroup (the reduction's barriers)
+  for (int ub = blockIdx.x * upb; ub < units; ub += gridDim.x * upb) {
+    const int u = ub + slot;
+    const int t = min(u, units - 1) / ngrp;
     const int i = (u - t * ngrp) * kV256Cols + L.b;
-    const bool active = i < nh;
+    const bool active = u < units && i < nh;
     int rr[M];
 #pragma unroll
     for (int n1 = 0; n1 < M; ++n1) rr[n1] = active ? rinv[(size_t)t * NV + 16 * n1 + L.q] : -1;
@@ -389,12 +397,12 @@ __global__ __launch_bounds__(64 * kVWaves) void k_adj_vertical16m(
 #pragma unroll
       for (int n = 0; n < M; ++n) hn[n] = rr[n] >= 0 ? src[rr[n]] : make_float2(0.f, 0.f);
     };
-    fetch_rows(0);
-    for (int c = 0; c < nc; ++c) {
+    if (c0 < c1) fetch_rows(c0);
+    for (int c = c0; c < c1; ++c) {
       float2 v[16], sv[16];
 #pragma unroll
       for (int n = 0; n < M; ++n) v[n] = hn[n];
-      if (c + 1 < nc) fetch_rows(c + 1);
+      if (c + 1 < c1) fetch_rows(c + 1);
       const float2* cs = coil_cm + ((size_t)c * nh + ic) * NV + qo;
 #pragma unroll
       for (int k2 = 0; k2 < 16; ++k2) sv[k2] = active ? cs[M * k2] : make_float2(0.f, 0.f);
@@ -402,11 +410,31 @@ __global__ __launch_bounds__(64 * kVWaves) void k_adj_vertical16m(
 #pragma unroll
       for (int k2 = 0; k2 < 16; ++k2) acc[k2] = cfmac(sv[k2], v[k2], acc[k2]);
     }
-    if (active && owner) {
-      float2* xs = x + ((size_t)t * nh + i) * NV + L.q;
+    if (csplit == 1) {
+      if (active && owner) {
+        float2* xs = x + ((size_t)t * nh + i) * NV + L.q;
 #pragma unroll
-      for (int k2 = 0; k2 < 16; ++k2) xs[M * k2] = cscale(acc[k2], scale);
+        for (int k2 = 0; k2 < 16; ++k2) xs[M * k2] = cscale(acc[k2], scale);
+      }
+      continue;
     }
+    // 64 x 16 partial sums per wave in its own transpose buffer (free after
+    // the last transform); wave `part` of the slot adds outputs k2 in
+    // [part * 16 / csplit, (part + 1) * 16 / csplit) over the slot's waves
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) tbuf[k2 * 64 + lane] = acc[k2];
+    __syncthreads();
+    const int kq = 16 / csplit, k0 = part * kq;
+    if (active && owner) {
+      const float2* red = lds + NV + (size_t)(slot * csplit) * kV256Lds;
+      float2* xs = x + ((size_t)t * nh + i) * NV + L.q;
+      for (int k2 = k0; k2 < k0 + kq; ++k2) {
+        float2 a = red[k2 * 64 + lane];
+        for (int w = 1; w < csplit; ++w) a = cadd(a, red[(size_t)w * kV256Lds + k2 * 64 + lane]);
+        xs[M * k2] = cscale(a, scale);
+      }
+    }
+    __syncthreads();  // the next pass rewrites the buffers
   }
 }
 
@@ -415,12 +443,14 @@ __global__ __launch_bounds__(64 * kVWaves) void k_adj_vertical16m(
 // transpose buffer at slot r of their column, and the wave walks the m
 // sampled values of its columns in r order: hybrid rows are stored (or
 // compared with the reference rows) contiguously, and the FP64 residual is
-// formed for the sampled values only.
+// formed for the sampled values only.  A unit of work is a column group of
+// one frame and one of csplit contiguous coil ranges (each coil's rows are
+// its own, so the stored rows do not depend on csplit).
 template <int M, int MODE>
 __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical16m(
     const float2* __restrict__ x, const float2* __restrict__ coil_cm, float2* __restrict__ hyb,
     const float2* __restrict__ ref, const int32_t* __restrict__ rinv, const int32_t* __restrict__ mcnt,
-    const float2* __restrict__ twv, int nh, int nt, int nc, int m_max, float scale, float tvl,
+    const float2* __restrict__ twv, int nh, int nt, int nc, int m_max, int csplit, float scale, float tvl,
     double* __restrict__ part) {
   constexpr int NV = 16 * M;
   extern __shared__ float2 lds[];
@@ -432,11 +462,13 @@ __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical16m(
   float2* tbuf = lds + NV + (size_t)wv * kV256Lds;
   stage_twiddles(twl, twv, NV);
   const int ngrp = (nh + kV256Cols - 1) / kV256Cols;
-  const int units = nt * ngrp;
+  const int units = nt * ngrp * csplit;  // (frame, column group, coil range)
   double acc = 0.0, l1 = 0.0;
   for (int u = blockIdx.x * kVWaves + wv; u < units; u += gridDim.x * kVWaves) {
-    const int t = u / ngrp;
-    const int i0 = (u - t * ngrp) * kV256Cols;  // first column of the group
+    const int g = u / csplit, cp = u - g * csplit;
+    const int c0 = cp * nc / csplit, c1 = (cp + 1) * nc / csplit;
+    const int t = g / ngrp;
+    const int i0 = (g - t * ngrp) * kV256Cols;  // first column of the group
     const int i = i0 + L.b;
     const bool active = i < nh;
     const int m = mcnt[t];
@@ -449,7 +481,7 @@ __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical16m(
     for (int n1 = 0; n1 < M; ++n1) xv[n1] = active ? xs[16 * n1] : make_float2(0.f, 0.f);
 #pragma unroll
     for (int k2 = 0; k2 < 16; ++k2) ro[k2] = (active && owner) ? rinv[(size_t)t * NV + L.q + M * k2] : -1;
-    if (MODE == kFwdResidual && tvl > 0.f && active && t + 1 < nt) {
+    if (MODE == kFwdResidual && tvl > 0.f && active && cp == 0 && t + 1 < nt) {
       const float2* xn = xs + (size_t)nh * NV;
 #pragma unroll
       for (int n1 = 0; n1 < M; ++n1) l1 += cabs_diff(xn[16 * n1], xv[n1]);
@@ -462,12 +494,12 @@ __global__ __launch_bounds__(64 * kVWaves) void k_fwd_vertical16m(
 #pragma unroll
       for (int n = 0; n < M; ++n) sn[n] = active ? cs[16 * n] : make_float2(0.f, 0.f);
     };
-    fetch_coil(0);
-    for (int c = 0; c < nc; ++c) {
+    if (c0 < c1) fetch_coil(c0);
+    for (int c = c0; c < c1; ++c) {
       float2 v[16];
 #pragma unroll
       for (int n = 0; n < M; ++n) v[n] = cmul(sn[n], xv[n]);
-      if (c + 1 < nc) fetch_coil(c + 1);
+      if (c + 1 < c1) fetch_coil(c + 1);
       fft16m_lanes<M, -1>(v, twl, tbuf, L);
       float2* slots = tbuf + L.b * (16 * 17);
 #pragma unroll
@@ -632,11 +664,28 @@ static unsigned vertical_grid(const cs_plan* p, int cw) {
 }
 
 // register passes (n = 16 M): blocks of kVWaves waves, one wave per group of
-// kV256Cols columns of one frame (at most 65535 blocks; the kernels loop over
-// further groups)
-static unsigned grid16m(int nh, int nt) {
-  const size_t units = (size_t)nt * ((nh + kV256Cols - 1) / kV256Cols);
+// kV256Cols columns of one frame and one of csplit coil ranges (at most 65535
+// blocks; the kernels loop over further groups)
+static unsigned grid16m(int nh, int nt, int csplit) {
+  const size_t units = (size_t)nt * ((nh + kV256Cols - 1) / kV256Cols) * csplit;
   return (unsigned)std::min<size_t>((units + kVWaves - 1) / kVWaves, 65535);
+}
+
+// Coil ranges per column group of the register vertical passes.  A lone wave
+// per column group walking all coils leaves the chip short of waves when
+// there are many coils and few frames or columns; then 2 or 4 waves share a
+// group's coil loop (each keeping at least 2 coils).  A function of the shape
+// only, so every caller of a pass on one shape gets the same split and the
+// same rounding.  The thresholds are measured (A, A', J, same box):
+//   groups x coils -> split: effect
+//   384 x 8, 512 x 16, 704 x 32 -> 4: 25-55% faster;  1024 x 16 -> 2: 17-33% faster;
+//   1152 x 12 -> 2: A' 7% slower;  1920 x 12 -> 4, 2048 x 8 -> 2: 5-25% slower
+// (the extra image loads and the LDS reduction cost more than the waves gain).
+constexpr int kSplitMaxGroups = 1024, kSplit4MaxGroups = 767;
+int coil_split16(int nh, int nt, int nc) {
+  const size_t groups = (size_t)nt * ((nh + kV256Cols - 1) / kV256Cols);
+  if (groups > (size_t)kSplitMaxGroups || nc < 4) return 1;
+  return groups <= (size_t)kSplit4MaxGroups && nc >= 8 ? 4 : 2;
 }
 
 // the sizes that take the register passes: n = 16 M for M = 4, 6, 8, 9, 12,
@@ -671,9 +720,10 @@ int launch_forward(cs_plan* p, const float2* x, bool x_colmajor, float2* y, hipS
     if (reg16_size(nv)) {
       reg16_switch(nv, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
-        hipLaunchKernelGGL((k_fwd_vertical16m<M, kFwdStore>), dim3(grid16m(nh, nt)), dim3(64 * kVWaves), kLds16m, s,
-                           x, p->coil_cm, p->ftmp, nullptr, p->rinv, p->mcnt, p->tw_v, nh, nt, nc, p->m_max, sv, 0.f,
-                           nullptr);
+        const int cs = coil_split16(nh, nt, nc);
+        hipLaunchKernelGGL((k_fwd_vertical16m<M, kFwdStore>), dim3(grid16m(nh, nt, cs)), dim3(64 * kVWaves), kLds16m,
+                           s, x, p->coil_cm, p->ftmp, nullptr, p->rinv, p->mcnt, p->tw_v, nh, nt, nc, p->m_max, cs, sv,
+                           0.f, nullptr);
       });
     } else {
       auto k = cw * nv <= 256 ? k_fwd_vertical<kFwdStore, 256> : k_fwd_vertical<kFwdStore, 512>;
@@ -714,7 +764,7 @@ int launch_forward_residual(cs_plan* p, const float2* x, double* part, int nbloc
       constexpr int M = decltype(mc)::value;
       hipLaunchKernelGGL((k_fwd_vertical16m<M, kFwdResidual>), dim3(nblocks), dim3(64 * kVWaves), kLds16m, s, x,
                          p->coil_cm, nullptr, p->ktmp, p->rinv, p->mcnt, p->tw_v, nh, nt, nc, p->m_max,
-                         1.0f / std::sqrt((float)nv), tv_lambda, part);
+                         coil_split16(nh, nt, nc), 1.0f / std::sqrt((float)nv), tv_lambda, part);
     });
     CS_HIP(hipGetLastError());
     return CS_OK;
@@ -748,12 +798,16 @@ int launch_adjoint_rows_raw(const float2* y, float2* hyb, const int32_t* rows, c
 
 int launch_adjoint_vertical_raw(const float2* hyb, const float2* coil_cm, float2* x, const int32_t* rows,
                                 const int32_t* mcnt, const int32_t* rinv, const FftDesc& fv, const float2* twv,
-                                int nv, int nh, int nt, int nc, int m_max, int cw, hipStream_t s) {
+                                int nv, int nh, int nt, int nc, int m_max, int cw, int csplit, hipStream_t s) {
   if (reg16_size(nv)) {
+    if (csplit != 1 && csplit != 2 && csplit != 4) return CS_EINVAL;
     reg16_switch(nv, [&](auto mc) {
       constexpr int M = decltype(mc)::value;
-      hipLaunchKernelGGL((k_adj_vertical16m<M>), dim3(grid16m(nh, nt)), dim3(64 * kVWaves), kLds16m, s, hyb, coil_cm,
-                         x, rinv, twv, nh, nt, nc, m_max, 1.0f / std::sqrt((float)nv));
+      // csplit waves per column group: kVWaves / csplit groups per block
+      const size_t units = (size_t)nt * ((nh + kV256Cols - 1) / kV256Cols);
+      const unsigned grid = (unsigned)std::min<size_t>((units * csplit + kVWaves - 1) / kVWaves, 65535);
+      hipLaunchKernelGGL((k_adj_vertical16m<M>), dim3(grid), dim3(64 * kVWaves), kLds16m, s, hyb, coil_cm, x, rinv,
+                         twv, nh, nt, nc, m_max, csplit, 1.0f / std::sqrt((float)nv));
     });
     CS_HIP(hipGetLastError());
     return CS_OK;
@@ -778,7 +832,8 @@ int launch_adjoint_image(cs_plan* p, float2* x, bool x_colmajor, hipStream_t s) 
   const int nv = p->desc.nv, nh = p->desc.nh, nt = p->desc.nt;
   float2* xo = x_colmajor ? x : p->img_tmp;
   int st = launch_adjoint_vertical_raw(p->ktmp, p->coil_cm, xo, p->rows, p->mcnt, p->rinv, p->fft_v, p->tw_v, nv,
-                                       nh, nt, p->desc.nc, p->m_max, fft_cols_per_group(p), s);
+                                       nh, nt, p->desc.nc, p->m_max, fft_cols_per_group(p),
+                                       coil_split16(nh, nt, p->desc.nc), s);
   if (st != CS_OK) return st;
   if (!x_colmajor) return launch_transpose(p->img_tmp, x, nt, nh, nv, s);
   return CS_OK;

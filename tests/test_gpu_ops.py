@@ -29,7 +29,10 @@ def _plan(case, mu=0.1, prior="tv"):
 # than one row tile, and with a ragged last tile of rows or columns)
 SHAPES = [(64, 64, 8, 4), (96, 128, 3, 2), (192, 96, 2, 3), (27, 12, 3, 2), (6, 4, 2, 1),
           (256, 48, 2, 2), (128, 81, 2, 5), (512, 8, 2, 1), (8, 512, 2, 1), (48, 256, 3, 2),
-          (256, 256, 2, 3), (256, 18, 3, 2)]
+          (256, 256, 2, 3), (256, 18, 3, 2),
+          # few column groups, many coils: the register vertical passes split
+          # the coil loop over 4 waves (uneven ranges 2, 2, 2, 3) and 2 waves
+          (128, 54, 3, 9), (96, 18, 2, 6)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=[f"{a}x{b}x{c}x{d}" for a, b, c, d in SHAPES])

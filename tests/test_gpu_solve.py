@@ -114,7 +114,9 @@ def test_zero_iterations_return_initialisation(prior):
                                          ("dft", (27, 12, 40, 2)),   # 324 pixels: ragged last tile, KP = 80
                                          ("dft", (16, 6, 64, 2)),    # maximum frame count, KP = 128
                                          ("tv", (27, 12, 40, 2)),
-                                         ("tv", (384, 4, 5, 2))], ids=str)      # 512-value wave FFT groups
+                                         ("tv", (384, 4, 5, 2)),     # 512-value wave FFT groups
+                                         # data term with the coil loop split over 4 and 2 waves
+                                         ("tv", (64, 18, 6, 9)), ("dft", (96, 18, 8, 6))], ids=str)
 def test_objective_trace_matches_oracle(prior, shape):
     fam = "cardiac" if prior == "tv" else "periodic"
     nv, nh, nt, nc = shape
