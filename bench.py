@@ -327,6 +327,31 @@ def stream_context(achieved) -> dict:
     return out
 
 
+def same_bytes_copy(nbytes: int, reps: int = 50) -> dict:
+    """A plain device copy moving nbytes in all (nbytes / 2 read, nbytes / 2
+    written), each copy between its own pair of HIP events on the current
+    stream, as the library times each launch: the rate a one-shot kernel of
+    that size reaches when it does nothing but move its bytes."""
+    import torch
+    n = max(nbytes // 8, 1)
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3)
+    del a, b
+    us = _median(ts)
+    return {"us_median": round(us, 2), "us_best": round(min(ts), 2), "GBps": round(8 * n / (us * 1e-6) / 1e9, 1)}
+
+
 def step_rows(plan, problem, y, t_plan: float, prior: str) -> dict:
     """Per-step figures beside the iteration: the SENSE forward and adjoint
     passes (torch events on the stream they run on, mean of 20 calls), the
@@ -668,6 +693,15 @@ def main() -> int:
         },
     }
     line["roofline"].update(stream_context(achieved))
+    if tl:
+        # the temporal step against a device copy of the same bytes, both
+        # event-timed per launch
+        t_us = tms / tl * 1e3
+        cp = same_bytes_copy(t_bytes)
+        line["kernels"][f"{tkind}_algorithmic_bytes"] = t_bytes
+        line["kernels"][f"{tkind}_GBps"] = round(t_bytes / (t_us * 1e-6) / 1e9, 1)
+        line["kernels"][f"{tkind}_same_bytes_copy"] = cp
+        line["kernels"][f"{tkind}_frac_of_copy"] = round(cp["us_median"] / t_us, 3)
     if not args.no_rows:
         line["rows"] = step_rows(plan, problem, y, t_plan, wl["prior"])
     # the paper's stopping rule: iterate until Delta(k) < 1e-3 (checked every 5

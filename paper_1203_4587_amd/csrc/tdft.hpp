@@ -163,16 +163,31 @@ __device__ __forceinline__ void dft_reg(float2 (&x)[N]) {
   }
 }
 
-// Lane groups of L = 4 or 8 lanes per pixel.  xor 1 and xor 2 are DPP quad
-// permutes; xor 4 is a bitmask-mode swizzle (lanes exchanged within 32).
+// Exchanges between lanes l and l ^ XOR.  A lane group of L = 4 or 8 lanes
+// per pixel has its members 1 apart (XOR = 1, 2, 4) or 64 / L apart (XOR = 8,
+// 16, 32 for L = 8; 16, 32 for L = 4).  xor 1 and xor 2 are DPP quad
+// permutes, xor 4 a bitmask-mode swizzle (lanes exchanged within 32), xor 8
+// a DPP rotation by 8 within each row of 16 lanes, xor 16 and xor 32 the
+// permlane swaps of rows of 16 and halves of 32 lanes (each returns the
+// swapped pair; a lane takes the copy that came from its partner).
 template <int XOR>
 __device__ __forceinline__ float lane_xor(float v) {
-  if constexpr (XOR == 1)
+  if constexpr (XOR == 1) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
-  else if constexpr (XOR == 2)
+  } else if constexpr (XOR == 2) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
-  else
+  } else if constexpr (XOR == 4) {
     return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (XOR << 10) | 0x1F));
+  } else if constexpr (XOR == 8) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));  // row_ror:8
+  } else if constexpr (XOR == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float((__lane_id() & 16) ? r[0] : r[1]);
+  } else {
+    static_assert(XOR == 32, "lane exchange distance");
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float((__lane_id() & 32) ? r[0] : r[1]);
+  }
 }
 // butterfly between partner lanes: the lane whose bit is clear gets v + w,
 // the other w - v (w the partner's value), as w + sgn v with sgn = -1 on the
@@ -182,6 +197,19 @@ __device__ __forceinline__ float2 lane_butterfly(float2 v, float sgn) {
   const float2 w = make_float2(lane_xor<XOR>(v.x), lane_xor<XOR>(v.y));
   return make_float2(fmaf(sgn, v.x, w.x), fmaf(sgn, v.y, w.y));
 }
+
+// Where a pixel's L lanes sit in the wave: STRIDED = false puts group g on
+// lanes L g + j (member j), STRIDED = true on lanes g + (64 / L) j, so that
+// lanes 0, 1, 2, ... hold consecutive groups (pixels) of one frame and a
+// wave's memory accesses run along the pixels.  LS is the distance between
+// members j and j + 1.
+template <int L, bool STRIDED>
+struct GroupLane {
+  static constexpr int G = 64 / L;  // groups per wave
+  static constexpr int LS = STRIDED ? G : 1;
+  static __device__ __forceinline__ int member(int lane) { return STRIDED ? lane / G : lane % L; }
+  static __device__ __forceinline__ int group(int lane) { return STRIDED ? lane % G : lane / L; }
+};
 
 // The lane's roots, computed once per kernel (they depend only on the lane):
 // exp(-2 pi i j k / nt) for k < N2, and exp(-2 pi i (j mod 4) / 8) for the
@@ -247,13 +275,14 @@ __device__ __forceinline__ int lane_bitrev(int j) {
   else return ((j & 1) << 2) | (j & 2) | (j >> 2);
 }
 
-// forward transform of a lane group (SIGN = -1 for Psi): frames j + L n2 in,
+// forward transform of a lane group (SIGN = -1 for Psi; LS the lane distance
+// between members, GroupLane): frames j + L n2 in,
 // frequencies k2 + N2 bitrev(j) out, unnormalised.  A length-N2 DFT in the
 // lane's registers, the twiddles exp(SIGN 2 pi i j k2 / nt), then a length-L
 // DFT across the group by decimation in frequency (stages xor L/2 .. xor 1,
 // the difference of a stage of half-size h multiplied by exp(SIGN 2 pi i
 // (j mod h) / 2h)).  Every lane of the wave must take part.
-template <int L, int N2, int SIGN>
+template <int L, int N2, int SIGN, int LS = 1>
 __device__ __forceinline__ void group_fft_time_to_freq(float2 (&x)[N2], int j, const GroupRoots<L, N2>& r) {
   dft_reg<N2, SIGN>(x);
 #pragma unroll
@@ -262,27 +291,27 @@ __device__ __forceinline__ void group_fft_time_to_freq(float2 (&x)[N2], int j, c
   for (int k = 0; k < N2; ++k) {
     float2 v = x[k];
     if constexpr (L == 8) {
-      v = lane_butterfly<4>(v, r.sg4);
+      v = lane_butterfly<4 * LS>(v, r.sg4);
       v = root_apply<SIGN>(v, r.c8, r.s8);  // exp(SIGN 2 pi i (j mod 4) / 8) on the high half, else 1
     }
-    v = lane_butterfly<2>(v, r.sg2);
+    v = lane_butterfly<2 * LS>(v, r.sg2);
     if ((j & 3) == 3) v = SIGN > 0 ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);  // * (SIGN i)
-    x[k] = lane_butterfly<1>(v, r.sg1);
+    x[k] = lane_butterfly<LS>(v, r.sg1);
   }
 }
 
 // the reverse steps (decimation in time): frequencies k2 + N2 bitrev(j) in,
 // frames j + L n2 out, unnormalised (SIGN = +1 for Psi')
-template <int L, int N2, int SIGN>
+template <int L, int N2, int SIGN, int LS = 1>
 __device__ __forceinline__ void group_fft_freq_to_time(float2 (&x)[N2], int j, const GroupRoots<L, N2>& r) {
 #pragma unroll
   for (int k = 0; k < N2; ++k) {
-    float2 v = lane_butterfly<1>(x[k], r.sg1);
+    float2 v = lane_butterfly<LS>(x[k], r.sg1);
     if ((j & 3) == 3) v = SIGN > 0 ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);  // * (SIGN i)
-    v = lane_butterfly<2>(v, r.sg2);
+    v = lane_butterfly<2 * LS>(v, r.sg2);
     if constexpr (L == 8) {
       v = root_apply<SIGN>(v, r.c8, r.s8);
-      v = lane_butterfly<4>(v, r.sg4);
+      v = lane_butterfly<4 * LS>(v, r.sg4);
     }
     x[k] = v;
   }
