@@ -941,7 +941,12 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
   constexpr int MT = DftTile<KT>::MT, NK = KT / 4;
   const int col = lane & 15, grp = lane >> 4;
   const bool pv = col < count;
-  const size_t p = p0 + col;
+  // addresses: a wave-uniform base (p0 and the frame step of the unrolled
+  // loop) plus one 32-bit byte offset per lane, the same for every stream
+  // (8 nt npix < 2^32 for every supported size); lanes past the tile's last
+  // pixel use its last pixel's offset and neither keep nor store a value
+  const uint32_t off = 8u * ((uint32_t)min(col, count - 1) + (uint32_t)grp * (uint32_t)npix);
+  const uint32_t offm = 8u * ((uint32_t)min(col, count - 1) + 4u * (uint32_t)grp * (uint32_t)npix);
   // every stream is requested up front (x and d2 are first needed for r):
   // one memory round trip per tile instead of two.  Measured at 256x256x32
   // (one box, three interleaved rounds): 24.4-24.6 us against 25.6-26.1 us
@@ -956,17 +961,17 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
     for (int k = 0; k < NK; ++k) {
       const int t = grp + 4 * k;
       const bool ok = t < nt && pv;
-      const size_t o = (size_t)t * npix + p;
-      mv[k] = ok ? m[o] : make_float2(0.f, 0.f);
-      dv[k] = (ok && t < nt - 1) ? d1[o] : make_float2(0.f, 0.f);
+      const size_t b = p0 + (size_t)(4 * k) * npix;
+      mv[k] = ok ? ld_off(m + b, off) : make_float2(0.f, 0.f);
+      dv[k] = (ok && t < nt - 1) ? ld_off(d1 + b, off) : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
       const int t = grp + 4 * k;
       const bool ok = t < nt && pv;
-      const size_t o = (size_t)t * npix + p;
-      xv[k] = ok ? x[o] : make_float2(0.f, 0.f);
-      zv[k] = ok ? d2[o] : make_float2(0.f, 0.f);
+      const size_t b = p0 + (size_t)(4 * k) * npix;
+      xv[k] = ok ? ld_off(x + b, off) : make_float2(0.f, 0.f);
+      zv[k] = ok ? ld_off(d2 + b, off) : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
@@ -1025,7 +1030,7 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
       const int t = 16 * mm + 4 * grp + j;
       const float2 mv = make_float2(are[mm][j], aim[mm][j]);
       buf0[t * 16 + col] = mv;
-      if (t < nt && pv) m[(size_t)t * npix + p] = mv;
+      if (t < nt && pv) st_off(m + p0 + (size_t)(16 * mm + j) * npix, offm, mv);
     }
   __builtin_amdgcn_wave_barrier();
   // d1_t <- e_t + m_{t+1} - m_t
@@ -1034,7 +1039,7 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
     const int t = grp + 4 * k;
     if (t + 1 < KT && t < nt - 1 && pv) {
       const float2 e0 = buf1[t * 16 + col], m0 = buf0[t * 16 + col], m1 = buf0[(t + 1) * 16 + col];
-      d1[(size_t)t * npix + p] = make_float2(e0.x + m1.x - m0.x, e0.y + m1.y - m0.y);
+      st_off(d1 + p0 + (size_t)(4 * k) * npix, off, make_float2(e0.x + m1.x - m0.x, e0.y + m1.y - m0.y));
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -1044,8 +1049,15 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
 constexpr int tv_wave_floats(int kt) { return 4 * kt * 16; }
 inline int tv_kt(int nt) { return (nt + 15) / 16 * 16; }
 
+// waves per SIMD the TV kernel is compiled for: its LDS (fragments plus two
+// KT x 16 buffers per wave) allows 4 at KT <= 32, where 4 waves of 4096 tiles
+// fill the chip at 256 x 256 pixels in one round; larger KT keep the
+// compiler's choice
 template <int KT>
-__global__ __launch_bounds__(256) void k_tv_tiles(
+constexpr int tv_waves_per_eu() { return KT <= 32 ? 4 : 1; }
+
+template <int KT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tv_waves_per_eu<KT>()))) void k_tv_tiles(
     const float* __restrict__ frags, float2* __restrict__ m,
                                                   float2* __restrict__ d1, const float2* __restrict__ x,
                                                   const float2* __restrict__ d2, int nt, size_t npix, size_t pix0,
