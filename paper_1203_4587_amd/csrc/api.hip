@@ -962,9 +962,18 @@ int cs_plan_tune(cs_plan* p, const cs_c64* y, float lambda, int32_t iters, cs_tu
 
 // ---------------------------------------------------------------- batches
 
+// Branches of the batch graph: the slices are dealt to this many chains in
+// LPT order (the largest factor first, each to the chain with the least work
+// so far), and the chains run concurrently.  Two chains let one slice's
+// temporal steps and set-up run beside another's factor stream; more of them
+// only make the streams compete (24 uneven slices, slice-iterations/s against
+// plain solves: 1 chain x1.00, 2 x1.034-1.037, 3 x1.012, 4 x0.996, one per
+// slice x0.993).
+constexpr size_t kBatchBranches = 2;
+
 struct cs_batch {
   std::vector<cs_plan*> plans;
-  std::vector<hipStream_t> streams;  // one per slice, used only while recording
+  std::vector<hipStream_t> streams;  // one per branch, used only while recording
   std::vector<hipEvent_t> joins;
   hipEvent_t fork = nullptr;
   hipStream_t capture = nullptr;
@@ -1099,14 +1108,16 @@ int cs_batch_solve(cs_batch* b, const cs_c64* const* y, const float* lambda, int
       CS_HIP(hipGraphExecDestroy(b->graph));
       b->graph = nullptr;
     }
+    const size_t nb = std::min(n, kBatchBranches);
     if (!b->capture) {
-      const int ms = batch_make_streams(b, n);
+      const int ms = batch_make_streams(b, nb);
       if (ms != CS_OK) return ms;
     }
-    // record: fork every slice's stream off the capture stream, run each
-    // slice's solve on its stream, join them back.  Slices are recorded in
-    // decreasing order of factor size (longest first, as in LPT scheduling),
-    // so the largest solves are the first to reach the GPU.
+    // record: fork each branch's stream off the capture stream, run its
+    // slices' solves one after another on it, join the branches back.  The
+    // slices go out in decreasing order of factor size, each to the branch
+    // with the least factor work so far (LPT scheduling), so the branches end
+    // close together and the largest solves are the first to reach the GPU.
     std::vector<size_t> order(n);
     for (size_t i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) {
@@ -1115,30 +1126,35 @@ int cs_batch_solve(cs_batch* b, const cs_c64* const* y, const float* lambda, int
     CS_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
     int st = CS_OK;
     hipError_t e = hipEventRecord(b->fork, b->capture);
-    std::vector<char> forked(n, 0);  // slice streams inside the capture and not yet joined back
+    std::vector<char> forked(nb, 0);  // branch streams inside the capture
+    std::vector<double> load(nb, 0.0);
     for (size_t oi = 0; oi < n && st == CS_OK && e == hipSuccess; ++oi) {
       const size_t i = order[oi];
-      e = hipStreamWaitEvent(b->streams[i], b->fork, 0);
-      if (e != hipSuccess) break;
-      forked[i] = 1;
+      const size_t j = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[j] += (double)factor_elems(b->plans[i]->flayout);
+      if (!forked[j]) {
+        e = hipStreamWaitEvent(b->streams[j], b->fork, 0);
+        if (e != hipSuccess) break;
+        forked[j] = 1;
+      }
       cs_plan* p = b->plans[i];
       const bool saved_timing = p->timing;
       const uint32_t saved_flags = p->desc.flags;
       p->timing = false;
       // recorded straight into the batch graph; y was checked above
       p->desc.flags &= ~(uint32_t)(CS_FLAG_GRAPH | CS_FLAG_CHECK_FINITE);
-      st = cs_admm_solve(p, y[i], lambda[i], p->mu, iters, x_out[i], nullptr, nullptr, b->streams[i]);
+      st = cs_admm_solve(p, y[i], lambda[i], p->mu, iters, x_out[i], nullptr, nullptr, b->streams[j]);
       p->timing = saved_timing;
       p->desc.flags = saved_flags;
-      if (st == CS_OK) e = hipEventRecord(b->joins[i], b->streams[i]);
-      if (st == CS_OK && e == hipSuccess) e = hipStreamWaitEvent(b->capture, b->joins[i], 0);
-      if (st == CS_OK && e == hipSuccess) forked[i] = 0;
     }
-    // after a failure every forked stream is still joined back before the
-    // capture ends, so that no stream stays attached to an abandoned capture
-    for (size_t i = 0; i < n; ++i)
-      if (forked[i] && hipEventRecord(b->joins[i], b->streams[i]) == hipSuccess)
-        (void)hipStreamWaitEvent(b->capture, b->joins[i], 0);
+    // every forked branch is joined back before the capture ends (also after
+    // a failure, so that no stream stays attached to an abandoned capture)
+    for (size_t j = 0; j < nb; ++j) {
+      if (!forked[j]) continue;
+      hipError_t ej = hipEventRecord(b->joins[j], b->streams[j]);
+      if (ej == hipSuccess) ej = hipStreamWaitEvent(b->capture, b->joins[j], 0);
+      if (e == hipSuccess) e = ej;
+    }
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->capture, &g);
     if (st != CS_OK || e != hipSuccess || e2 != hipSuccess) {
