@@ -68,6 +68,26 @@ def test_small_uneven_batch_matches_plain_and_oracle():
         assert err < TOL
 
 
+@pytest.mark.parametrize("count", [1, 2, 3])
+def test_batches_of_few_slices_match_plain(count):
+    """The slices are dealt to (at most) two chains of the batch graph: one
+    slice, one slice per chain, and a chain of two beside a chain of one all
+    solve every slice bit for bit as a plain solve does."""
+    from paper_1203_4587_amd.api import Batch, Plan, Slice
+    cases = _small_cases()[:count]
+    dev = [c.device() for c in cases]
+    batch = Batch([Slice(coil, mask, prior, MU, RHO, 0) for (coil, mask, _), (_, prior) in zip(dev, SMALL)])
+    ys = [y for _, _, y in dev]
+    bufs = [torch.empty(batch.image_shape(k), dtype=torch.complex64, device="cuda") for k in range(count)]
+    xs = [t.clone() for t in batch.solve(ys, LAMS[:count], 9, outs=bufs)]
+    xs2 = batch.solve(ys, LAMS[:count], 9, outs=bufs)   # the same pointers: a replay
+    for k in range(count):
+        coil, mask, y = dev[k]
+        plain = Plan(coil, mask, MU, prior=SMALL[k][1], mu_ratio=RHO).solve(y, LAMS[k], 9)
+        assert torch.equal(xs[k], plain), k
+        assert torch.equal(xs2[k], plain), k
+
+
 def test_batch_graph_replay_tracks_data_and_rerecords():
     """A replay reads the current contents of the same buffers; new buffers,
     lambdas or iteration counts record the graph again.  Every replay is
