@@ -277,11 +277,13 @@ int cs_admm_solve_until(cs_plan* plan, const cs_c64* y, float lambda, float mu, 
  * Many independent slices (uneven sizes, coil counts, sampling, priors) solved
  * together.  Each slice is one plan (as cs_plan_create); cs_batch_solve runs
  * every slice's whole solve -- H'y setup and `iters` iterations -- as one
- * hipGraph launch in which the slices are independent branches, so the GPU
- * overlaps them and the host pays one launch per call.  The graph is
- * recorded on the first call and replayed while the pointers, lambdas and
- * iteration count stay the same.  Results equal cs_admm_solve on each slice
- * bit for bit. */
+ * hipGraph launch of two concurrent chains of slices (dealt largest factor
+ * first, each to the chain with less work so far), so the GPU overlaps one
+ * slice's short steps with another's factor stream and the host pays one
+ * launch per call.  The graph is recorded on the first call and replayed
+ * while the pointers, lambdas, iteration count and each slice's mu, form and
+ * FFT tiles stay the same.  Results equal cs_admm_solve on each slice bit for
+ * bit. */
 typedef struct cs_batch cs_batch;
 
 typedef struct {
