@@ -929,24 +929,33 @@ int launch_dft_apply(cs_plan* p, const float2* in, float2* out, float2* dual, co
 // is one real contraction m = T^{-1} r of the padded KT x KT inverse (built in
 // FP64 on the host) with the KT x 16 real and imaginary parts of r, on
 // v_mfma_f32_16x16x4f32 (fragment layout as for the temporal DFT).  The
-// pointwise lines run with lane l on pixel l % 16 and frames t = l / 16 + 4 k;
-// values a lane needs from a neighbouring frame pass through the wave's LDS.
+// pointwise lines run with lane l on pixel l % 16 and frames t = l / 16 + 4 k
+// (or, in 8-pixel tiles, pixel l % 8 and frames l / 8 + 8 k); values a lane
+// needs from a neighbouring frame pass through the wave's LDS.
 // One wave per 16 pixels gives four times the waves of a pixel-per-lane
 // recurrence, which is what hides the latency of the streams.
-template <int KT>
+template <int KT, int PX = 16>
 __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* buf0, float2* buf1,
                                         float2* __restrict__ m, float2* __restrict__ d1,
                                         const float2* __restrict__ x, const float2* __restrict__ d2, int nt,
                                         size_t npix, size_t p0, int count, float tau, float rho, int lane) {
-  constexpr int MT = DftTile<KT>::MT, NK = KT / 4;
-  const int col = lane & 15, grp = lane >> 4;
+  // PX = 16 or 8 pixels per wave: lane l on pixel l % PX and frames
+  // l / PX + G k (G = 64 / PX); with 8 the contraction's columns 8..15 carry
+  // whatever the buffers hold and their results are dropped (each output
+  // column of the product depends on its own column only)
+  static_assert(PX == 16 || PX == 8, "TV tile width");
+  constexpr int MT = DftTile<KT>::MT, G = 64 / PX, NK = KT / G;
+  const int col = lane % PX, grp = lane / PX;
   const bool pv = col < count;
   // addresses: a wave-uniform base (p0 and the frame step of the unrolled
   // loop) plus one 32-bit byte offset per lane, the same for every stream
   // (8 nt npix < 2^32 for every supported size); lanes past the tile's last
   // pixel use its last pixel's offset and neither keep nor store a value
   const uint32_t off = 8u * ((uint32_t)min(col, count - 1) + (uint32_t)grp * (uint32_t)npix);
-  const uint32_t offm = 8u * ((uint32_t)min(col, count - 1) + 4u * (uint32_t)grp * (uint32_t)npix);
+  // the product's output layout: lane l holds frames 16 mm + 4 (l / 16) + j of column l % 16
+  const int ocol = lane & 15, ogrp = lane >> 4;
+  const bool opv = ocol < PX && ocol < count;
+  const uint32_t offm = 8u * ((uint32_t)min(ocol, count - 1) + 4u * (uint32_t)ogrp * (uint32_t)npix);
   // every stream is requested up front (x and d2 are first needed for r):
   // one memory round trip per tile instead of two.  Measured at 256x256x32
   // (one box, three interleaved rounds): 24.4-24.6 us against 25.6-26.1 us
@@ -959,23 +968,23 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
     float2 mv[NK], dv[NK];
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      const int t = grp + 4 * k;
+      const int t = grp + G * k;
       const bool ok = t < nt && pv;
-      const size_t b = p0 + (size_t)(4 * k) * npix;
+      const size_t b = p0 + (size_t)(G * k) * npix;
       mv[k] = ok ? ld_off(m + b, off) : make_float2(0.f, 0.f);
       dv[k] = (ok && t < nt - 1) ? ld_off(d1 + b, off) : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      const int t = grp + 4 * k;
+      const int t = grp + G * k;
       const bool ok = t < nt && pv;
-      const size_t b = p0 + (size_t)(4 * k) * npix;
+      const size_t b = p0 + (size_t)(G * k) * npix;
       xv[k] = ok ? ld_off(x + b, off) : make_float2(0.f, 0.f);
       zv[k] = ok ? ld_off(d2 + b, off) : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      const int t = grp + 4 * k;
+      const int t = grp + G * k;
       buf0[t * 16 + col] = mv[k];
       buf1[t * 16 + col] = dv[k];
     }
@@ -986,7 +995,7 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
     float2 ev[NK];
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      const int t = grp + 4 * k;
+      const int t = grp + G * k;
       ev[k] = make_float2(0.f, 0.f);
       if (t + 1 < KT && t < nt - 1) {
         const float2 m0 = buf0[t * 16 + col], m1 = buf0[(t + 1) * 16 + col], dt = buf1[t * 16 + col];
@@ -996,7 +1005,7 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int k = 0; k < NK; ++k) buf1[(grp + 4 * k) * 16 + col] = ev[k];
+    for (int k = 0; k < NK; ++k) buf1[(grp + G * k) * 16 + col] = ev[k];
   }
   __builtin_amdgcn_wave_barrier();
   // r_t = rho (x_t + d2_t) + e_t - e_{t-1}, split into real and imaginary
@@ -1006,7 +1015,7 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
   {
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      const int t = grp + 4 * k;
+      const int t = grp + G * k;
       float2 r = make_float2(0.f, 0.f);
       if (t < nt) {
         const float2 e0 = buf1[t * 16 + col];
@@ -1027,19 +1036,19 @@ __device__ __forceinline__ void tv_tile(const float* __restrict__ frag, float2* 
   for (int mm = 0; mm < MT; ++mm)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int t = 16 * mm + 4 * grp + j;
+      const int t = 16 * mm + 4 * ogrp + j;
       const float2 mv = make_float2(are[mm][j], aim[mm][j]);
-      buf0[t * 16 + col] = mv;
-      if (t < nt && pv) st_off(m + p0 + (size_t)(16 * mm + j) * npix, offm, mv);
+      buf0[t * 16 + ocol] = mv;
+      if (t < nt && opv) st_off(m + p0 + (size_t)(16 * mm + j) * npix, offm, mv);
     }
   __builtin_amdgcn_wave_barrier();
   // d1_t <- e_t + m_{t+1} - m_t
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    const int t = grp + 4 * k;
+    const int t = grp + G * k;
     if (t + 1 < KT && t < nt - 1 && pv) {
       const float2 e0 = buf1[t * 16 + col], m0 = buf0[t * 16 + col], m1 = buf0[(t + 1) * 16 + col];
-      st_off(d1 + p0 + (size_t)(4 * k) * npix, off, make_float2(e0.x + m1.x - m0.x, e0.y + m1.y - m0.y));
+      st_off(d1 + p0 + (size_t)(G * k) * npix, off, make_float2(e0.x + m1.x - m0.x, e0.y + m1.y - m0.y));
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -1056,7 +1065,7 @@ inline int tv_kt(int nt) { return (nt + 15) / 16 * 16; }
 template <int KT>
 constexpr int tv_waves_per_eu() { return KT <= 32 ? 4 : 1; }
 
-template <int KT>
+template <int KT, int PX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tv_waves_per_eu<KT>()))) void k_tv_tiles(
     const float* __restrict__ frags, float2* __restrict__ m,
                                                   float2* __restrict__ d1, const float2* __restrict__ x,
@@ -1069,27 +1078,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tv_waves_pe
   load_frags<KT>(lds_f, frags);
   __syncthreads();
   const int nw = blockDim.x >> 6;
-  const size_t ntiles = (pix1 - pix0 + 15) / 16;
+  const size_t ntiles = (pix1 - pix0 + PX - 1) / PX;
   for (size_t tl = (size_t)blockIdx.x * nw + wv; tl < ntiles; tl += (size_t)gridDim.x * nw) {
-    const size_t p0 = pix0 + tl * 16;
-    const int count = (int)std::min<size_t>(16, pix1 - p0);
-    tv_tile<KT>(lds_f, buf0, buf1, m, d1, x, d2, nt, npix, p0, count, tau, rho, lane);
+    const size_t p0 = pix0 + tl * PX;
+    const int count = (int)std::min<size_t>(PX, pix1 - p0);
+    tv_tile<KT, PX>(lds_f, buf0, buf1, m, d1, x, d2, nt, npix, p0, count, tau, rho, lane);
   }
 }
+
+template <int KT, int PX>
+static int tv_tiles_launch_px(cs_plan* p, float tau, float rho, size_t npix, size_t pix0, size_t pix1,
+                              hipStream_t s) {
+  constexpr int waves = 4;
+  const size_t lds = ((size_t)DftTile<KT>::FRAG + (size_t)waves * tv_wave_floats(KT)) * sizeof(float);
+  CS_HIP_STATUS(ensure_dynamic_lds((const void*)k_tv_tiles<KT, PX>, lds));
+  const size_t ntiles = (pix1 - pix0 + PX - 1) / PX;
+  const unsigned grid = (unsigned)std::min<size_t>((ntiles + waves - 1) / waves, 65535);
+  hipLaunchKernelGGL((k_tv_tiles<KT, PX>), dim3(grid), dim3(64 * waves), lds, s, p->tv_frags, p->s0, p->s1, p->s2,
+                     p->s3, p->desc.nt, npix, pix0, pix1, tau, rho);
+  CS_HIP(hipGetLastError());
+  return CS_OK;
+}
+
+// pixels per wave of the TV step: 8 where 16-pixel tiles would leave fewer
+// than kTvNarrowTiles waves (small images: twice the waves in flight).
+// Measured (event-timed per launch, two rounds): 128 x 128 x 22 frames 9.7 ->
+// 9.0-9.2 us with 8; 192 x 192 x 24 13.8 -> 15.1 us and 256 x 256 x 32 21.1 ->
+// 23.2 us, so 16 stays above the threshold.
+constexpr size_t kTvNarrowTiles = 2048;
 
 template <int KT>
 static int tv_tiles_launch(cs_plan* p, float tau, float rho, int i0, int i1, hipStream_t s) {
   const size_t npix = (size_t)p->desc.nv * p->desc.nh;
   const size_t pix0 = (size_t)i0 * p->desc.nv, pix1 = (size_t)i1 * p->desc.nv;
-  constexpr int waves = 4;
-  const size_t lds = ((size_t)DftTile<KT>::FRAG + (size_t)waves * tv_wave_floats(KT)) * sizeof(float);
-  CS_HIP_STATUS(ensure_dynamic_lds((const void*)k_tv_tiles<KT>, lds));
-  const size_t ntiles = (pix1 - pix0 + 15) / 16;
-  const unsigned grid = (unsigned)std::min<size_t>((ntiles + waves - 1) / waves, 65535);
-  hipLaunchKernelGGL(k_tv_tiles<KT>, dim3(grid), dim3(64 * waves), lds, s, p->tv_frags, p->s0, p->s1, p->s2, p->s3,
-                     p->desc.nt, npix, pix0, pix1, tau, rho);
-  CS_HIP(hipGetLastError());
-  return CS_OK;
+  if ((pix1 - pix0 + 15) / 16 < kTvNarrowTiles) return tv_tiles_launch_px<KT, 8>(p, tau, rho, npix, pix0, pix1, s);
+  return tv_tiles_launch_px<KT, 16>(p, tau, rho, npix, pix0, pix1, s);
 }
 
 // pixels of columns [i0, i1): the solver layout puts column i's rows at i*nv .. i*nv + nv - 1
