@@ -219,7 +219,7 @@ template <int L, int N2>
 struct GroupRoots {
   float c[N2], s[N2];
   float c8, s8;          // 1, 0 on the lanes of the first stage's low half
-  float sg1, sg2, sg4;   // butterfly signs of the stages xor 1, 2, 4
+  float sg1, sg2, sg4;   // butterfly signs of the stages between members j ^ 1, j ^ 2, j ^ 4
 };
 
 // the roots of every lane of a group, as a compile-time table in device
@@ -276,12 +276,13 @@ __device__ __forceinline__ int lane_bitrev(int j) {
 }
 
 // forward transform of a lane group (SIGN = -1 for Psi; LS the lane distance
-// between members, GroupLane): frames j + L n2 in,
-// frequencies k2 + N2 bitrev(j) out, unnormalised.  A length-N2 DFT in the
-// lane's registers, the twiddles exp(SIGN 2 pi i j k2 / nt), then a length-L
-// DFT across the group by decimation in frequency (stages xor L/2 .. xor 1,
-// the difference of a stage of half-size h multiplied by exp(SIGN 2 pi i
-// (j mod h) / 2h)).  Every lane of the wave must take part.
+// between members, GroupLane): frames j + L n2 in, frequencies k2 + N2
+// bitrev(j) out, unnormalised.  A length-N2 DFT in the lane's registers, the
+// twiddles exp(SIGN 2 pi i j k2 / nt), then a length-L DFT across the group by
+// decimation in frequency (stages between members j ^ L/2 .. j ^ 1, i.e.
+// lanes LS L/2 .. LS apart; the difference of a stage of half-size h
+// multiplied by exp(SIGN 2 pi i (j mod h) / 2h)).  Every lane of the wave must
+// take part.
 template <int L, int N2, int SIGN, int LS = 1>
 __device__ __forceinline__ void group_fft_time_to_freq(float2 (&x)[N2], int j, const GroupRoots<L, N2>& r) {
   dft_reg<N2, SIGN>(x);
