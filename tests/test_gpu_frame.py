@@ -41,6 +41,7 @@ def _oracle(case, iters, cols=None):
     ((16, 8, 64, 2), 8),        # maximum frame count
     ((16, 8, 36, 2), 8),        # register FFT with 4 lanes per pixel (odd per-lane length)
     ((24, 6, 20, 2), 10),
+    ((24, 9, 22, 2), 8),        # 22 frames (the paper's count): the MFMA contraction
 ], ids=str)
 def test_frame_solves_match_oracle(shape, iters):
     from paper_1203_4587_amd.api import Plan

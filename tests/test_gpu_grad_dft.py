@@ -62,7 +62,8 @@ def test_forward_ckpt_equals_plain_solve(every):
                                                ((96, 12, 40, 3), 4, 3),    # 80-wide embedding
                                                ((16, 8, 64, 2), 3, 2),     # maximum frame count
                                                ((16, 8, 36, 2), 3, 2),     # register FFT, 4 lanes per pixel
-                                               ((24, 8, 20, 2), 3, 2)],
+                                               ((24, 8, 20, 2), 3, 2),
+                                               ((24, 9, 22, 2), 3, 2)],    # 22 frames (the paper's count)
                          ids=str)
 def test_gradient_matches_oracle_reference(shape, iters, every):
     """dL/dy, dL/dlambda, dL/dmu of L = Re<g, x_K> against the FP64 reverse sweep."""

@@ -63,6 +63,9 @@ def test_tv_small_workload_matches_oracle():
     ((24, 8, 48, 2), "dft", 10),
     ((16, 8, 36, 2), "dft", 10),
     ((16, 6, 60, 2), "dft", 8),
+    # frame counts that keep the MFMA contraction: 6, and 22 as in the paper's data
+    ((24, 8, 6, 2), "dft", 10),
+    ((24, 9, 22, 2), "dft", 10),      # 216 pixels: ragged last tile
 ], ids=lambda v: str(v))
 def test_solves_match_oracle(shape, prior, iters):
     nv, nh, nt, nc = shape
@@ -116,7 +119,8 @@ def test_zero_iterations_return_initialisation(prior):
                                          ("tv", (27, 12, 40, 2)),
                                          ("tv", (384, 4, 5, 2)),     # 512-value wave FFT groups
                                          # data term with the coil loop split over 4 and 2 waves
-                                         ("tv", (64, 18, 6, 9)), ("dft", (96, 18, 8, 6))], ids=str)
+                                         ("tv", (64, 18, 6, 9)), ("dft", (96, 18, 8, 6)),
+                                         ("dft", (24, 9, 22, 2))], ids=str)   # 22 frames (the paper's count)
 def test_objective_trace_matches_oracle(prior, shape):
     fam = "cardiac" if prior == "tv" else "periodic"
     nv, nh, nt, nc = shape
@@ -227,7 +231,8 @@ FORM_CASES = [((64, 32, 10, 4), "tv"), ((64, 32, 10, 4), "dft"), ((96, 24, 40, 3
               ((96, 24, 40, 3), "tv"), ((192, 16, 32, 4), "dft"), ((192, 16, 24, 4), "tv"),
               ((144, 12, 20, 3), "dft"), ((144, 12, 20, 3), "tv"), ((128, 16, 48, 2), "tv"),
               ((64, 8, 64, 2), "dft"), ((2, 8, 6, 2), "tv"), ((6, 12, 5, 2), "dft"),
-              ((512, 4, 6, 2), "tv"), ((384, 4, 5, 2), "dft"), ((64, 8, 36, 2), "dft"), ((64, 8, 48, 2), "dft")]
+              ((512, 4, 6, 2), "tv"), ((384, 4, 5, 2), "dft"), ((64, 8, 36, 2), "dft"), ((64, 8, 48, 2), "dft"),
+              ((64, 8, 22, 2), "dft"), ((48, 8, 6, 2), "dft")]
 
 
 @pytest.mark.parametrize("shape,prior", FORM_CASES, ids=[f"{s}-{p}" for s, p in FORM_CASES])
