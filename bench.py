@@ -474,6 +474,46 @@ def eigen_form(plan, problem, coil, mask, y, prior: str, steps: int, workload: s
     return out
 
 
+# block sizes of the x-update sweep: (nv, nh, nt), each factor at least twice
+# the 256 MB last-level cache so that every launch streams it from HBM
+XU_SWEEP = [(64, 512, 64), (128, 256, 64), (192, 192, 40), (256, 256, 32), (384, 128, 16), (512, 64, 16)]
+
+
+def xu_sweep() -> dict:
+    """The x-update's rate across block sizes n_v: a 10-iteration temporal-DFT
+    solve (4 coils, R = 4, seeded synthetic data) per size with HIP events
+    around every launch; algorithmic bytes = packed factor + 3 images (reads
+    H'y and u, writes z), as in the roofline object."""
+    import torch
+    from paper_1203_4587_amd import synthetic as S
+    from paper_1203_4587_amd import _lib
+    from paper_1203_4587_amd.api import Plan, to_device
+    out = []
+    for nv, nh, nt in XU_SWEEP:
+        pr = S.make_problem(nv, nh, nt, 4, 4, 8, "dft", "periodic", 3000 + nv, name=f"xu-{nv}")
+        plan = Plan(to_device(pr.coil), to_device(pr.mask, dtype=torch.uint8), pr.mu, prior="dft")
+        y = plan.apply_A(to_device(pr.x_true)) + to_device(pr.noise)
+        plan.solve(y, pr.lam, 5)
+        plan.kernel_timing(True)
+        plan.solve(y, pr.lam, 10)
+        torch.cuda.synchronize()
+        n, ms = plan.kernel_times().get("x_update", (0, 0.0))
+        plan.kernel_timing(False)
+        f = plan.flags
+        form = ("rows" if nv % 2 else "wave2" if nv % 64 == 0 and (nv // 2) % 64 and not (f & _lib.CS_FLAG_XU_GROUP)
+                else "wave" if (nv // 2) % 64 == 0 and not (f & _lib.CS_FLAG_XU_GROUP) else "pairs")
+        nbytes = 8 * nh * nt * nv * (nv + 1) // 2 + 3 * 8 * nt * nv * nh
+        us = ms * 1e3 / max(n, 1)
+        out.append({"nv": nv, "nh": nh, "nt": nt, "blocks": nh * nt, "form": form, "launches": n,
+                    "us": round(us, 2), "algorithmic_bytes": nbytes, "GBps": round(nbytes / (us * 1e-6) / 1e9, 1),
+                    "hbm_frac": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)})
+        log(f"x-update sweep nv={nv}: {out[-1]['us']} us, {out[-1]['GBps']} GB/s ({form})")
+        plan.close()
+        del y
+        torch.cuda.empty_cache()
+    return {"xu_sweep": out, "peak_GBps": HBM_PEAK_GBS}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -494,6 +534,8 @@ def main() -> int:
     ap.add_argument("--unrolled-reps", type=int, default=10, help="timed forward+backward passes")
     ap.add_argument("--no-tune", action="store_true", help="time the default form instead of the tuned one")
     ap.add_argument("--no-eigen", action="store_true", help="skip the eigen-form (any-mu) factor measurement")
+    ap.add_argument("--xu-sweep", action="store_true",
+                    help="only measure the x-update across block sizes n_v = 64 .. 512 and print that JSON object")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the per-step figures (SENSE passes, plan, objective monitor)")
     ap.add_argument("--xu-form", choices=["wave", "group"], default=None,
@@ -518,6 +560,9 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.xu_sweep:
+        print(json.dumps(xu_sweep()), flush=True)
+        return 0
     wl = WORKLOADS[args.workload]
     problem = S.CONFIGS[wl.get("config", args.workload)]()
     nt, nv, nh = problem.x_true.shape
